@@ -1,0 +1,277 @@
+/*
+ * uc_lp.h -- C ABI of libuclp: restarted PDHG for unit-commitment LP
+ * relaxations on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem is the continuous relaxation that both legs of the paper's
+ * concurrent GPU-CPU solver hand to their LP method (Sec. II-C: the GPU leg
+ * solves "the relaxed linear problem" with PDHG, the CPU leg the same problem
+ * with barrier; Sec. III-C: PDHG replaces the barrier solve):
+ *
+ *     min c'x   s.t.  a_i'x  = b_i   (sense 'E')
+ *                     a_i'x >= b_i   (sense 'G')
+ *                     a_i'x <= b_i   (sense 'L', negated internally)
+ *                     lb <= x <= ub  (+-INFINITY allowed)
+ *
+ * The solve/poll/terminate surface (create, asynchronous solve, non-blocking
+ * status, cancel) is what the concurrent driver of Algorithm 1 needs: start a
+ * solve, poll it on a fixed interval, and terminate the slower leg.  The
+ * default limits follow the PDHG parameter paragraph of Sec. II-D
+ * (iteration limit 100,000, convergence tolerance 1e-4, absolute feasibility
+ * tolerance 1e-5).
+ *
+ * Conventions for every function below
+ *   - All pointers are HOST pointers unless stated otherwise.  Arrays passed
+ *     in are deep-copied before the call returns; the caller keeps ownership.
+ *   - Functions return UC_LP_OK (0) or a negative uc_lp_err code.  They never
+ *     abort or throw across the ABI.  A thread-local message describing the
+ *     last failure is available from uc_lp_last_error().
+ *   - Index arrays are int32, CSR with row_ptr[0] = 0, row_ptr[m] = nnz,
+ *     column indices in [0, n), no duplicate (row, column) pairs.
+ *   - Dual values y follow the Lagrangian c'x - y'(Ax - b): y_i >= 0 on 'G'
+ *     rows, y_i <= 0 on 'L' rows, free on 'E' rows.
+ */
+#ifndef UC_LP_H
+#define UC_LP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct uc_lp uc_lp;          /* one LP instance                         */
+typedef struct uc_engine uc_engine;  /* one GPU, an HBM budget and a slot table */
+
+enum uc_lp_err {
+  UC_LP_OK = 0,
+  UC_LP_EINVAL = -1,   /* malformed input (see uc_lp_create)                   */
+  UC_LP_ENOMEM = -2,   /* host or device allocation failed                      */
+  UC_LP_EBUDGET = -3,  /* instance larger than the whole engine HBM budget      */
+  UC_LP_EHIP = -4,     /* a HIP runtime call failed                             */
+  UC_LP_ESTATE = -5,   /* call not valid in the handle's current state          */
+  UC_LP_ENOTSUP = -6,  /* option value not supported                            */
+  UC_LP_ETIMEOUT = -7  /* uc_lp_wait timed out (the solve keeps running)        */
+};
+
+/* Arithmetic of the iterates. */
+enum uc_lp_precision {
+  UC_LP_FP64 = 0,              /* FP64 matrix values and iterates                  */
+  UC_LP_FP32_MIXED = 1,        /* FP32 values/iterates; FP64 KKT, restart, gap     */
+  UC_LP_FP32_MIXED_POLISH = 2  /* FP32 until eps_rel, then FP64 until eps_polish   */
+};
+
+/* Solve status. */
+enum uc_lp_status_code {
+  UC_LP_IDLE = 0,        /* created, no solve requested                */
+  UC_LP_QUEUED = 1,      /* waiting for an engine slot / HBM budget    */
+  UC_LP_RUNNING = 2,
+  UC_LP_OPTIMAL = 3,     /* stopping tolerance reached                 */
+  UC_LP_ITER_LIMIT = 4,
+  UC_LP_TIME_LIMIT = 5,
+  UC_LP_CANCELLED = 6,   /* uc_lp_cancel was called                    */
+  UC_LP_NUMERICAL = 7,   /* a non-finite KKT quantity appeared         */
+  UC_LP_INFEASIBLE = 8,  /* detected by the minimal presolve           */
+  UC_LP_FAILED = 9       /* device error during the solve              */
+};
+
+/* SpMV kernel family used by the PDHG half-steps. */
+enum uc_lp_spmv_algo {
+  UC_LP_SPMV_ROWSPLIT = 0,  /* row blocks of bounded nnz, LDS-staged products */
+  UC_LP_SPMV_MERGEPATH = 1  /* equal shares of rows+nnz per workgroup         */
+};
+
+typedef struct {
+  int32_t precision;     /* uc_lp_precision, default UC_LP_FP32_MIXED_POLISH   */
+  int32_t kkt_every;     /* iterations between KKT/restart checks, default 64  */
+  int32_t ruiz_iters;    /* Ruiz equilibration passes, default 10              */
+  int32_t power_iters;   /* power-iteration steps for ||A||_2, default 64      */
+  int64_t iter_limit;    /* total iteration limit, default 100000              */
+  double eps_rel;        /* relative KKT stopping tolerance, default 1e-4      */
+  double eps_abs_feas;   /* absolute feasibility tolerance (inf-norm of the
+                            unscaled row violation) also required, default 1e-5;
+                            0 disables                                          */
+  double eps_polish;     /* relative KKT target of the FP64 polish, 1e-8       */
+  double time_limit_s;   /* wall-clock limit of one solve, default 3600        */
+  double step_scale;     /* eta = step_scale / ||A_hat||_2, default 0.99       */
+  int32_t spmv_algo;     /* uc_lp_spmv_algo, default UC_LP_SPMV_ROWSPLIT       */
+  int32_t verbose;       /* 0 = silent, 1 = one line per check on stderr       */
+  int32_t timing;        /* 1 = time sampled kernel launches with HIP events   */
+  int32_t reserved;
+} uc_lp_opts;
+
+typedef struct {
+  int32_t status;          /* uc_lp_status_code                               */
+  int32_t precision_now;   /* arithmetic of the current / final phase         */
+  int64_t iters;           /* PDHG iterations, all phases                     */
+  int64_t iters_fp64;      /* of which in FP64 (polish or FP64 mode)          */
+  int64_t restarts;
+  double t_total_s;        /* solve start -> finish (or now)                  */
+  double t_setup_s;        /* transpose, scaling, power iteration             */
+  double t_to_eps_s;       /* solve start -> first check with rel_kkt<=eps_rel
+                              (and the absolute feasibility tolerance); -1 if
+                              not reached                                      */
+  double t_queue_s;        /* solve request -> admission into a slot          */
+  double pobj, dobj;       /* unscaled, original problem                      */
+  double rel_primal, rel_dual, rel_gap, rel_kkt;
+  double abs_primal_inf;   /* inf-norm of unscaled row violations             */
+  double pobj_at_eps;      /* primal objective at the eps_rel milestone       */
+  double rel_kkt_at_eps;
+  double norm_a_est;       /* power-iteration estimate of ||A_hat||_2         */
+  double omega;            /* current primal weight                           */
+  double primal_kernel_us; /* mean duration of timed primal half-step kernels  */
+  double dual_kernel_us;   /* mean duration of timed dual half-step kernels    */
+  int64_t timed_launches;  /* number of launches in each mean above           */
+  int32_t m_presolved, n_presolved;  /* sizes after the minimal presolve      */
+  int64_t nnz_presolved;
+  int64_t device_bytes;    /* device memory held by this instance             */
+} uc_lp_info;
+
+/* Fill *opts with the defaults listed in uc_lp_opts. */
+void uc_lp_opts_default(uc_lp_opts* opts);
+
+/* ---- engine: one device, one HBM budget, up to max_slots resident solves --
+ * Instances created against an engine are uploaded when they are admitted
+ * into a slot (FIFO order, when a slot is free and the budget allows) and are
+ * iterated together by batched kernels that cover every resident instance.
+ * device: HIP device ordinal.  hbm_budget_bytes: 0 = 90% of free memory.
+ * max_slots: 1..1024.  Returns EINVAL, EHIP or ENOMEM on failure. */
+int uc_engine_create(int device, size_t hbm_budget_bytes, int32_t max_slots,
+                     uc_engine** out);
+/* Cancels every running or queued solve, waits for the worker, frees all.
+ * NULL is a no-op.  Instances of the engine must be destroyed first. */
+void uc_engine_destroy(uc_engine* eng);
+
+/* Create one LP instance.
+ * eng == NULL: a private engine on device 0 is created; the instance is
+ *   validated, presolved and uploaded before the call returns.
+ * eng != NULL: validated and presolved now; uploaded at admission.
+ * Arrays: row_ptr[m+1], col_idx[nnz], val[nnz], c[n], b[m], sense[m]
+ *   ('E', 'G' or 'L'), lb[n], ub[n].
+ * EINVAL: m or n < 1, nnz < 0, row_ptr not monotone or row_ptr[0] != 0 or
+ *   row_ptr[m] != nnz, column index outside [0, n) or repeated within a row,
+ *   NaN or infinite matrix value, cost or right-hand side, lb > ub,
+ *   lb = +inf or ub = -inf, unknown sense code.
+ * EBUDGET: the instance needs more device memory than the engine budget.
+ * The minimal presolve removes fixed columns (lb == ub) and empty rows; an
+ * empty row that cannot be satisfied makes the instance INFEASIBLE (reported
+ * by uc_lp_status after uc_lp_solve, not as an error here). */
+int uc_lp_create(uc_engine* eng, int32_t m, int32_t n, int64_t nnz,
+                 const int32_t* row_ptr, const int32_t* col_idx, const double* val,
+                 const double* c, const double* b, const char* sense,
+                 const double* lb, const double* ub, const uc_lp_opts* opts,
+                 uc_lp** out);
+
+/* Replace c, b, lb, ub (any may be NULL = keep) of an instance that is not
+ * running; the matrix is unchanged.  Same validation as uc_lp_create. */
+int uc_lp_update_data(uc_lp* lp, const double* c, const double* b,
+                      const double* lb, const double* ub);
+
+/* Start an asynchronous solve.  x0[n], y0[m] (original space) warm-start the
+ * iterates; NULL = start from the projection of 0 and y = 0.  ESTATE if a
+ * solve of this handle is queued or running. */
+int uc_lp_solve(uc_lp* lp, const double* x0, const double* y0);
+
+/* Non-blocking snapshot of the solve state.  Safe to call from any thread
+ * while the solve runs. */
+int uc_lp_status(const uc_lp* lp, uc_lp_info* out);
+
+/* Block until the solve is no longer QUEUED/RUNNING or timeout_s elapses
+ * (timeout_s < 0: no limit).  ETIMEOUT on timeout. */
+int uc_lp_wait(uc_lp* lp, double timeout_s);
+
+/* Request termination of a queued or running solve (the "terminate the
+ * other solver" step of Algorithm 1).  Takes effect at the next check
+ * (at most kkt_every iterations later); the status becomes CANCELLED.
+ * OK if nothing is running. */
+int uc_lp_cancel(uc_lp* lp);
+
+/* Copy the final iterate, unscaled and in the original row/column order:
+ * x[n], y[m] (either may be NULL).  ESTATE unless the status is terminal
+ * (OPTIMAL, ITER_LIMIT, TIME_LIMIT, CANCELLED or NUMERICAL). */
+int uc_lp_get_solution(const uc_lp* lp, double* x, double* y);
+
+/* Cancel if running, wait, release device memory.  NULL is a no-op. */
+void uc_lp_destroy(uc_lp* lp);
+
+/* Thread-local description of the last failure ("" if none). */
+const char* uc_lp_last_error(void);
+
+/* ---- scenario batches sharing one matrix --------------------------------
+ * Solve n_scen LPs that share the matrix of `base` (created with eng ==
+ * NULL) and differ in c, b, lb, ub: arrays c[n_scen*n], b[n_scen*m],
+ * lb[n_scen*n], ub[n_scen*n], scenario-major.  One read of the matrix per
+ * half-step serves every scenario.  x0[n], y0[m] (may be NULL) warm-start all
+ * scenarios from one point.  Blocks until all scenarios stop.  Solutions are
+ * written to x[n_scen*n], y[n_scen*m] and per-scenario results to
+ * info[n_scen].  n_scen in 1..16.  ENOTSUP for other counts. */
+int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* c,
+                          const double* b, const double* lb, const double* ub,
+                          const double* x0, const double* y0, double* x,
+                          double* y, uc_lp_info* info);
+
+/* ---- step-level entry points (the same kernels the solve runs) -----------
+ * These expose single steps of the method so that each can be compared
+ * element by element with an independent implementation.  They act on the
+ * instance's internal problem: fixed columns and empty rows removed, 'L'
+ * rows negated, 'E' rows first.  They require a handle created with
+ * eng == NULL that is not running, and they run the instance's setup
+ * (transpose, scaling, power iteration) if it has not run yet. */
+
+/* Internal sizes and maps: row_map[m_int] gives the original row of each
+ * internal row (negative = negated 'L' row, encoded -(row+1)), col_map[n_int]
+ * the original column of each internal column.  Any pointer may be NULL. */
+int uc_lp_internal_dims(uc_lp* lp, int32_t* m_int, int32_t* n_int, int64_t* nnz_int,
+                        int32_t* m_eq, int32_t* row_map, int32_t* col_map);
+
+/* The transpose built on the device (Sec. "a stored A^T"): t_row_ptr[n_int+1],
+ * t_col[nnz_int], t_val[nnz_int] of the UNSCALED internal matrix, with the
+ * entries of each transposed row in increasing original row order. */
+int uc_lp_get_transpose(uc_lp* lp, int32_t* t_row_ptr, int32_t* t_col, double* t_val);
+
+/* Diagonal scaling A_hat = D_r A D_c of the internal problem: d_row[m_int],
+ * d_col[n_int]; and the power-iteration estimate of ||A_hat||_2. */
+int uc_lp_get_scaling(uc_lp* lp, double* d_row, double* d_col, double* norm_est);
+
+/* One PDHG step on the scaled internal problem, in the given precision
+ * (UC_LP_FP64 or UC_LP_FP32_MIXED): from (x, y), anchor (x0, y0), inner
+ * iteration index k and steps tau, sigma, computes
+ *   x_hat = proj_[l,u](x - tau (c - A'y)),
+ *   y_hat = proj_Y(y + sigma (b - A (2 x_hat - x))),
+ *   x_next = w (2 x_hat - x) + (1 - w) x0,  y_next likewise, w = (k+1)/(k+2).
+ * All vectors are FP64 host arrays of internal length (x*: n_int, y*: m_int);
+ * FP32 mode rounds the inputs to FP32 and widens the outputs. */
+int uc_lp_debug_step(uc_lp* lp, int32_t precision, const double* x, const double* y,
+                     const double* x0, const double* y0, int64_t k, double tau,
+                     double sigma, double* x_hat, double* y_hat, double* x_next,
+                     double* y_next);
+
+/* KKT quantities of an ORIGINAL-space pair (x[n], y[m]), evaluated by the
+ * solver's own FP64 check kernels.  Fills pobj, dobj, rel_* and
+ * abs_primal_inf of *out (other fields zero). */
+int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp_info* out);
+
+/* Standalone SpMV y = A x on host arrays, through the same SpMV kernels:
+ * precision UC_LP_FP64 (FP64 values, FP64 accumulation) or UC_LP_FP32_MIXED
+ * (values and x rounded to FP32, FP32 accumulation); algo uc_lp_spmv_algo.
+ * device: HIP ordinal.  Same CSR validation as uc_lp_create. */
+int uc_spmv(int device, int32_t m, int32_t n, int64_t nnz, const int32_t* row_ptr,
+            const int32_t* col_idx, const double* val, const double* x, double* y,
+            int32_t precision, int32_t algo);
+
+/* Time the SpMV kernels on device-resident data: `copies` independent copies
+ * of the matrix (so the working set can exceed the last-level cache) are
+ * multiplied round-robin `reps` times.  Writes the mean kernel time in
+ * microseconds to *us_per_spmv. */
+int uc_spmv_bench(int device, int32_t m, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                  const int32_t* col_idx, const double* val, int32_t precision,
+                  int32_t algo, int32_t copies, int32_t reps, double* us_per_spmv);
+
+/* Device stream-copy bandwidth in GB/s for `bytes` per buffer (calibration
+ * of the roofline and of hardware traffic counters). */
+int uc_copy_bench(int device, size_t bytes, int32_t reps, double* gbps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UC_LP_H */
