@@ -1,0 +1,990 @@
+// Device kernels of libuclp (gfx950, wave64).
+//
+// Every hot kernel walks a list of tiles (slot, row block).  A row block is a
+// run of consecutive CSR rows holding at most kRowsPerBlock rows and
+// kNnzTile entries (or one longer row).  The 256 threads of a workgroup
+// first load the block's entries with coalesced reads, multiply them by the
+// gathered vector entries and stage the products in LDS; then thread t sums
+// row r0 + t from LDS in CSR order and runs the per-row epilogue
+// (projection, extrapolation, Halpern averaging or KKT terms).  The
+// summation order of a row therefore depends only on the matrix, so results
+// are bitwise reproducible and independent of which other instances share a
+// launch.
+//
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; the
+// tile index is remapped so that each XCD walks one contiguous eighth of the
+// tiles, which keeps the gathered vector window of that range in its own L2.
+
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+#include <math.h>
+#include <stdint.h>
+
+#include "uclp_dev.h"
+
+namespace uclp {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+constexpr int kXcd = 8;
+
+__host__ __device__ inline int xcd_grid(int ntiles) {
+  int per = (ntiles + kXcd - 1) / kXcd;
+  return per * kXcd;
+}
+
+__device__ inline int xcd_tile(int ntiles) {
+  int per = (ntiles + kXcd - 1) / kXcd;
+  int w = blockIdx.x;
+  int t = (w % kXcd) * per + (w / kXcd);
+  return t < ntiles ? t : -1;
+}
+
+template <typename T>
+__device__ inline T clampv(T v, T lo, T hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+template <typename T>
+__device__ inline const Vecs<T>& vecs(const SlotDev& s);
+template <>
+__device__ inline const Vecs<float>& vecs<float>(const SlotDev& s) { return s.f; }
+template <>
+__device__ inline const Vecs<double>& vecs<double>(const SlotDev& s) { return s.d; }
+
+// Block-wide sum (or max) of NQ doubles per thread; result valid in thread 0.
+template <int NQ>
+__device__ inline void block_reduce(double (&v)[NQ], const bool (&is_max)[NQ], double* red) {
+  // red: LDS scratch of (kThreads / 64) * NQ doubles
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double x = v[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_down(x, off, 64);
+      x = is_max[q] ? fmax(x, o) : x + o;
+    }
+    v[q] = x;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) red[wave * NQ + q] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double x = red[q];
+      for (int w = 1; w < kThreads / 64; ++w) x = is_max[q] ? fmax(x, red[w * NQ + q]) : x + red[w * NQ + q];
+      v[q] = x;
+    }
+  }
+}
+
+// Row sums of one row block: products val[k] * g(k) staged in LDS, then summed
+// per row.  Returns true in the thread that owns a row; `row` and `sum` are
+// set there.  Long rows (one row above kNnzTile) are reduced by the whole
+// block and reported by thread 0.
+template <typename ACC, typename Prod>
+__device__ inline bool block_row_sum(const int* __restrict__ ptr, int r0, int r1, ACC* lds,
+                                     ACC* red, Prod prod, int& row, ACC& sum) {
+  const int k0 = ptr[r0];
+  const int k1 = ptr[r1];
+  const int nz = k1 - k0;
+  if (nz <= kNnzTile) {
+    for (int k = threadIdx.x; k < nz; k += kThreads) lds[k] = prod(k0 + k);
+    __syncthreads();
+    const int r = r0 + threadIdx.x;
+    if (r < r1) {
+      const int a = ptr[r] - k0;
+      const int b = ptr[r + 1] - k0;
+      ACC s = 0;
+      for (int k = a; k < b; ++k) s += lds[k];
+      row = r;
+      sum = s;
+      return true;
+    }
+    return false;
+  }
+  // one long row
+  ACC s = 0;
+  for (int k = k0 + threadIdx.x; k < k1; k += kThreads) s += prod(k);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ACC t = red[0];
+    for (int w = 1; w < kThreads / 64; ++w) t += red[w];
+    row = r0;
+    sum = t;
+    return true;
+  }
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// PDHG half-steps (one scenario per slot)
+// ---------------------------------------------------------------------------
+
+// Primal half-step over the rows of A^T (= columns j of A):
+//   g = c_j - (A^T y)_j ; x_hat = clamp(x - tau g, l, u) ; xbar = 2 x_hat - x
+//   non-check: x <- w xbar + (1 - w) x0,  w = (k + 1)/(k + 2), 1 - w = 1/(k + 2)
+//   check:     x_hat stored, x kept for the residuals
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__ slots,
+                                                     const Tile* __restrict__ tiles, int ntiles,
+                                                     int jiter) {
+  __shared__ T lds[kNnzTile];
+  __shared__ T red[kThreads / 64];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const Vecs<T>& V = vecs<T>(S);
+  const int r0 = S.t_blk[tl.blk];
+  const int r1 = S.t_blk[tl.blk + 1];
+  const int* __restrict__ col = S.t_col;
+  const T* __restrict__ val = V.tv;
+  const T* __restrict__ y = V.y;
+  int j;
+  T s;
+  if (!block_row_sum<T>(S.t_ptr, r0, r1, lds, red, [&](int k) { return val[k] * y[col[k]]; }, j, s))
+    return;
+  const T tau = (T)S.tau[0];
+  const T g = V.c[j] - s;
+  const T x = V.x[j];
+  const T xh = clampv<T>(x - tau * g, V.l[j], V.u[j]);
+  const T xb = (T)2 * xh - x;
+  V.xbar[j] = xb;
+  if (CHECK) {
+    V.xhat[j] = xh;
+  } else {
+    const double kk = (double)(S.k0[0] + jiter);
+    const T w = (T)((kk + 1.0) / (kk + 2.0));
+    const T wa = (T)(1.0 / (kk + 2.0));
+    V.x[j] = w * xb + wa * V.x0[j];
+  }
+}
+
+// Dual half-step over the rows of A:
+//   y_hat = y + sigma (b - A xbar), projected to y >= 0 on rows i >= m_eq
+//   non-check: y <- w (2 y_hat - y) + (1 - w) y0 ; check: y_hat stored
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ slots,
+                                                   const Tile* __restrict__ tiles, int ntiles,
+                                                   int jiter) {
+  __shared__ T lds[kNnzTile];
+  __shared__ T red[kThreads / 64];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const Vecs<T>& V = vecs<T>(S);
+  const int r0 = S.a_blk[tl.blk];
+  const int r1 = S.a_blk[tl.blk + 1];
+  const int* __restrict__ col = S.a_col;
+  const T* __restrict__ val = V.av;
+  const T* __restrict__ xb = V.xbar;
+  int i;
+  T s;
+  if (!block_row_sum<T>(S.a_ptr, r0, r1, lds, red, [&](int k) { return val[k] * xb[col[k]]; }, i, s))
+    return;
+  const T sigma = (T)S.sigma[0];
+  const T y = V.y[i];
+  T yh = y + sigma * (V.b[i] - s);
+  if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
+  if (CHECK) {
+    V.yhat[i] = yh;
+  } else {
+    const double kk = (double)(S.k0[0] + jiter);
+    const T w = (T)((kk + 1.0) / (kk + 2.0));
+    const T wa = (T)(1.0 / (kk + 2.0));
+    V.y[i] = w * ((T)2 * yh - y) + wa * V.y0[i];
+  }
+}
+
+// KKT check over the rows of A (FP64 values, FP64 accumulation):
+//   s1 = (A x_hat)_i, s2 = (A (x_hat - x))_i
+//   unscaled violation r_i = (b_i - s1)/D_r,i (G rows: max(0, .))
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict__ slots,
+                                                       const Tile* __restrict__ tiles, int ntiles) {
+  __shared__ double lds1[kNnzTile];
+  __shared__ double lds2[kNnzTile];
+  __shared__ double red[(kThreads / 64) * RQ_N];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const Vecs<T>& V = vecs<T>(S);
+  const int r0 = S.a_blk[tl.blk];
+  const int r1 = S.a_blk[tl.blk + 1];
+  const int* __restrict__ ptr = S.a_ptr;
+  const int* __restrict__ col = S.a_col;
+  const double* __restrict__ val = S.d.av;
+  const T* __restrict__ xh = V.xhat;
+  const T* __restrict__ x = V.x;
+  const int k0 = ptr[r0];
+  const int k1 = ptr[r1];
+  const int nz = k1 - k0;
+  double q[RQ_N] = {0, 0, 0, 0, 0, 0};
+  const bool is_max[RQ_N] = {false, false, false, false, false, true};
+  int row = -1;
+  double s1 = 0, s2 = 0;
+  if (nz <= kNnzTile) {
+    for (int k = threadIdx.x; k < nz; k += kThreads) {
+      const int c = col[k0 + k];
+      const double v = val[k0 + k];
+      const double a = (double)xh[c];
+      lds1[k] = v * a;
+      lds2[k] = v * (a - (double)x[c]);
+    }
+    __syncthreads();
+    const int r = r0 + threadIdx.x;
+    if (r < r1) {
+      for (int k = ptr[r] - k0; k < ptr[r + 1] - k0; ++k) {
+        s1 += lds1[k];
+        s2 += lds2[k];
+      }
+      row = r;
+    }
+  } else {
+    for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
+      const int c = col[k];
+      const double a = (double)xh[c];
+      s1 += val[k] * a;
+      s2 += val[k] * (a - (double)x[c]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s1 += __shfl_down(s1, off, 64);
+      s2 += __shfl_down(s2, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      lds1[threadIdx.x >> 6] = s1;
+      lds2[threadIdx.x >> 6] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s1 = lds1[0];
+      s2 = lds2[0];
+      for (int w = 1; w < kThreads / 64; ++w) {
+        s1 += lds1[w];
+        s2 += lds2[w];
+      }
+      row = r0;
+    }
+  }
+  if (row >= 0) {
+    double r = S.d.b[row] - s1;
+    if (row >= S.m_eq) r = r > 0.0 ? r : 0.0;
+    const double ru = r / S.dr[row];
+    const double yh = (double)V.yhat[row];
+    const double dy = yh - (double)V.y[row];
+    const double d0 = yh - (double)V.y0[row];
+    q[RQ_RES2] = ru * ru;
+    q[RQ_BY] = S.d.b[row] * yh;
+    q[RQ_DY2] = dy * dy;
+    q[RQ_DYADX] = dy * s2;
+    q[RQ_DY0] = d0 * d0;
+    q[RQ_RESMAX] = fabs(ru);
+  }
+  __syncthreads();
+  block_reduce<RQ_N>(q, is_max, red);
+  if (threadIdx.x == 0) {
+    double* out = S.part_a + (size_t)tl.blk * RQ_N;
+#pragma unroll
+    for (int k = 0; k < RQ_N; ++k) out[k] = q[k];
+  }
+}
+
+// KKT check over the rows of A^T: reduced cost d_hat = c_j - (A^T y_hat)_j,
+// bound multiplier by finiteness of the bounds, unscaled by 1/D_c.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_kkt_cols(const SlotDev* __restrict__ slots,
+                                                       const Tile* __restrict__ tiles, int ntiles) {
+  __shared__ double lds[kNnzTile];
+  __shared__ double red[(kThreads / 64) * RQ_N];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const Vecs<T>& V = vecs<T>(S);
+  const int r0 = S.t_blk[tl.blk];
+  const int r1 = S.t_blk[tl.blk + 1];
+  const int* __restrict__ col = S.t_col;
+  const double* __restrict__ val = S.d.tv;
+  const T* __restrict__ yh = V.yhat;
+  double q[CQ_N] = {0, 0, 0, 0, 0};
+  const bool is_max[CQ_N] = {false, false, false, false, false};
+  int j = -1;
+  double s = 0;
+  const bool own = block_row_sum<double>(S.t_ptr, r0, r1, lds, red,
+                                         [&](int k) { return val[k] * (double)yh[col[k]]; }, j, s);
+  if (own) {
+    const double c = S.d.c[j];
+    const double l = S.d.l[j];
+    const double u = S.d.u[j];
+    const double dh = c - s;
+    const bool fl = isfinite(l);
+    const bool fu = isfinite(u);
+    double lam = 0.0;
+    if (fl && fu) lam = dh;
+    else if (fl) lam = dh > 0.0 ? dh : 0.0;
+    else if (fu) lam = dh < 0.0 ? dh : 0.0;
+    const double dres = (dh - lam) / S.dc[j];
+    const double xhv = (double)V.xhat[j];
+    const double dx = xhv - (double)V.x[j];
+    const double d0 = xhv - (double)V.x0[j];
+    q[CQ_DRES2] = dres * dres;
+    q[CQ_LBUB] = (lam > 0.0 ? l * lam : 0.0) + (lam < 0.0 ? u * lam : 0.0);
+    q[CQ_CX] = c * xhv;
+    q[CQ_DX2] = dx * dx;
+    q[CQ_DX0] = d0 * d0;
+  }
+  __syncthreads();
+  block_reduce<CQ_N>(q, is_max, red);
+  if (threadIdx.x == 0) {
+    double* out = S.part_t + (size_t)tl.blk * CQ_N;
+#pragma unroll
+    for (int k = 0; k < CQ_N; ++k) out[k] = q[k];
+  }
+}
+
+// Final reduction of the block partials of one slot, in block order.
+__global__ __launch_bounds__(kThreads) void k_reduce(const SlotDev* __restrict__ slots,
+                                                     const int* __restrict__ ids) {
+  __shared__ double red[(kThreads / 64) * (RQ_N + CQ_N)];
+  const SlotDev& S = slots[ids[blockIdx.x]];
+  double q[RQ_N + CQ_N];
+  bool is_max[RQ_N + CQ_N];
+#pragma unroll
+  for (int k = 0; k < RQ_N + CQ_N; ++k) {
+    q[k] = 0.0;
+    is_max[k] = (k == RQ_RESMAX);
+  }
+  for (int b = threadIdx.x; b < S.a_nblk; b += kThreads) {
+    const double* p = S.part_a + (size_t)b * RQ_N;
+#pragma unroll
+    for (int k = 0; k < RQ_N; ++k) q[k] = is_max[k] ? fmax(q[k], p[k]) : q[k] + p[k];
+  }
+  for (int b = threadIdx.x; b < S.t_nblk; b += kThreads) {
+    const double* p = S.part_t + (size_t)b * CQ_N;
+#pragma unroll
+    for (int k = 0; k < CQ_N; ++k) q[RQ_N + k] += p[k];
+  }
+  block_reduce<RQ_N + CQ_N>(q, is_max, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < RQ_N + CQ_N; ++k) S.scal[k] = q[k];
+  }
+}
+
+// After a check: either restart at (x_hat, y_hat) or take the Halpern step.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_finish_x(const SlotDev* __restrict__ slots,
+                                                       const Tile* __restrict__ tiles, int ntiles,
+                                                       int kk) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const Vecs<T>& V = vecs<T>(S);
+  const int j = S.t_blk[tl.blk] + threadIdx.x;
+  if (j >= S.t_blk[tl.blk + 1]) return;
+  if (S.restart[0]) {
+    const T xh = V.xhat[j];
+    V.x[j] = xh;
+    V.x0[j] = xh;
+  } else {
+    const double k = (double)(S.k0[0] + kk);
+    const T w = (T)((k + 1.0) / (k + 2.0));
+    const T wa = (T)(1.0 / (k + 2.0));
+    V.x[j] = w * V.xbar[j] + wa * V.x0[j];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_finish_y(const SlotDev* __restrict__ slots,
+                                                       const Tile* __restrict__ tiles, int ntiles,
+                                                       int kk) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const Vecs<T>& V = vecs<T>(S);
+  const int i = S.a_blk[tl.blk] + threadIdx.x;
+  if (i >= S.a_blk[tl.blk + 1]) return;
+  if (S.restart[0]) {
+    const T yh = V.yhat[i];
+    V.y[i] = yh;
+    V.y0[i] = yh;
+  } else {
+    const double k = (double)(S.k0[0] + kk);
+    const T w = (T)((k + 1.0) / (k + 2.0));
+    const T wa = (T)(1.0 / (k + 2.0));
+    V.y[i] = w * ((T)2 * V.yhat[i] - V.y[i]) + wa * V.y0[i];
+  }
+}
+
+// FP32 -> FP64 switch: the FP64 phase starts (as a restart) at the FP32 x_hat, y_hat.
+__global__ __launch_bounds__(kThreads) void k_promote_x(const SlotDev* __restrict__ slots,
+                                                        const Tile* __restrict__ tiles, int ntiles) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const int j = S.t_blk[tl.blk] + threadIdx.x;
+  if (j >= S.t_blk[tl.blk + 1]) return;
+  const double v = (double)S.f.xhat[j];
+  S.d.x[j] = v;
+  S.d.x0[j] = v;
+  S.d.xhat[j] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_promote_y(const SlotDev* __restrict__ slots,
+                                                        const Tile* __restrict__ tiles, int ntiles) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const int i = S.a_blk[tl.blk] + threadIdx.x;
+  if (i >= S.a_blk[tl.blk + 1]) return;
+  const double v = (double)S.f.yhat[i];
+  S.d.y[i] = v;
+  S.d.y0[i] = v;
+  S.d.yhat[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_expand_rows(const int* __restrict__ ptr, int m, int* __restrict__ row_of) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  for (int k = ptr[r]; k < ptr[r + 1]; ++k) row_of[k] = r;
+}
+
+__global__ void k_iota(int* v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (int)i;
+}
+
+__global__ void k_gather_transpose(const int* __restrict__ perm, const int* __restrict__ row_of,
+                                   const double* __restrict__ val, int64_t nnz, int* __restrict__ t_col,
+                                   double* __restrict__ t_val) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int k = perm[p];
+  t_col[p] = row_of[k];
+  t_val[p] = val[k];
+}
+
+// fac[r] = 1/sqrt(max_k |a_rk| drow_r dcol_c) (op 0) or of the sum (op 1); 1 for empty rows.
+__global__ __launch_bounds__(kThreads) void k_scale_factor(int op, const int* __restrict__ ptr,
+                                                           const int* __restrict__ col,
+                                                           const double* __restrict__ val,
+                                                           const double* __restrict__ drow,
+                                                           const double* __restrict__ dcol,
+                                                           const int* __restrict__ blk, int nblk,
+                                                           double* __restrict__ fac) {
+  __shared__ double red[kThreads / 64];
+  const int b = blockIdx.x;
+  if (b >= nblk) return;
+  const int r0 = blk[b];
+  const int r1 = blk[b + 1];
+  const int k0 = ptr[r0];
+  const int k1 = ptr[r1];
+  const int nz = k1 - k0;
+  auto term = [&](int k, int r) { return fabs(val[k]) * (drow[r] * dcol[col[k]]); };
+  if (nz <= kNnzTile) {
+    // one thread per row; the row index of each entry is needed for drow,
+    // so each thread walks its own row (rows are short after blocking)
+    const int r = r0 + threadIdx.x;
+    if (r < r1) {
+      double acc = 0.0;
+      for (int k = ptr[r]; k < ptr[r + 1]; ++k) {
+        const double v = term(k, r);
+        acc = op == 0 ? fmax(acc, v) : acc + v;
+      }
+      fac[r] = acc > 0.0 ? 1.0 / sqrt(acc) : 1.0;
+    }
+    return;
+  }
+  double acc = 0.0;
+  for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
+    const double v = term(k, r0);
+    acc = op == 0 ? fmax(acc, v) : acc + v;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(acc, off, 64);
+    acc = op == 0 ? fmax(acc, o) : acc + o;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < kThreads / 64; ++w) t = op == 0 ? fmax(t, red[w]) : t + red[w];
+    fac[r0] = t > 0.0 ? 1.0 / sqrt(t) : 1.0;
+  }
+}
+
+__global__ void k_mul_inplace(double* d, const double* f, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] *= f[i];
+}
+
+__global__ void k_scale_values(const int* __restrict__ ptr, const int* __restrict__ col,
+                               const double* __restrict__ raw, const double* __restrict__ drow,
+                               const double* __restrict__ dcol, int rows, double* __restrict__ v64,
+                               float* __restrict__ v32) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const double dr = drow[r];
+  for (int k = ptr[r]; k < ptr[r + 1]; ++k) {
+    // raw * (d_row * d_col): the same rounding for A and for its transpose
+    const double v = raw[k] * (dr * dcol[col[k]]);
+    v64[k] = v;
+    v32[k] = (float)v;
+  }
+}
+
+__global__ void k_fill(double* d, double v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = v;
+}
+
+__global__ void k_scale_vectors(const double* __restrict__ c, const double* __restrict__ l,
+                                const double* __restrict__ u, const double* __restrict__ b,
+                                const double* __restrict__ dc, const double* __restrict__ dr, int n,
+                                int m, int nscen, double* c64, double* l64, double* u64, double* b64,
+                                float* c32, float* l32, float* u32, float* b32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)n * nscen;
+  const int64_t mm = (int64_t)m * nscen;
+  if (i < nn) {
+    // scenario-major input (s * n + j) -> interleaved output (j * nscen + s)
+    const int s = (int)(i / n);
+    const int j = (int)(i % n);
+    const int64_t o = (int64_t)j * nscen + s;
+    const double d = dc[j];
+    const double cv = c[i] * d;
+    const double lv = l[i] / d;
+    const double uv = u[i] / d;
+    c64[o] = cv;
+    l64[o] = lv;
+    u64[o] = uv;
+    c32[o] = (float)cv;
+    l32[o] = (float)lv;
+    u32[o] = (float)uv;
+  } else if (i < nn + mm) {
+    const int64_t k = i - nn;
+    const int s = (int)(k / m);
+    const int r = (int)(k % m);
+    const int64_t o = (int64_t)r * nscen + s;
+    const double bv = b[k] * dr[r];
+    b64[o] = bv;
+    b32[o] = (float)bv;
+  }
+}
+
+template <typename V, typename ACC>
+__global__ __launch_bounds__(kThreads) void k_spmv(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                   const V* __restrict__ val, const V* __restrict__ x,
+                                                   V* __restrict__ y, const int* __restrict__ blk,
+                                                   int nblk) {
+  __shared__ ACC lds[kNnzTile];
+  __shared__ ACC red[kThreads / 64];
+  const int t = xcd_tile(nblk);
+  if (t < 0) return;
+  int r;
+  ACC s;
+  if (block_row_sum<ACC>(ptr, blk[t], blk[t + 1], lds, red,
+                         [&](int k) { return (ACC)val[k] * (ACC)x[col[k]]; }, r, s))
+    y[r] = (V)s;
+}
+
+// ---- merge-path SpMV (Merrill & Garland, SC'16) -----------------------------
+// The merge of the row-end list (row_ptr[1..m]) with the entry indices
+// 0..nnz-1 has m + nnz steps; each thread takes kMergeItems consecutive
+// steps.  A thread's first coordinate comes from a binary search along its
+// diagonal.  Rows finished inside a thread are written directly; the partial
+// sum of the row still open at the end of a thread is a carry, added by a
+// second kernel in thread order (deterministic).
+constexpr int kMergeItems = 8;
+
+__device__ inline void merge_search(int diag, const int* __restrict__ row_end, int m, int64_t nnz,
+                                    int& row, int& k) {
+  int lo = diag - (int)nnz > 0 ? diag - (int)nnz : 0;
+  int hi = diag < m ? diag : m;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    // consume a row end before entry (diag - mid - 1) when row_end[mid] <= that entry
+    if (row_end[mid] <= diag - mid - 1) lo = mid + 1;
+    else hi = mid;
+  }
+  row = lo;
+  k = diag - lo;
+}
+
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_spmv_merge(const int* __restrict__ ptr,
+                                                         const int* __restrict__ col,
+                                                         const V* __restrict__ val,
+                                                         const V* __restrict__ x, V* __restrict__ y,
+                                                         int m, int64_t nnz, int nthreads,
+                                                         int* __restrict__ carry_row,
+                                                         V* __restrict__ carry_val) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nthreads) return;
+  const int64_t total = (int64_t)m + nnz;
+  const int d0 = (int)min((int64_t)tid * kMergeItems, total);
+  const int d1 = (int)min((int64_t)(tid + 1) * kMergeItems, total);
+  const int* row_end = ptr + 1;
+  int row, k, row1, k1;
+  merge_search(d0, row_end, m, nnz, row, k);
+  merge_search(d1, row_end, m, nnz, row1, k1);
+  V sum = 0;
+  for (; row < row1; ++row) {
+    const int e = row_end[row];
+    for (; k < e; ++k) sum += val[k] * x[col[k]];
+    y[row] = sum;
+    sum = 0;
+  }
+  for (; k < k1; ++k) sum += val[k] * x[col[k]];
+  carry_row[tid] = row1 < m ? row1 : -1;
+  carry_val[tid] = sum;
+}
+
+// A row may collect carries from several consecutive threads and its final
+// piece from the thread where it ends (already written to y).  Thread t adds
+// its carry only if it is the first of its row's run, summing the whole run.
+template <typename V>
+__global__ void k_merge_fixup(const int* __restrict__ carry_row, const V* __restrict__ carry_val,
+                              int nthreads, V* __restrict__ y, const int* __restrict__ ptr) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nthreads) return;
+  const int r = carry_row[t];
+  if (r < 0) return;
+  if (t > 0 && carry_row[t - 1] == r) return;
+  V s = 0;
+  for (int u = t; u < nthreads && carry_row[u] == r; ++u) s += carry_val[u];
+  // the row's own thread wrote y[r] = (its piece); carries precede it in order
+  y[r] = s + y[r];
+  (void)ptr;
+}
+
+// ---- reductions / vectors --------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_sumsq_part(const double* __restrict__ v, int64_t n,
+                                                         double* __restrict__ part) {
+  __shared__ double red[kThreads / 64];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    acc += v[i] * v[i];
+  double q[1] = {acc};
+  const bool mx[1] = {false};
+  block_reduce<1>(q, mx, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = q[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_sum_part(const double* __restrict__ part, int np,
+                                                       double* __restrict__ out) {
+  __shared__ double red[kThreads / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += kThreads) acc += part[i];
+  double q[1] = {acc};
+  const bool mx[1] = {false};
+  block_reduce<1>(q, mx, red);
+  if (threadIdx.x == 0) *out = q[0];
+}
+
+__global__ void k_normalize(const double* __restrict__ w, const double* __restrict__ nrm2,
+                            double* __restrict__ v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = *nrm2;
+  v[i] = s > 0.0 ? w[i] / sqrt(s) : 0.0;
+}
+
+// deterministic pseudo-random start vector in [-1, 1): a 32-bit integer hash
+// (Wang's mix) of (index, seed)
+__global__ void k_hash_vector(double* v, int64_t n, uint32_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t h = (uint32_t)i * 2654435761u ^ seed;
+  h = (h ^ 61u) ^ (h >> 16);
+  h *= 9u;
+  h ^= h >> 4;
+  h *= 0x27d4eb2du;
+  h ^= h >> 15;
+  v[i] = (double)h / 2147483648.0 - 1.0;
+}
+
+template <typename T>
+__global__ void k_init_iterates(const SlotDev* __restrict__ slot, const double* __restrict__ x_in,
+                                const double* __restrict__ y_in, int n, int m, int m_eq, int nscen) {
+  const SlotDev& S = *slot;
+  const Vecs<T>& V = vecs<T>(S);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)n * nscen;
+  const int64_t mm = (int64_t)m * nscen;
+  if (i < nn) {
+    const int j = (int)(i / nscen);
+    double v = x_in ? x_in[i] / S.dc[j] : 0.0;
+    T tv = clampv<T>((T)v, V.l[i], V.u[i]);
+    V.x[i] = tv;
+    V.x0[i] = tv;
+    V.xhat[i] = tv;
+    V.xbar[i] = tv;
+  } else if (i < nn + mm) {
+    const int64_t k = i - nn;
+    const int r = (int)(k / nscen);
+    double v = y_in ? y_in[k] / S.dr[r] : 0.0;
+    if (r >= m_eq && v < 0.0) v = 0.0;
+    V.y[k] = (T)v;
+    V.y0[k] = (T)v;
+    V.yhat[k] = (T)v;
+  }
+}
+
+template <typename T>
+__global__ void k_unscale(const SlotDev* __restrict__ slot, double* __restrict__ x_out,
+                          double* __restrict__ y_out, int n, int m, int nscen) {
+  const SlotDev& S = *slot;
+  const Vecs<T>& V = vecs<T>(S);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)n * nscen;
+  const int64_t mm = (int64_t)m * nscen;
+  if (i < nn) {
+    x_out[i] = (double)V.xhat[i] * S.dc[i / nscen];
+  } else if (i < nn + mm) {
+    const int64_t k = i - nn;
+    y_out[k] = (double)V.yhat[k] * S.dr[k / nscen];
+  }
+}
+
+__global__ void k_to_f32(const double* a, float* b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+__global__ void k_copy(const float4* __restrict__ a, float4* __restrict__ b, int64_t n4) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline int nb(int64_t n, int t = kThreads) { return (int)((n + t - 1) / t); }
+
+void launch_primal(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
+                   int jiter, int nscen, hipStream_t s) {
+  if (ntiles <= 0) return;
+  (void)nscen;
+  dim3 g(xcd_grid(ntiles));
+  if (prec == 1) {
+    if (check) k_primal<float, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    else k_primal<float, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+  } else {
+    if (check) k_primal<double, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    else k_primal<double, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+  }
+}
+
+void launch_dual(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
+                 int jiter, int nscen, hipStream_t s) {
+  if (ntiles <= 0) return;
+  (void)nscen;
+  dim3 g(xcd_grid(ntiles));
+  if (prec == 1) {
+    if (check) k_dual<float, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    else k_dual<float, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+  } else {
+    if (check) k_dual<double, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    else k_dual<double, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+  }
+}
+
+void launch_kkt(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
+                int natiles, int nscen, hipStream_t s) {
+  (void)nscen;
+  if (prec == 1) {
+    if (natiles > 0) k_kkt_rows<float><<<xcd_grid(natiles), kThreads, 0, s>>>(slots, atiles, natiles);
+    if (nttiles > 0) k_kkt_cols<float><<<xcd_grid(nttiles), kThreads, 0, s>>>(slots, ttiles, nttiles);
+  } else {
+    if (natiles > 0) k_kkt_rows<double><<<xcd_grid(natiles), kThreads, 0, s>>>(slots, atiles, natiles);
+    if (nttiles > 0) k_kkt_cols<double><<<xcd_grid(nttiles), kThreads, 0, s>>>(slots, ttiles, nttiles);
+  }
+}
+
+void launch_reduce(const SlotDev* slots, const int* slot_ids, int nslots, int nscen, hipStream_t s) {
+  (void)nscen;
+  if (nslots > 0) k_reduce<<<nslots, kThreads, 0, s>>>(slots, slot_ids);
+}
+
+void launch_finish(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
+                   int natiles, int kk, int nscen, hipStream_t s) {
+  (void)nscen;
+  if (prec == 1) {
+    if (nttiles > 0) k_finish_x<float><<<xcd_grid(nttiles), kThreads, 0, s>>>(slots, ttiles, nttiles, kk);
+    if (natiles > 0) k_finish_y<float><<<xcd_grid(natiles), kThreads, 0, s>>>(slots, atiles, natiles, kk);
+  } else {
+    if (nttiles > 0) k_finish_x<double><<<xcd_grid(nttiles), kThreads, 0, s>>>(slots, ttiles, nttiles, kk);
+    if (natiles > 0) k_finish_y<double><<<xcd_grid(natiles), kThreads, 0, s>>>(slots, atiles, natiles, kk);
+  }
+}
+
+void launch_promote(const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
+                    int natiles, int nscen, hipStream_t s) {
+  (void)nscen;
+  if (nttiles > 0) k_promote_x<<<xcd_grid(nttiles), kThreads, 0, s>>>(slots, ttiles, nttiles);
+  if (natiles > 0) k_promote_y<<<xcd_grid(natiles), kThreads, 0, s>>>(slots, atiles, natiles);
+}
+
+void launch_expand_rows(const int* ptr, int m, int* row_of, hipStream_t s) {
+  if (m > 0) k_expand_rows<<<nb(m), kThreads, 0, s>>>(ptr, m, row_of);
+}
+
+void launch_iota(int* v, int64_t n, hipStream_t s) {
+  if (n > 0) k_iota<<<nb(n), kThreads, 0, s>>>(v, n);
+}
+
+void launch_gather_transpose(const int* perm, const int* row_of, const double* val, int64_t nnz,
+                             int* t_col, double* t_val, hipStream_t s) {
+  if (nnz > 0) k_gather_transpose<<<nb(nnz), kThreads, 0, s>>>(perm, row_of, val, nnz, t_col, t_val);
+}
+
+static int key_bits(int n) {
+  int b = 1;
+  while (b < 31 && (1 << b) < n) ++b;
+  return b;
+}
+
+size_t radix_sort_temp_bytes(int64_t nnz, int n) {
+  size_t bytes = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const int*)nullptr, (int*)nullptr,
+                                     (const int*)nullptr, (int*)nullptr, (int)nnz, 0, key_bits(n));
+  return bytes;
+}
+
+int radix_sort_pairs(void* temp, size_t temp_bytes, const int* keys_in, int* keys_out,
+                     const int* vals_in, int* vals_out, int64_t nnz, int n, hipStream_t s) {
+  if (nnz == 0) return 0;
+  hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in,
+                                                    vals_out, (int)nnz, 0, key_bits(n), s);
+  return e == hipSuccess ? 0 : -1;
+}
+
+void launch_scale_factor(int op, const int* ptr, const int* col, const double* val, const double* drow,
+                         const double* dcol, const int* blk, int nblk, int rows, double* fac,
+                         hipStream_t s) {
+  (void)rows;
+  if (nblk > 0) k_scale_factor<<<nblk, kThreads, 0, s>>>(op, ptr, col, val, drow, dcol, blk, nblk, fac);
+}
+
+void launch_mul_inplace(double* d, const double* f, int n, hipStream_t s) {
+  if (n > 0) k_mul_inplace<<<nb(n), kThreads, 0, s>>>(d, f, n);
+}
+
+void launch_scale_values(const int* ptr, const int* col, const double* raw, const double* drow,
+                         const double* dcol, int rows, double* v64, float* v32, hipStream_t s) {
+  if (rows > 0) k_scale_values<<<nb(rows), kThreads, 0, s>>>(ptr, col, raw, drow, dcol, rows, v64, v32);
+}
+
+void launch_fill(double* d, double v, int64_t n, hipStream_t s) {
+  if (n > 0) k_fill<<<nb(n), kThreads, 0, s>>>(d, v, n);
+}
+
+void launch_scale_vectors(const double* c, const double* l, const double* u, const double* b,
+                          const double* dc, const double* dr, int n, int m, int nscen, double* c64,
+                          double* l64, double* u64, double* b64, float* c32, float* l32, float* u32,
+                          float* b32, hipStream_t s) {
+  const int64_t tot = (int64_t)(n + m) * nscen;
+  if (tot > 0)
+    k_scale_vectors<<<nb(tot), kThreads, 0, s>>>(c, l, u, b, dc, dr, n, m, nscen, c64, l64, u64, b64,
+                                                 c32, l32, u32, b32);
+}
+
+void launch_spmv64(const int* ptr, const int* col, const double* val, const double* x, double* y,
+                   const int* blk, int nblk, hipStream_t s) {
+  if (nblk > 0) k_spmv<double, double><<<xcd_grid(nblk), kThreads, 0, s>>>(ptr, col, val, x, y, blk, nblk);
+}
+
+void launch_spmv32(const int* ptr, const int* col, const float* val, const float* x, float* y,
+                   const int* blk, int nblk, hipStream_t s) {
+  if (nblk > 0) k_spmv<float, float><<<xcd_grid(nblk), kThreads, 0, s>>>(ptr, col, val, x, y, blk, nblk);
+}
+
+int merge_carry_count(int m, int64_t nnz) {
+  return (int)(((int64_t)m + nnz + kMergeItems - 1) / kMergeItems);
+}
+
+void launch_spmv_merge64(const int* ptr, const int* col, const double* val, const double* x, double* y,
+                         int m, int64_t nnz, int* carry_row, double* carry_val, hipStream_t s) {
+  const int nt = merge_carry_count(m, nnz);
+  if (nt <= 0) return;
+  k_spmv_merge<double><<<nb(nt), kThreads, 0, s>>>(ptr, col, val, x, y, m, nnz, nt, carry_row, carry_val);
+  k_merge_fixup<double><<<nb(nt), kThreads, 0, s>>>(carry_row, carry_val, nt, y, ptr);
+}
+
+void launch_spmv_merge32(const int* ptr, const int* col, const float* val, const float* x, float* y,
+                         int m, int64_t nnz, int* carry_row, float* carry_val, hipStream_t s) {
+  const int nt = merge_carry_count(m, nnz);
+  if (nt <= 0) return;
+  k_spmv_merge<float><<<nb(nt), kThreads, 0, s>>>(ptr, col, val, x, y, m, nnz, nt, carry_row, carry_val);
+  k_merge_fixup<float><<<nb(nt), kThreads, 0, s>>>(carry_row, carry_val, nt, y, ptr);
+}
+
+void launch_norm2(const double* v, int64_t n, double* part, double* out, hipStream_t s) {
+  int g = nb(n);
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  k_sumsq_part<<<g, kThreads, 0, s>>>(v, n, part);
+  k_sum_part<<<1, kThreads, 0, s>>>(part, g, out);
+}
+
+void launch_normalize(const double* w, const double* nrm2, double* v, int64_t n, hipStream_t s) {
+  if (n > 0) k_normalize<<<nb(n), kThreads, 0, s>>>(w, nrm2, v, n);
+}
+
+void launch_hash_vector(double* v, int64_t n, uint32_t seed, hipStream_t s) {
+  if (n > 0) k_hash_vector<<<nb(n), kThreads, 0, s>>>(v, n, seed);
+}
+
+void launch_init_iterates(const SlotDev* slot, int prec, const double* x_in, const double* y_in, int n,
+                          int m, int m_eq, int nscen, hipStream_t s) {
+  const int64_t tot = (int64_t)(n + m) * nscen;
+  if (tot <= 0) return;
+  if (prec == 1) k_init_iterates<float><<<nb(tot), kThreads, 0, s>>>(slot, x_in, y_in, n, m, m_eq, nscen);
+  else k_init_iterates<double><<<nb(tot), kThreads, 0, s>>>(slot, x_in, y_in, n, m, m_eq, nscen);
+}
+
+void launch_unscale(const SlotDev* slot, int prec, double* x_out, double* y_out, int n, int m, int nscen,
+                    hipStream_t s) {
+  const int64_t tot = (int64_t)(n + m) * nscen;
+  if (tot <= 0) return;
+  if (prec == 1) k_unscale<float><<<nb(tot), kThreads, 0, s>>>(slot, x_out, y_out, n, m, nscen);
+  else k_unscale<double><<<nb(tot), kThreads, 0, s>>>(slot, x_out, y_out, n, m, nscen);
+}
+
+void launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
+  if (n > 0) k_to_f32<<<nb(n), kThreads, 0, s>>>(a, b, n);
+}
+
+void launch_copy_kernel(const float4* a, float4* b, int64_t n4, hipStream_t s) {
+  int g = nb(n4);
+  if (g > 8192) g = 8192;
+  if (g > 0) k_copy<<<g, kThreads, 0, s>>>(a, b, n4);
+}
+
+}  // namespace uclp

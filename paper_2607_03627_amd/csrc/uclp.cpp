@@ -1,0 +1,1661 @@
+// libuclp host runtime: the C ABI of include/uc_lp.h.
+//
+// Layers (bottom up):
+//   presolve   validation, removal of fixed columns and empty rows, 'L' rows
+//              negated, equality rows first, row-block partitions
+//   Instance   one LP: host copy of the internal problem and one device arena
+//              (CSR of A and A^T, FP64 and FP32 scaled values, scaled data,
+//              iterates of both precisions, partial sums)
+//   setup      device transpose, Ruiz + Pock-Chambolle scaling, power
+//              iteration for ||A_hat||_2, initial iterates
+//   Engine     one device, an HBM budget, a FIFO of queued solves and a slot
+//              table; a worker thread runs epochs of kkt_every PDHG iterations
+//              over every resident instance with batched kernels, then one
+//              FP64 KKT check per instance, restart / primal-weight /
+//              termination decisions on the host, and admission of queued
+//              instances at the epoch boundary.
+//
+// The method (restarted reflected-Halpern PDHG with adaptive restarts and a
+// smoothed primal weight, after Applegate et al. 2021 and Lu & Yang 2024) is
+// the first-order LP solve that the paper runs on its GPU leg (Sec. II-C,
+// III-C) with the limits of Sec. II-D.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/uc_lp.h"
+#include "uclp_dev.h"
+
+using namespace uclp;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPOK(call)                                                                          \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(UC_LP_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                                 \
+  } while (0)
+
+static double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// options
+// ---------------------------------------------------------------------------
+
+extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->precision = UC_LP_FP32_MIXED_POLISH;
+  o->kkt_every = 64;
+  o->ruiz_iters = 10;
+  o->power_iters = 64;
+  o->iter_limit = 100000;
+  o->eps_rel = 1e-4;
+  o->eps_abs_feas = 0.0;
+  o->eps_polish = 1e-8;
+  o->time_limit_s = 3600.0;
+  o->step_scale = 0.99;
+  o->spmv_algo = UC_LP_SPMV_ROWSPLIT;
+  o->verbose = 0;
+  o->timing = 0;
+}
+
+static int check_opts(const uc_lp_opts& o) {
+  if (o.precision < 0 || o.precision > 2) return fail(UC_LP_ENOTSUP, "precision %d", o.precision);
+  if (o.kkt_every < 1 || o.kkt_every > 1 << 20) return fail(UC_LP_EINVAL, "kkt_every %d", o.kkt_every);
+  if (o.ruiz_iters < 0 || o.ruiz_iters > 1000) return fail(UC_LP_EINVAL, "ruiz_iters");
+  if (o.power_iters < 1 || o.power_iters > 100000) return fail(UC_LP_EINVAL, "power_iters");
+  if (o.iter_limit < 1) return fail(UC_LP_EINVAL, "iter_limit");
+  if (!(o.eps_rel > 0) || !(o.eps_polish > 0) || !(o.eps_abs_feas >= 0))
+    return fail(UC_LP_EINVAL, "tolerances must be positive");
+  if (!(o.time_limit_s > 0)) return fail(UC_LP_EINVAL, "time_limit_s");
+  if (!(o.step_scale > 0 && o.step_scale < 1)) return fail(UC_LP_EINVAL, "step_scale in (0,1)");
+  if (o.spmv_algo != UC_LP_SPMV_ROWSPLIT) return fail(UC_LP_ENOTSUP, "spmv_algo %d for PDHG", o.spmv_algo);
+  return UC_LP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation and minimal presolve
+// ---------------------------------------------------------------------------
+
+static int validate_csr(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                        const double* v) {
+  if (m < 1 || n < 1) return fail(UC_LP_EINVAL, "m=%d n=%d must be >= 1", m, n);
+  if (nnz < 0 || nnz > INT32_MAX) return fail(UC_LP_EINVAL, "nnz=%lld out of range", (long long)nnz);
+  if (!rp || (nnz > 0 && (!ci || !v))) return fail(UC_LP_EINVAL, "NULL CSR array");
+  if (rp[0] != 0) return fail(UC_LP_EINVAL, "row_ptr[0] != 0");
+  if (rp[m] != nnz) return fail(UC_LP_EINVAL, "row_ptr[m]=%d != nnz", rp[m]);
+  std::vector<int32_t> seen(n, -1);
+  for (int32_t r = 0; r < m; ++r) {
+    if (rp[r + 1] < rp[r]) return fail(UC_LP_EINVAL, "row_ptr not monotone at row %d", r);
+    for (int32_t k = rp[r]; k < rp[r + 1]; ++k) {
+      const int32_t c = ci[k];
+      if (c < 0 || c >= n) return fail(UC_LP_EINVAL, "column index %d out of range at entry %d", c, k);
+      if (seen[c] == r) return fail(UC_LP_EINVAL, "duplicate entry (%d,%d)", r, c);
+      seen[c] = r;
+      if (!std::isfinite(v[k])) return fail(UC_LP_EINVAL, "non-finite matrix value at entry %d", k);
+    }
+  }
+  return UC_LP_OK;
+}
+
+static int validate_data(int32_t m, int32_t n, const double* c, const double* b, const char* sense,
+                         const double* lb, const double* ub) {
+  if (!c || !b || !sense || !lb || !ub) return fail(UC_LP_EINVAL, "NULL data array");
+  for (int32_t j = 0; j < n; ++j) {
+    if (!std::isfinite(c[j])) return fail(UC_LP_EINVAL, "non-finite cost c[%d]", j);
+    if (std::isnan(lb[j]) || std::isnan(ub[j])) return fail(UC_LP_EINVAL, "NaN bound at column %d", j);
+    if (lb[j] > ub[j]) return fail(UC_LP_EINVAL, "lb > ub at column %d", j);
+    if (lb[j] == INFINITY || ub[j] == -INFINITY) return fail(UC_LP_EINVAL, "infinite bound on the wrong side at column %d", j);
+  }
+  for (int32_t i = 0; i < m; ++i) {
+    if (!std::isfinite(b[i])) return fail(UC_LP_EINVAL, "non-finite right-hand side b[%d]", i);
+    if (sense[i] != 'E' && sense[i] != 'G' && sense[i] != 'L')
+      return fail(UC_LP_EINVAL, "unknown sense code %d at row %d", (int)sense[i], i);
+  }
+  return UC_LP_OK;
+}
+
+static void partition_rows(const std::vector<int>& ptr, int rows, std::vector<int>& blk) {
+  blk.clear();
+  blk.push_back(0);
+  int r = 0;
+  while (r < rows) {
+    const int start = r;
+    const int z0 = ptr[r];
+    if (ptr[r + 1] - z0 > kNnzTile) {
+      ++r;
+      blk.push_back(r);
+      continue;
+    }
+    while (r < rows && r - start < kRowsPerBlock && ptr[r + 1] - z0 <= kNnzTile) ++r;
+    blk.push_back(r);
+  }
+}
+
+struct HostProblem {
+  int32_t m = 0, n = 0;
+  int64_t nnz = 0;
+  // original data (kept for update_data and postsolve)
+  std::vector<int32_t> o_ptr, o_col;
+  std::vector<double> o_val, o_c, o_b, o_lb, o_ub;
+  std::vector<char> o_sense;
+  // internal problem
+  int mi = 0, ni = 0, m_eq = 0;
+  int64_t nnzi = 0;
+  std::vector<int> a_ptr, a_col, t_ptr, a_blk, t_blk;
+  std::vector<double> a_val, c, b, l, u;
+  std::vector<int> row_map;  // internal row -> original row (negative: -(row+1), negated 'L')
+  std::vector<int> col_map;  // internal column -> original column
+  std::vector<int> int_col;  // original column -> internal column or -1 (fixed)
+  double obj_offset = 0.0;
+  double norm_b = 0.0, norm_c = 0.0;
+  bool infeasible = false;
+};
+
+// Data-dependent part of the presolve (right-hand side shift, objective
+// offset, norms, feasibility of removed rows).  The structure (which columns
+// are fixed and which rows are empty) is fixed at create time.
+static void presolve_data(HostProblem& P) {
+  const int32_t m = P.m;
+  std::vector<double> shift(m, 0.0);
+  P.obj_offset = 0.0;
+  for (int32_t r = 0; r < m; ++r)
+    for (int32_t k = P.o_ptr[r]; k < P.o_ptr[r + 1]; ++k) {
+      const int j = P.o_col[k];
+      if (P.int_col[j] < 0) shift[r] += P.o_val[k] * P.o_lb[j];
+    }
+  for (int32_t j = 0; j < P.n; ++j)
+    if (P.int_col[j] < 0) P.obj_offset += P.o_c[j] * P.o_lb[j];
+  P.infeasible = false;
+  std::vector<char> kept(m, 0);
+  for (int i = 0; i < P.mi; ++i) {
+    const int enc = P.row_map[i];
+    const int r = enc >= 0 ? enc : -enc - 1;
+    kept[r] = 1;
+    const double sgn = enc >= 0 ? 1.0 : -1.0;
+    P.b[i] = sgn * (P.o_b[r] - shift[r]);
+  }
+  for (int32_t r = 0; r < m; ++r) {
+    if (kept[r]) continue;
+    const double rhs = P.o_b[r] - shift[r];  // removed row reads 0 (=,>=,<=) rhs
+    const double tol = 1e-9 * (1.0 + std::fabs(P.o_b[r]));
+    if ((P.o_sense[r] == 'E' && std::fabs(rhs) > tol) || (P.o_sense[r] == 'G' && rhs > tol) ||
+        (P.o_sense[r] == 'L' && rhs < -tol))
+      P.infeasible = true;
+  }
+  for (int j = 0; j < P.ni; ++j) {
+    const int o = P.col_map[j];
+    P.c[j] = P.o_c[o];
+    P.l[j] = P.o_lb[o];
+    P.u[j] = P.o_ub[o];
+  }
+  double nb = 0, nc = 0;
+  for (int32_t r = 0; r < m; ++r) nb += P.o_b[r] * P.o_b[r];
+  for (int32_t j = 0; j < P.n; ++j) nc += P.o_c[j] * P.o_c[j];
+  P.norm_b = std::sqrt(nb);
+  P.norm_c = std::sqrt(nc);
+}
+
+static void presolve_structure(HostProblem& P) {
+  const int32_t m = P.m, n = P.n;
+  P.int_col.assign(n, -1);
+  P.col_map.clear();
+  for (int32_t j = 0; j < n; ++j)
+    if (!(P.o_lb[j] == P.o_ub[j])) {
+      P.int_col[j] = (int)P.col_map.size();
+      P.col_map.push_back(j);
+    }
+  P.ni = (int)P.col_map.size();
+  // rows with at least one entry in a kept column; E rows first
+  std::vector<int> cnt(m, 0);
+  for (int32_t r = 0; r < m; ++r)
+    for (int32_t k = P.o_ptr[r]; k < P.o_ptr[r + 1]; ++k)
+      if (P.int_col[P.o_col[k]] >= 0) ++cnt[r];
+  P.row_map.clear();
+  for (int pass = 0; pass < 2; ++pass)
+    for (int32_t r = 0; r < m; ++r) {
+      if (cnt[r] == 0) continue;
+      const bool eq = P.o_sense[r] == 'E';
+      if ((pass == 0) != eq) continue;
+      P.row_map.push_back(P.o_sense[r] == 'L' ? -(r + 1) : r);
+    }
+  P.m_eq = 0;
+  for (int enc : P.row_map)
+    if (enc >= 0 && P.o_sense[enc] == 'E') ++P.m_eq;
+  P.mi = (int)P.row_map.size();
+  P.a_ptr.assign(P.mi + 1, 0);
+  P.a_col.clear();
+  P.a_val.clear();
+  for (int i = 0; i < P.mi; ++i) {
+    const int enc = P.row_map[i];
+    const int r = enc >= 0 ? enc : -enc - 1;
+    const double sgn = enc >= 0 ? 1.0 : -1.0;
+    // keep the columns of a row in increasing internal order
+    std::vector<std::pair<int, double>> ent;
+    for (int32_t k = P.o_ptr[r]; k < P.o_ptr[r + 1]; ++k) {
+      const int jc = P.int_col[P.o_col[k]];
+      if (jc >= 0) ent.emplace_back(jc, sgn * P.o_val[k]);
+    }
+    std::sort(ent.begin(), ent.end());
+    for (auto& e : ent) {
+      P.a_col.push_back(e.first);
+      P.a_val.push_back(e.second);
+    }
+    P.a_ptr[i + 1] = (int)P.a_col.size();
+  }
+  P.nnzi = (int64_t)P.a_col.size();
+  // transposed row pointer (column counts) and both partitions
+  P.t_ptr.assign(P.ni + 1, 0);
+  for (int c : P.a_col) ++P.t_ptr[c + 1];
+  for (int j = 0; j < P.ni; ++j) P.t_ptr[j + 1] += P.t_ptr[j];
+  partition_rows(P.a_ptr, P.mi, P.a_blk);
+  partition_rows(P.t_ptr, P.ni, P.t_blk);
+  P.b.assign(P.mi, 0.0);
+  P.c.assign(P.ni, 0.0);
+  P.l.assign(P.ni, 0.0);
+  P.u.assign(P.ni, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// device arena of one instance
+// ---------------------------------------------------------------------------
+
+struct Arena {
+  char* base = nullptr;
+  size_t bytes = 0, used = 0;
+  template <typename T>
+  T* take(size_t count) {
+    const size_t off = (used + 255) & ~(size_t)255;
+    used = off + std::max<size_t>(count, 1) * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
+template <typename T>
+static void carve_vecs(Arena& A, Vecs<T>& V, int n, int m, int ns) {
+  V.x = A.take<T>((size_t)n * ns);
+  V.x0 = A.take<T>((size_t)n * ns);
+  V.xbar = A.take<T>((size_t)n * ns);
+  V.xhat = A.take<T>((size_t)n * ns);
+  V.y = A.take<T>((size_t)m * ns);
+  V.y0 = A.take<T>((size_t)m * ns);
+  V.yhat = A.take<T>((size_t)m * ns);
+  V.c = A.take<T>((size_t)n * ns);
+  V.l = A.take<T>((size_t)n * ns);
+  V.u = A.take<T>((size_t)n * ns);
+  V.b = A.take<T>((size_t)m * ns);
+}
+
+struct DevMem {
+  Arena ar;
+  int *a_ptr, *a_col, *t_ptr, *t_col, *a_blk, *t_blk;
+  double *a_raw, *t_raw;
+  double *a_v64, *t_v64;
+  float *a_v32, *t_v32;
+  double *c_in, *b_in, *l_in, *u_in;  // unscaled internal data (scenario-major)
+  double *dr, *dc, *fr, *fc;
+  double *part_a, *part_t, *scal;
+  double *x_out, *y_out, *x_warm, *y_warm;
+  double *pv, *pw, *pu, *red_part, *red_out;  // power iteration / norms
+  int *row_of, *keys_in, *keys_out, *perm_in, *perm_out;
+  void* sort_temp;
+  size_t sort_bytes;
+  Vecs<float> f;
+  Vecs<double> d;
+  SlotDev* slot_dev;  // device copy of this instance's descriptor
+};
+
+static void carve(DevMem& D, const HostProblem& P, int ns) {
+  Arena& A = D.ar;
+  const int m = P.mi, n = P.ni;
+  const int64_t z = P.nnzi;
+  D.a_ptr = A.take<int>(m + 1);
+  D.a_col = A.take<int>(z);
+  D.t_ptr = A.take<int>(n + 1);
+  D.t_col = A.take<int>(z);
+  D.a_blk = A.take<int>(P.a_blk.size());
+  D.t_blk = A.take<int>(P.t_blk.size());
+  D.a_raw = A.take<double>(z);
+  D.t_raw = A.take<double>(z);
+  D.a_v64 = A.take<double>(z);
+  D.t_v64 = A.take<double>(z);
+  D.a_v32 = A.take<float>(z);
+  D.t_v32 = A.take<float>(z);
+  D.c_in = A.take<double>((size_t)n * ns);
+  D.l_in = A.take<double>((size_t)n * ns);
+  D.u_in = A.take<double>((size_t)n * ns);
+  D.b_in = A.take<double>((size_t)m * ns);
+  D.dr = A.take<double>(m);
+  D.dc = A.take<double>(n);
+  D.fr = A.take<double>(m);
+  D.fc = A.take<double>(n);
+  const size_t na = P.a_blk.size(), nt = P.t_blk.size();
+  D.part_a = A.take<double>(na * RQ_N * ns);
+  D.part_t = A.take<double>(nt * CQ_N * ns);
+  D.scal = A.take<double>((size_t)kScal * ns);
+  D.x_out = A.take<double>((size_t)n * ns);
+  D.y_out = A.take<double>((size_t)m * ns);
+  D.x_warm = A.take<double>((size_t)n * ns);
+  D.y_warm = A.take<double>((size_t)m * ns);
+  D.pv = A.take<double>(n);
+  D.pw = A.take<double>(n);
+  D.pu = A.take<double>(m);
+  D.red_part = A.take<double>(1024);
+  D.red_out = A.take<double>(8);
+  D.row_of = A.take<int>(z);
+  D.keys_in = D.a_col;  // the sort reads the column indices in place
+  D.keys_out = A.take<int>(z);
+  D.perm_in = A.take<int>(z);
+  D.perm_out = A.take<int>(z);
+  D.sort_bytes = radix_sort_temp_bytes(z, n);
+  D.sort_temp = A.take<char>(D.sort_bytes);
+  carve_vecs(A, D.f, n, m, ns);
+  carve_vecs(A, D.d, n, m, ns);
+  D.slot_dev = A.take<SlotDev>(1);
+}
+
+static size_t arena_bytes(const HostProblem& P, int ns) {
+  DevMem D;
+  std::memset((void*)&D, 0, sizeof D);
+  carve(D, P, ns);
+  return D.ar.used + 256;
+}
+
+// ---------------------------------------------------------------------------
+// engine and instance
+// ---------------------------------------------------------------------------
+
+struct PdhgState {
+  int prec = 1;          // 1: FP32 phase, 0: FP64 phase
+  double eta = 0, omega = 1;
+  long long k_inner = 0;    // steps since the last restart
+  long long phase_total = 0;
+  long long iters = 0, iters64 = 0, restarts = 0;
+  bool r_start_set = false, r_prev_set = false;
+  double r_start = 0, r_prev = 0;
+  double t_start = 0;
+};
+
+struct uc_engine {
+  int device = 0;
+  size_t budget = 0, used = 0;
+  int max_slots = 1;
+  bool private_engine = false;
+  hipStream_t stream = nullptr;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<uc_lp*> queue;
+  std::vector<uc_lp*> active;
+  bool shutdown = false;
+  // device tables
+  SlotDev* d_slots = nullptr;
+  Tile* d_tiles = nullptr;
+  size_t tile_cap = 0;
+  int* d_ids = nullptr;
+  double* h_scal = nullptr;  // pinned, max_slots * kScal
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  std::vector<SlotDev> h_slots;
+  std::string err;
+};
+
+struct uc_lp {
+  uc_engine* eng = nullptr;
+  bool owns_engine = false;
+  uc_lp_opts opts;
+  HostProblem P;
+  DevMem D;
+  bool uploaded = false;
+  bool setup_done = false;
+  size_t need_bytes = 0;
+  std::atomic<int> status{UC_LP_IDLE};
+  std::atomic<bool> cancel{false};
+  mutable std::mutex mu;
+  std::condition_variable done_cv;
+  uc_lp_info info;
+  std::vector<double> warm_x, warm_y;  // internal space
+  bool has_warm = false;
+  std::vector<double> sol_x, sol_y;    // original space
+  PdhgState st;
+  int slot = -1;
+  double t_request = 0;
+  double timed_primal_ms = 0, timed_dual_ms = 0;
+  long long timed_n = 0;
+};
+
+static void set_info(uc_lp* lp, const uc_lp_info& in) {
+  std::lock_guard<std::mutex> g(lp->mu);
+  lp->info = in;
+}
+
+static uc_lp_info get_info(const uc_lp* lp) {
+  std::lock_guard<std::mutex> g(lp->mu);
+  return lp->info;
+}
+
+static void finish_status(uc_lp* lp, int status) {
+  {
+    std::lock_guard<std::mutex> g(lp->mu);
+    lp->info.status = status;
+    lp->status.store(status);
+  }
+  lp->done_cv.notify_all();
+}
+
+static bool terminal(int s) {
+  return s == UC_LP_OPTIMAL || s == UC_LP_ITER_LIMIT || s == UC_LP_TIME_LIMIT || s == UC_LP_CANCELLED ||
+         s == UC_LP_NUMERICAL || s == UC_LP_INFEASIBLE || s == UC_LP_FAILED;
+}
+
+// ---- device memory of an instance ------------------------------------------
+
+static int upload(uc_lp* lp) {
+  HostProblem& P = lp->P;
+  DevMem& D = lp->D;
+  hipStream_t s = lp->eng->stream;
+  std::memset((void*)&D, 0, sizeof D);
+  const size_t bytes = arena_bytes(P, 1);
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(UC_LP_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  D.ar.base = (char*)base;
+  D.ar.bytes = bytes;
+  carve(D, P, 1);
+  HIPOK(hipMemcpyAsync(D.a_ptr, P.a_ptr.data(), sizeof(int) * (P.mi + 1), hipMemcpyHostToDevice, s));
+  if (P.nnzi) {
+    HIPOK(hipMemcpyAsync(D.a_col, P.a_col.data(), sizeof(int) * P.nnzi, hipMemcpyHostToDevice, s));
+    HIPOK(hipMemcpyAsync(D.a_raw, P.a_val.data(), sizeof(double) * P.nnzi, hipMemcpyHostToDevice, s));
+  }
+  HIPOK(hipMemcpyAsync(D.t_ptr, P.t_ptr.data(), sizeof(int) * (P.ni + 1), hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(D.a_blk, P.a_blk.data(), sizeof(int) * P.a_blk.size(), hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(D.t_blk, P.t_blk.data(), sizeof(int) * P.t_blk.size(), hipMemcpyHostToDevice, s));
+  HIPOK(hipStreamSynchronize(s));
+  lp->uploaded = true;
+  lp->setup_done = false;
+  return UC_LP_OK;
+}
+
+static void release(uc_lp* lp) {
+  if (lp->D.ar.base) {
+    (void)hipFree(lp->D.ar.base);
+    lp->D.ar.base = nullptr;
+  }
+  lp->uploaded = false;
+  lp->setup_done = false;
+}
+
+static SlotDev make_slot(const uc_lp* lp) {
+  const HostProblem& P = lp->P;
+  const DevMem& D = lp->D;
+  SlotDev S;
+  std::memset((void*)&S, 0, sizeof S);
+  S.a_ptr = D.a_ptr;
+  S.a_col = D.a_col;
+  S.t_ptr = D.t_ptr;
+  S.t_col = D.t_col;
+  S.a_blk = D.a_blk;
+  S.t_blk = D.t_blk;
+  S.m = P.mi;
+  S.n = P.ni;
+  S.m_eq = P.m_eq;
+  S.nscen = 1;
+  S.a_nblk = (int)P.a_blk.size() - 1;
+  S.t_nblk = (int)P.t_blk.size() - 1;
+  S.dr = D.dr;
+  S.dc = D.dc;
+  S.f = D.f;
+  S.d = D.d;
+  S.f.av = D.a_v32;
+  S.f.tv = D.t_v32;
+  S.d.av = D.a_v64;
+  S.d.tv = D.t_v64;
+  S.part_a = D.part_a;
+  S.part_t = D.part_t;
+  S.scal = D.scal;
+  return S;
+}
+
+// Transpose, scaling, scaled data, power iteration.  Runs on `s`, synchronous.
+static int setup_device(uc_lp* lp) {
+  HostProblem& P = lp->P;
+  DevMem& D = lp->D;
+  hipStream_t s = lp->eng->stream;
+  const int m = P.mi, n = P.ni;
+  const int64_t z = P.nnzi;
+  const int na = (int)P.a_blk.size() - 1, nt = (int)P.t_blk.size() - 1;
+  // data (may have changed through uc_lp_update_data)
+  HIPOK(hipMemcpyAsync(D.c_in, P.c.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(D.l_in, P.l.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(D.u_in, P.u.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  if (m) HIPOK(hipMemcpyAsync(D.b_in, P.b.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
+  // a1: A^T by a stable radix sort of the column indices
+  launch_expand_rows(D.a_ptr, m, D.row_of, s);
+  launch_iota(D.perm_in, z, s);
+  if (radix_sort_pairs(D.sort_temp, D.sort_bytes, D.keys_in, D.keys_out, D.perm_in, D.perm_out, z, n, s))
+    return fail(UC_LP_EHIP, "radix sort failed");
+  launch_gather_transpose(D.perm_out, D.row_of, D.a_raw, z, D.t_col, D.t_raw, s);
+  // a2: Ruiz equilibration then Pock-Chambolle (alpha = 1)
+  launch_fill(D.dr, 1.0, m, s);
+  launch_fill(D.dc, 1.0, n, s);
+  for (int it = 0; it < lp->opts.ruiz_iters; ++it) {
+    launch_scale_factor(0, D.a_ptr, D.a_col, D.a_raw, D.dr, D.dc, D.a_blk, na, m, D.fr, s);
+    launch_scale_factor(0, D.t_ptr, D.t_col, D.t_raw, D.dc, D.dr, D.t_blk, nt, n, D.fc, s);
+    launch_mul_inplace(D.dr, D.fr, m, s);
+    launch_mul_inplace(D.dc, D.fc, n, s);
+  }
+  launch_scale_factor(1, D.a_ptr, D.a_col, D.a_raw, D.dr, D.dc, D.a_blk, na, m, D.fr, s);
+  launch_scale_factor(1, D.t_ptr, D.t_col, D.t_raw, D.dc, D.dr, D.t_blk, nt, n, D.fc, s);
+  launch_mul_inplace(D.dr, D.fr, m, s);
+  launch_mul_inplace(D.dc, D.fc, n, s);
+  launch_scale_values(D.a_ptr, D.a_col, D.a_raw, D.dr, D.dc, m, D.a_v64, D.a_v32, s);
+  launch_scale_values(D.t_ptr, D.t_col, D.t_raw, D.dc, D.dr, n, D.t_v64, D.t_v32, s);
+  launch_scale_vectors(D.c_in, D.l_in, D.u_in, D.b_in, D.dc, D.dr, n, m, 1, (double*)D.d.c,
+                       (double*)D.d.l, (double*)D.d.u, (double*)D.d.b, (float*)D.f.c, (float*)D.f.l,
+                       (float*)D.f.u, (float*)D.f.b, s);
+  // a3: ||A_hat||_2 by power iteration on A_hat' A_hat, and ||c_hat||, ||b_hat||
+  launch_norm2(D.d.c, n, D.red_part, D.red_out + 1, s);
+  if (m) launch_norm2(D.d.b, m, D.red_part, D.red_out + 2, s);
+  else launch_fill(D.red_out + 2, 0.0, 1, s);
+  launch_hash_vector(D.pv, n, 12345u, s);
+  launch_norm2(D.pv, n, D.red_part, D.red_out, s);
+  launch_normalize(D.pv, D.red_out, D.pv, n, s);
+  for (int it = 0; it < lp->opts.power_iters; ++it) {
+    launch_spmv64(D.a_ptr, D.a_col, D.a_v64, D.pv, D.pu, D.a_blk, na, s);
+    launch_spmv64(D.t_ptr, D.t_col, D.t_v64, D.pu, D.pw, D.t_blk, nt, s);
+    launch_norm2(D.pw, n, D.red_part, D.red_out, s);
+    launch_normalize(D.pw, D.red_out, D.pv, n, s);
+  }
+  double h[3] = {0, 0, 0};
+  HIPOK(hipMemcpyAsync(h, D.red_out, sizeof h, hipMemcpyDeviceToHost, s));
+  HIPOK(hipStreamSynchronize(s));
+  HIPOK(hipGetLastError());
+  const double norm_est = std::pow(std::max(h[0], 0.0), 0.25);
+  const double cn = std::sqrt(h[1]), bn = std::sqrt(h[2]);
+  PdhgState& st = lp->st;
+  st.eta = norm_est > 0 ? lp->opts.step_scale / norm_est : 1.0;
+  st.omega = (cn > 0 && bn > 0) ? cn / bn : 1.0;
+  {
+    std::lock_guard<std::mutex> g(lp->mu);
+    lp->info.norm_a_est = norm_est;
+    lp->info.omega = st.omega;
+  }
+  SlotDev S = make_slot(lp);
+  HIPOK(hipMemcpyAsync(D.slot_dev, &S, sizeof S, hipMemcpyHostToDevice, s));
+  HIPOK(hipStreamSynchronize(s));
+  lp->setup_done = true;
+  return UC_LP_OK;
+}
+
+static int init_iterates(uc_lp* lp, int prec) {
+  DevMem& D = lp->D;
+  HostProblem& P = lp->P;
+  hipStream_t s = lp->eng->stream;
+  const double *xi = nullptr, *yi = nullptr;
+  if (lp->has_warm) {
+    HIPOK(hipMemcpyAsync(D.x_warm, lp->warm_x.data(), sizeof(double) * P.ni, hipMemcpyHostToDevice, s));
+    if (P.mi) HIPOK(hipMemcpyAsync(D.y_warm, lp->warm_y.data(), sizeof(double) * P.mi, hipMemcpyHostToDevice, s));
+    xi = D.x_warm;
+    yi = D.y_warm;
+  }
+  launch_init_iterates(D.slot_dev, prec, xi, yi, P.ni, P.mi, P.m_eq, 1, s);
+  HIPOK(hipGetLastError());
+  return UC_LP_OK;
+}
+
+static int fetch_solution(uc_lp* lp, int prec) {
+  DevMem& D = lp->D;
+  HostProblem& P = lp->P;
+  hipStream_t s = lp->eng->stream;
+  launch_unscale(D.slot_dev, prec, D.x_out, D.y_out, P.ni, P.mi, 1, s);
+  std::vector<double> xi(P.ni), yi(P.mi);
+  HIPOK(hipMemcpyAsync(xi.data(), D.x_out, sizeof(double) * P.ni, hipMemcpyDeviceToHost, s));
+  if (P.mi) HIPOK(hipMemcpyAsync(yi.data(), D.y_out, sizeof(double) * P.mi, hipMemcpyDeviceToHost, s));
+  HIPOK(hipStreamSynchronize(s));
+  lp->sol_x.assign(P.n, 0.0);
+  lp->sol_y.assign(P.m, 0.0);
+  for (int32_t j = 0; j < P.n; ++j)
+    if (P.int_col[j] < 0) lp->sol_x[j] = P.o_lb[j];
+  for (int j = 0; j < P.ni; ++j) lp->sol_x[P.col_map[j]] = xi[j];
+  for (int i = 0; i < P.mi; ++i) {
+    const int enc = P.row_map[i];
+    if (enc >= 0) lp->sol_y[enc] = yi[i];
+    else lp->sol_y[-enc - 1] = -yi[i];
+  }
+  return UC_LP_OK;
+}
+
+// ---- the KKT check: scalars -> info, restart / termination decisions -------
+
+struct CheckOut {
+  bool terminate = false;
+  int status = UC_LP_RUNNING;
+  bool restart = false;
+  bool promote = false;
+};
+
+static void kkt_from_scalars(const uc_lp* lp, const double* q, uc_lp_info& in) {
+  const HostProblem& P = lp->P;
+  const double rho_p = std::sqrt(std::max(q[RQ_RES2], 0.0));
+  const double rho_d = std::sqrt(std::max(q[RQ_N + CQ_DRES2], 0.0));
+  const double pobj = q[RQ_N + CQ_CX] + P.obj_offset;
+  const double dobj = q[RQ_BY] + q[RQ_N + CQ_LBUB] + P.obj_offset;
+  in.pobj = pobj;
+  in.dobj = dobj;
+  in.rel_primal = rho_p / (1.0 + P.norm_b);
+  in.rel_dual = rho_d / (1.0 + P.norm_c);
+  in.rel_gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
+  in.rel_kkt = std::max(in.rel_primal, std::max(in.rel_dual, in.rel_gap));
+  in.abs_primal_inf = q[RQ_RESMAX];
+}
+
+static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
+  PdhgState& st = lp->st;
+  const uc_lp_opts& o = lp->opts;
+  CheckOut out;
+  uc_lp_info in = get_info(lp);
+  kkt_from_scalars(lp, q, in);
+  st.iters += K;
+  if (st.prec == 0) st.iters64 += K;
+  st.phase_total += K;
+  const long long k_end = st.k_inner + K;
+  const double dx2 = q[RQ_N + CQ_DX2], dy2 = q[RQ_DY2], cross = q[RQ_DYADX];
+  const double rfp2 = st.omega / st.eta * dx2 + dy2 / (st.omega * st.eta) - 2.0 * cross;
+  const double rfp = std::sqrt(std::max(rfp2, 0.0));
+  in.iters = st.iters;
+  in.iters_fp64 = st.iters64;
+  in.precision_now = st.prec == 1 ? UC_LP_FP32_MIXED : UC_LP_FP64;
+  in.t_total_s = tnow - st.t_start;
+  const bool feas_ok = o.eps_abs_feas <= 0 || in.abs_primal_inf <= o.eps_abs_feas;
+  const bool finite = std::isfinite(in.rel_kkt) && std::isfinite(rfp) && std::isfinite(in.pobj);
+  if (!finite) {
+    out.terminate = true;
+    out.status = UC_LP_NUMERICAL;
+  } else {
+    if (in.t_to_eps_s < 0 && in.rel_kkt <= o.eps_rel && feas_ok) {
+      in.t_to_eps_s = tnow - st.t_start;
+      in.pobj_at_eps = in.pobj;
+      in.rel_kkt_at_eps = in.rel_kkt;
+    }
+    const bool polish_phase = o.precision == UC_LP_FP32_MIXED_POLISH && st.prec == 0;
+    const double target = polish_phase ? o.eps_polish : o.eps_rel;
+    if (in.rel_kkt <= target && feas_ok) {
+      if (o.precision == UC_LP_FP32_MIXED_POLISH && st.prec == 1) {
+        out.promote = true;
+      } else {
+        out.terminate = true;
+        out.status = UC_LP_OPTIMAL;
+      }
+    }
+    if (!out.terminate && st.iters >= o.iter_limit) {
+      out.terminate = true;
+      out.status = UC_LP_ITER_LIMIT;
+    }
+    if (!out.terminate && in.t_total_s >= o.time_limit_s) {
+      out.terminate = true;
+      out.status = UC_LP_TIME_LIMIT;
+    }
+    if (!out.terminate && lp->cancel.load()) {
+      out.terminate = true;
+      out.status = UC_LP_CANCELLED;
+    }
+  }
+  if (!out.terminate && !out.promote) {
+    if (!st.r_start_set) {
+      st.r_start = rfp;
+      st.r_start_set = true;
+    }
+    bool rs = rfp <= 0.2 * st.r_start;
+    if (!rs && rfp <= 0.8 * st.r_start && st.r_prev_set && rfp > st.r_prev) rs = true;
+    if (!rs && (double)k_end >= 0.36 * (double)st.phase_total) rs = true;
+    st.r_prev = rfp;
+    st.r_prev_set = true;
+    if (rs) {
+      const double dX = std::sqrt(std::max(q[RQ_N + CQ_DX0], 0.0));
+      const double dY = std::sqrt(std::max(q[RQ_DY0], 0.0));
+      if (dX > 1e-10 && dY > 1e-10) st.omega = std::exp(0.5 * std::log(dY / dX) + 0.5 * std::log(st.omega));
+      st.k_inner = 0;
+      st.r_start_set = false;
+      st.r_prev_set = false;
+      ++st.restarts;
+      out.restart = true;
+    } else {
+      st.k_inner = k_end;
+    }
+  }
+  if (out.promote) {
+    // the FP64 phase starts at (x_hat, y_hat) as after a restart
+    st.prec = 0;
+    st.k_inner = 0;
+    st.phase_total = 0;
+    st.r_start_set = false;
+    st.r_prev_set = false;
+  }
+  in.restarts = st.restarts;
+  in.omega = st.omega;
+  if (lp->timed_n > 0) {
+    in.primal_kernel_us = 1e3 * lp->timed_primal_ms / lp->timed_n;
+    in.dual_kernel_us = 1e3 * lp->timed_dual_ms / lp->timed_n;
+    in.timed_launches = lp->timed_n;
+  }
+  if (o.verbose)
+    fprintf(stderr, "[uclp] it %lld prec %s kkt %.2e (p %.1e d %.1e g %.1e) pobj %.10g omega %.3g rfp %.3e rs %lld\n",
+            st.iters, st.prec ? "fp32" : "fp64", in.rel_kkt, in.rel_primal, in.rel_dual, in.rel_gap, in.pobj,
+            st.omega, rfp, st.restarts);
+  set_info(lp, in);
+  return out;
+}
+
+// ---- engine worker -----------------------------------------------------------
+
+static int engine_tables(uc_engine* E, size_t ntiles) {
+  if (ntiles > E->tile_cap) {
+    if (E->d_tiles) (void)hipFree(E->d_tiles);
+    E->d_tiles = nullptr;
+    size_t cap = std::max<size_t>(ntiles, 2 * E->tile_cap);
+    HIPOK(hipMalloc(&E->d_tiles, cap * sizeof(Tile)));
+    E->tile_cap = cap;
+  }
+  return UC_LP_OK;
+}
+
+static void worker_fail(uc_engine* E, uc_lp* lp) {
+  {
+    std::lock_guard<std::mutex> g(lp->mu);
+    lp->info.status = UC_LP_FAILED;
+  }
+  std::fprintf(stderr, "[uclp] solve failed: %s\n", g_err.c_str());
+  E->err = g_err;
+  lp->status.store(UC_LP_FAILED);
+  lp->done_cv.notify_all();
+}
+
+static void start_instance(uc_engine* E, uc_lp* lp) {
+  const double t0 = now_s();
+  lp->st = PdhgState();
+  lp->st.t_start = t0;
+  lp->timed_primal_ms = lp->timed_dual_ms = 0;
+  lp->timed_n = 0;
+  {
+    std::lock_guard<std::mutex> g(lp->mu);
+    uc_lp_info in;
+    std::memset(&in, 0, sizeof in);
+    in.status = UC_LP_RUNNING;
+    in.t_to_eps_s = -1;
+    in.t_queue_s = t0 - lp->t_request;
+    in.m_presolved = lp->P.mi;
+    in.n_presolved = lp->P.ni;
+    in.nnz_presolved = lp->P.nnzi;
+    in.device_bytes = (int64_t)lp->need_bytes;
+    lp->info = in;
+  }
+  lp->status.store(UC_LP_RUNNING);
+  if (lp->P.infeasible) {
+    finish_status(lp, UC_LP_INFEASIBLE);
+    return;
+  }
+  int rc = UC_LP_OK;
+  if (!lp->uploaded) rc = upload(lp);
+  if (rc == UC_LP_OK) rc = setup_device(lp);
+  lp->st.prec = lp->opts.precision == UC_LP_FP64 ? 0 : 1;
+  if (rc == UC_LP_OK) rc = init_iterates(lp, lp->st.prec);
+  if (rc != UC_LP_OK) {
+    worker_fail(E, lp);
+    return;
+  }
+  {
+    std::lock_guard<std::mutex> g(lp->mu);
+    lp->info.t_setup_s = now_s() - t0;
+    lp->info.omega = lp->st.omega;
+  }
+  E->active.push_back(lp);
+}
+
+static void retire(uc_engine* E, uc_lp* lp, int status) {
+  int rc = fetch_solution(lp, lp->st.prec);
+  if (!E->private_engine) {
+    release(lp);
+    std::lock_guard<std::mutex> g(E->mu);
+    E->used -= lp->need_bytes;
+  }
+  {
+    std::lock_guard<std::mutex> g(lp->mu);
+    lp->info.t_total_s = now_s() - lp->st.t_start;
+  }
+  if (rc != UC_LP_OK) worker_fail(E, lp);
+  else finish_status(lp, status);
+}
+
+static void run_epochs(uc_engine* E) {
+  hipStream_t s = E->stream;
+  // batch layout: slots 0..A-1 are the active instances in order
+  const int A = (int)E->active.size();
+  int K = 1 << 30;
+  for (auto* lp : E->active) K = std::min(K, lp->opts.kkt_every);
+  std::vector<Tile> tt[2], at[2];
+  std::vector<int> ids(A);
+  E->h_slots.resize(std::max<size_t>(E->h_slots.size(), (size_t)A));
+  for (int a = 0; a < A; ++a) {
+    uc_lp* lp = E->active[a];
+    lp->slot = a;
+    ids[a] = a;
+    SlotDev S = make_slot(lp);
+    S.tau[0] = lp->st.eta / lp->st.omega;
+    S.sigma[0] = lp->st.eta * lp->st.omega;
+    S.k0[0] = lp->st.k_inner;
+    S.restart[0] = 0;
+    S.active[0] = 1;
+    E->h_slots[a] = S;
+    const int p = lp->st.prec;
+    for (int b = 0; b < S.t_nblk; ++b) tt[p].push_back({a, b});
+    for (int b = 0; b < S.a_nblk; ++b) at[p].push_back({a, b});
+  }
+  const size_t off_t1 = 0, off_t0 = tt[1].size(), off_a1 = off_t0 + tt[0].size(),
+               off_a0 = off_a1 + at[1].size(), total = off_a0 + at[0].size();
+  if (engine_tables(E, total) != UC_LP_OK) {
+    for (auto* lp : E->active) worker_fail(E, lp);
+    E->active.clear();
+    return;
+  }
+  std::vector<Tile> all;
+  all.reserve(total);
+  all.insert(all.end(), tt[1].begin(), tt[1].end());
+  all.insert(all.end(), tt[0].begin(), tt[0].end());
+  all.insert(all.end(), at[1].begin(), at[1].end());
+  all.insert(all.end(), at[0].begin(), at[0].end());
+  hipError_t e = hipSuccess;
+  if (total) e = hipMemcpyAsync(E->d_tiles, all.data(), total * sizeof(Tile), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(E->d_slots, E->h_slots.data(), A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(E->d_ids, ids.data(), A * sizeof(int), hipMemcpyHostToDevice, s);
+  const Tile* T1 = E->d_tiles + off_t1;
+  const Tile* T0 = E->d_tiles + off_t0;
+  const Tile* A1 = E->d_tiles + off_a1;
+  const Tile* A0 = E->d_tiles + off_a0;
+  const int nT1 = (int)tt[1].size(), nT0 = (int)tt[0].size(), nA1 = (int)at[1].size(), nA0 = (int)at[0].size();
+  bool timing = false;
+  for (auto* lp : E->active) timing |= lp->opts.timing != 0;
+  for (int j = 0; j < K && e == hipSuccess; ++j) {
+    const bool check = j == K - 1;
+    const bool tj = timing && j == 0;
+    if (tj) (void)hipEventRecord(E->ev[0], s);
+    launch_primal(1, check, E->d_slots, T1, nT1, j, 1, s);
+    launch_primal(0, check, E->d_slots, T0, nT0, j, 1, s);
+    if (tj) (void)hipEventRecord(E->ev[1], s);
+    launch_dual(1, check, E->d_slots, A1, nA1, j, 1, s);
+    launch_dual(0, check, E->d_slots, A0, nA0, j, 1, s);
+    if (tj) (void)hipEventRecord(E->ev[2], s);
+  }
+  launch_kkt(1, E->d_slots, T1, nT1, A1, nA1, 1, s);
+  launch_kkt(0, E->d_slots, T0, nT0, A0, nA0, 1, s);
+  launch_reduce(E->d_slots, E->d_ids, A, 1, s);
+  for (int a = 0; a < A && e == hipSuccess; ++a)
+    e = hipMemcpyAsync(E->h_scal + (size_t)a * kScal, E->active[a]->D.scal, kScal * sizeof(double),
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    fail(UC_LP_EHIP, "epoch failed: %s", hipGetErrorString(e));
+    for (auto* lp : E->active) worker_fail(E, lp);
+    E->active.clear();
+    return;
+  }
+  if (timing) {
+    float t01 = 0, t12 = 0;
+    if (hipEventElapsedTime(&t01, E->ev[0], E->ev[1]) == hipSuccess &&
+        hipEventElapsedTime(&t12, E->ev[1], E->ev[2]) == hipSuccess) {
+      for (auto* lp : E->active)
+        if (lp->opts.timing) {
+          lp->timed_primal_ms += t01;
+          lp->timed_dual_ms += t12;
+          ++lp->timed_n;
+        }
+    }
+  }
+  const double tnow = now_s();
+  std::vector<CheckOut> outs(A);
+  for (int a = 0; a < A; ++a) {
+    uc_lp* lp = E->active[a];
+    // the finish kernel needs the epoch-start k0 and the restart decision
+    outs[a] = process_check(lp, E->h_scal + (size_t)a * kScal, K, tnow);
+    E->h_slots[a].restart[0] = outs[a].restart ? 1 : 0;
+  }
+  e = hipMemcpyAsync(E->d_slots, E->h_slots.data(), A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
+  launch_finish(1, E->d_slots, T1, nT1, A1, nA1, K - 1, 1, s);
+  launch_finish(0, E->d_slots, T0, nT0, A0, nA0, K - 1, 1, s);
+  // precision switches: FP32 x_hat, y_hat -> FP64 iterates of the same slot
+  std::vector<Tile> pt, pa, both;
+  for (int a = 0; a < A; ++a)
+    if (outs[a].promote) {
+      for (int b = 0; b < E->h_slots[a].t_nblk; ++b) pt.push_back({a, b});
+      for (int b = 0; b < E->h_slots[a].a_nblk; ++b) pa.push_back({a, b});
+    }
+  if (!pt.empty() || !pa.empty()) {
+    // reuse the tile buffer after the epoch's kernels (same stream, ordered)
+    both = pt;
+    both.insert(both.end(), pa.begin(), pa.end());
+    if (engine_tables(E, both.size()) == UC_LP_OK) {
+      (void)hipMemcpyAsync(E->d_tiles, both.data(), both.size() * sizeof(Tile), hipMemcpyHostToDevice, s);
+      launch_promote(E->d_slots, E->d_tiles, (int)pt.size(), E->d_tiles + pt.size(), (int)pa.size(), 1, s);
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  std::vector<uc_lp*> keep;
+  for (int a = 0; a < A; ++a) {
+    uc_lp* lp = E->active[a];
+    if (outs[a].terminate) retire(E, lp, outs[a].status);
+    else keep.push_back(lp);
+  }
+  E->active.swap(keep);
+}
+
+static void worker_main(uc_engine* E) {
+  (void)hipSetDevice(E->device);
+  for (;;) {
+    std::vector<uc_lp*> admit;
+    {
+      std::unique_lock<std::mutex> g(E->mu);
+      if (E->active.empty())
+        E->cv.wait(g, [&] { return E->shutdown || !E->queue.empty(); });
+      if (E->shutdown && E->queue.empty() && E->active.empty()) break;
+      // drop cancelled queued requests
+      for (auto it = E->queue.begin(); it != E->queue.end();) {
+        if ((*it)->cancel.load()) {
+          uc_lp* lp = *it;
+          it = E->queue.erase(it);
+          if (!E->private_engine) E->used -= lp->need_bytes;
+          g.unlock();
+          finish_status(lp, UC_LP_CANCELLED);
+          g.lock();
+        } else {
+          ++it;
+        }
+      }
+      while (!E->queue.empty() && (int)(E->active.size() + admit.size()) < E->max_slots) {
+        uc_lp* lp = E->queue.front();
+        if (!E->private_engine && E->used + lp->need_bytes > E->budget) break;
+        if (!E->private_engine) E->used += lp->need_bytes;
+        E->queue.pop_front();
+        admit.push_back(lp);
+      }
+      if (E->shutdown) {
+        for (auto* lp : E->active) lp->cancel.store(true);
+      }
+    }
+    for (auto* lp : admit) start_instance(E, lp);
+    if (!E->active.empty()) run_epochs(E);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C ABI: engine
+// ---------------------------------------------------------------------------
+
+static int engine_init(uc_engine* E) {
+  HIPOK(hipSetDevice(E->device));
+  HIPOK(hipStreamCreate(&E->stream));
+  HIPOK(hipMalloc(&E->d_slots, sizeof(SlotDev) * E->max_slots));
+  HIPOK(hipMalloc(&E->d_ids, sizeof(int) * E->max_slots));
+  HIPOK(hipHostMalloc((void**)&E->h_scal, sizeof(double) * kScal * E->max_slots, hipHostMallocDefault));
+  for (auto& ev : E->ev) HIPOK(hipEventCreate(&ev));
+  E->worker = std::thread(worker_main, E);
+  return UC_LP_OK;
+}
+
+static void engine_free(uc_engine* E) {
+  if (!E) return;
+  {
+    std::lock_guard<std::mutex> g(E->mu);
+    E->shutdown = true;
+  }
+  E->cv.notify_all();
+  if (E->worker.joinable()) E->worker.join();
+  (void)hipSetDevice(E->device);
+  if (E->d_slots) (void)hipFree(E->d_slots);
+  if (E->d_ids) (void)hipFree(E->d_ids);
+  if (E->d_tiles) (void)hipFree(E->d_tiles);
+  if (E->h_scal) (void)hipHostFree(E->h_scal);
+  for (auto& ev : E->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (E->stream) (void)hipStreamDestroy(E->stream);
+  delete E;
+}
+
+extern "C" int uc_engine_create(int device, size_t hbm_budget_bytes, int32_t max_slots, uc_engine** out) {
+  g_err.clear();
+  if (!out) return fail(UC_LP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 1024) return fail(UC_LP_EINVAL, "max_slots %d not in 1..1024", max_slots);
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(UC_LP_EHIP, "no HIP device");
+  if (device < 0 || device >= count) return fail(UC_LP_EINVAL, "device %d of %d", device, count);
+  uc_engine* E = new (std::nothrow) uc_engine();
+  if (!E) return fail(UC_LP_ENOMEM, "engine allocation");
+  E->device = device;
+  E->max_slots = max_slots;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete E;
+    return fail(UC_LP_EHIP, "hipSetDevice");
+  }
+  size_t fr = 0, tot = 0;
+  (void)hipMemGetInfo(&fr, &tot);
+  E->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+  int rc = engine_init(E);
+  if (rc != UC_LP_OK) {
+    engine_free(E);
+    return rc;
+  }
+  *out = E;
+  return UC_LP_OK;
+}
+
+extern "C" void uc_engine_destroy(uc_engine* eng) {
+  if (!eng) return;
+  {
+    std::lock_guard<std::mutex> g(eng->mu);
+    for (auto* lp : eng->queue) lp->cancel.store(true);
+    for (auto* lp : eng->active) lp->cancel.store(true);
+  }
+  engine_free(eng);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI: instances
+// ---------------------------------------------------------------------------
+
+extern "C" int uc_lp_create(uc_engine* eng, int32_t m, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                            const int32_t* col_idx, const double* val, const double* c, const double* b,
+                            const char* sense, const double* lb, const double* ub, const uc_lp_opts* opts,
+                            uc_lp** out) {
+  g_err.clear();
+  if (!out) return fail(UC_LP_EINVAL, "out is NULL");
+  *out = nullptr;
+  uc_lp_opts o;
+  uc_lp_opts_default(&o);
+  if (opts) o = *opts;
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if ((rc = validate_csr(m, n, nnz, row_ptr, col_idx, val))) return rc;
+  if ((rc = validate_data(m, n, c, b, sense, lb, ub))) return rc;
+  std::unique_ptr<uc_lp> lp(new (std::nothrow) uc_lp());
+  if (!lp) return fail(UC_LP_ENOMEM, "instance allocation");
+  lp->opts = o;
+  HostProblem& P = lp->P;
+  P.m = m;
+  P.n = n;
+  P.nnz = nnz;
+  P.o_ptr.assign(row_ptr, row_ptr + m + 1);
+  P.o_col.assign(col_idx, col_idx + nnz);
+  P.o_val.assign(val, val + nnz);
+  P.o_c.assign(c, c + n);
+  P.o_b.assign(b, b + m);
+  P.o_sense.assign(sense, sense + m);
+  P.o_lb.assign(lb, lb + n);
+  P.o_ub.assign(ub, ub + n);
+  presolve_structure(P);
+  presolve_data(P);
+  if (P.ni == 0) return fail(UC_LP_ENOTSUP, "every column is fixed; nothing to solve");
+  lp->need_bytes = arena_bytes(P, 1);
+  std::memset(&lp->info, 0, sizeof lp->info);
+  lp->info.t_to_eps_s = -1;
+  if (eng) {
+    if (lp->need_bytes > eng->budget)
+      return fail(UC_LP_EBUDGET, "instance needs %zu bytes, engine budget is %zu", lp->need_bytes, eng->budget);
+    lp->eng = eng;
+  } else {
+    uc_engine* E = nullptr;
+    rc = uc_engine_create(0, 0, 1, &E);
+    if (rc) return rc;
+    E->private_engine = true;
+    lp->eng = E;
+    lp->owns_engine = true;
+    rc = upload(lp.get());
+    if (rc) {
+      uc_engine_destroy(E);
+      return rc;
+    }
+  }
+  *out = lp.release();
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_update_data(uc_lp* lp, const double* c, const double* b, const double* lb,
+                                 const double* ub) {
+  g_err.clear();
+  if (!lp) return fail(UC_LP_EINVAL, "NULL handle");
+  const int s = lp->status.load();
+  if (s == UC_LP_QUEUED || s == UC_LP_RUNNING) return fail(UC_LP_ESTATE, "solve in progress");
+  HostProblem& P = lp->P;
+  std::vector<double> nc = c ? std::vector<double>(c, c + P.n) : P.o_c;
+  std::vector<double> nb = b ? std::vector<double>(b, b + P.m) : P.o_b;
+  std::vector<double> nl = lb ? std::vector<double>(lb, lb + P.n) : P.o_lb;
+  std::vector<double> nu = ub ? std::vector<double>(ub, ub + P.n) : P.o_ub;
+  int rc = validate_data(P.m, P.n, nc.data(), nb.data(), P.o_sense.data(), nl.data(), nu.data());
+  if (rc) return rc;
+  for (int32_t j = 0; j < P.n; ++j)
+    if ((nl[j] == nu[j]) != (P.int_col[j] < 0))
+      return fail(UC_LP_ENOTSUP, "column %d changes between fixed and free; create a new instance", j);
+  P.o_c.swap(nc);
+  P.o_b.swap(nb);
+  P.o_lb.swap(nl);
+  P.o_ub.swap(nu);
+  presolve_data(P);
+  lp->setup_done = false;
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_solve(uc_lp* lp, const double* x0, const double* y0) {
+  g_err.clear();
+  if (!lp) return fail(UC_LP_EINVAL, "NULL handle");
+  const int s = lp->status.load();
+  if (s == UC_LP_QUEUED || s == UC_LP_RUNNING) return fail(UC_LP_ESTATE, "solve already in progress");
+  HostProblem& P = lp->P;
+  lp->has_warm = x0 || y0;
+  if (lp->has_warm) {
+    lp->warm_x.assign(P.ni, 0.0);
+    lp->warm_y.assign(P.mi, 0.0);
+    if (x0)
+      for (int j = 0; j < P.ni; ++j) lp->warm_x[j] = x0[P.col_map[j]];
+    if (y0)
+      for (int i = 0; i < P.mi; ++i) {
+        const int enc = P.row_map[i];
+        lp->warm_y[i] = enc >= 0 ? y0[enc] : -y0[-enc - 1];
+      }
+    for (double v : lp->warm_x)
+      if (!std::isfinite(v)) return fail(UC_LP_EINVAL, "non-finite warm start");
+    for (double v : lp->warm_y)
+      if (!std::isfinite(v)) return fail(UC_LP_EINVAL, "non-finite warm start");
+  }
+  lp->cancel.store(false);
+  lp->t_request = now_s();
+  uc_engine* E = lp->eng;
+  {
+    std::lock_guard<std::mutex> g(lp->mu);
+    lp->info.status = UC_LP_QUEUED;
+    lp->info.t_to_eps_s = -1;
+  }
+  lp->status.store(UC_LP_QUEUED);
+  {
+    std::lock_guard<std::mutex> g(E->mu);
+    E->queue.push_back(lp);
+  }
+  E->cv.notify_all();
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_status(const uc_lp* lp, uc_lp_info* out) {
+  g_err.clear();
+  if (!lp || !out) return fail(UC_LP_EINVAL, "NULL argument");
+  *out = get_info(lp);
+  out->status = lp->status.load();
+  if (out->status == UC_LP_RUNNING && lp->st.t_start > 0) out->t_total_s = now_s() - lp->st.t_start;
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_wait(uc_lp* lp, double timeout_s) {
+  g_err.clear();
+  if (!lp) return fail(UC_LP_EINVAL, "NULL handle");
+  std::unique_lock<std::mutex> g(lp->mu);
+  auto pending = [&] {
+    const int s = lp->status.load();
+    return s == UC_LP_QUEUED || s == UC_LP_RUNNING;
+  };
+  if (timeout_s < 0) {
+    lp->done_cv.wait(g, [&] { return !pending(); });
+    return UC_LP_OK;
+  }
+  if (!lp->done_cv.wait_for(g, std::chrono::duration<double>(timeout_s), [&] { return !pending(); }))
+    return fail(UC_LP_ETIMEOUT, "wait timed out");
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_cancel(uc_lp* lp) {
+  g_err.clear();
+  if (!lp) return fail(UC_LP_EINVAL, "NULL handle");
+  lp->cancel.store(true);
+  lp->eng->cv.notify_all();
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_get_solution(const uc_lp* lp, double* x, double* y) {
+  g_err.clear();
+  if (!lp) return fail(UC_LP_EINVAL, "NULL handle");
+  const int s = lp->status.load();
+  if (!(s == UC_LP_OPTIMAL || s == UC_LP_ITER_LIMIT || s == UC_LP_TIME_LIMIT || s == UC_LP_CANCELLED ||
+        s == UC_LP_NUMERICAL))
+    return fail(UC_LP_ESTATE, "no solution in status %d", s);
+  if (lp->sol_x.size() != (size_t)lp->P.n) return fail(UC_LP_ESTATE, "solution not available");
+  if (x) std::memcpy(x, lp->sol_x.data(), sizeof(double) * lp->P.n);
+  if (y) std::memcpy(y, lp->sol_y.data(), sizeof(double) * lp->P.m);
+  return UC_LP_OK;
+}
+
+extern "C" void uc_lp_destroy(uc_lp* lp) {
+  if (!lp) return;
+  lp->cancel.store(true);
+  uc_engine* E = lp->eng;
+  E->cv.notify_all();
+  {
+    std::unique_lock<std::mutex> g(lp->mu);
+    lp->done_cv.wait(g, [&] {
+      const int s = lp->status.load();
+      return s != UC_LP_QUEUED && s != UC_LP_RUNNING;
+    });
+  }
+  if (lp->owns_engine) {
+    engine_free(E);  // joins the worker before the instance memory goes
+    (void)hipSetDevice(0);
+    release(lp);
+  } else {
+    (void)hipSetDevice(E->device);
+    if (lp->uploaded) {
+      release(lp);
+    }
+  }
+  delete lp;
+}
+
+extern "C" const char* uc_lp_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// step-level entry points
+// ---------------------------------------------------------------------------
+
+static int debug_ready(uc_lp* lp) {
+  if (!lp) return fail(UC_LP_EINVAL, "NULL handle");
+  if (!lp->owns_engine) return fail(UC_LP_ESTATE, "step-level calls need a handle created with eng == NULL");
+  const int s = lp->status.load();
+  if (s == UC_LP_QUEUED || s == UC_LP_RUNNING) return fail(UC_LP_ESTATE, "solve in progress");
+  HIPOK(hipSetDevice(lp->eng->device));
+  if (!lp->uploaded) {
+    int rc = upload(lp);
+    if (rc) return rc;
+  }
+  if (!lp->setup_done) return setup_device(lp);
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_internal_dims(uc_lp* lp, int32_t* m_int, int32_t* n_int, int64_t* nnz_int, int32_t* m_eq,
+                                   int32_t* row_map, int32_t* col_map) {
+  g_err.clear();
+  if (!lp) return fail(UC_LP_EINVAL, "NULL handle");
+  const HostProblem& P = lp->P;
+  if (m_int) *m_int = P.mi;
+  if (n_int) *n_int = P.ni;
+  if (nnz_int) *nnz_int = P.nnzi;
+  if (m_eq) *m_eq = P.m_eq;
+  if (row_map) std::memcpy(row_map, P.row_map.data(), sizeof(int) * P.mi);
+  if (col_map) std::memcpy(col_map, P.col_map.data(), sizeof(int) * P.ni);
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_get_transpose(uc_lp* lp, int32_t* t_row_ptr, int32_t* t_col, double* t_val) {
+  g_err.clear();
+  int rc = debug_ready(lp);
+  if (rc) return rc;
+  hipStream_t s = lp->eng->stream;
+  const HostProblem& P = lp->P;
+  if (t_row_ptr) HIPOK(hipMemcpyAsync(t_row_ptr, lp->D.t_ptr, sizeof(int) * (P.ni + 1), hipMemcpyDeviceToHost, s));
+  if (t_col && P.nnzi) HIPOK(hipMemcpyAsync(t_col, lp->D.t_col, sizeof(int) * P.nnzi, hipMemcpyDeviceToHost, s));
+  if (t_val && P.nnzi) HIPOK(hipMemcpyAsync(t_val, lp->D.t_raw, sizeof(double) * P.nnzi, hipMemcpyDeviceToHost, s));
+  HIPOK(hipStreamSynchronize(s));
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_get_scaling(uc_lp* lp, double* d_row, double* d_col, double* norm_est) {
+  g_err.clear();
+  int rc = debug_ready(lp);
+  if (rc) return rc;
+  hipStream_t s = lp->eng->stream;
+  const HostProblem& P = lp->P;
+  if (d_row && P.mi) HIPOK(hipMemcpyAsync(d_row, lp->D.dr, sizeof(double) * P.mi, hipMemcpyDeviceToHost, s));
+  if (d_col) HIPOK(hipMemcpyAsync(d_col, lp->D.dc, sizeof(double) * P.ni, hipMemcpyDeviceToHost, s));
+  HIPOK(hipStreamSynchronize(s));
+  if (norm_est) *norm_est = get_info(lp).norm_a_est;
+  return UC_LP_OK;
+}
+
+template <typename T>
+static int put_vec(T* dst, const double* src, size_t n, hipStream_t s) {
+  std::vector<T> tmp(src, src + n);
+  HIPOK(hipMemcpyAsync(dst, tmp.data(), sizeof(T) * n, hipMemcpyHostToDevice, s));
+  HIPOK(hipStreamSynchronize(s));
+  return UC_LP_OK;
+}
+
+template <typename T>
+static int get_vec(double* dst, const T* src, size_t n, hipStream_t s) {
+  std::vector<T> tmp(n);
+  HIPOK(hipMemcpyAsync(tmp.data(), src, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+  HIPOK(hipStreamSynchronize(s));
+  for (size_t i = 0; i < n; ++i) dst[i] = (double)tmp[i];
+  return UC_LP_OK;
+}
+
+template <typename T>
+static int debug_step_t(uc_lp* lp, const double* x, const double* y, const double* x0, const double* y0,
+                        int64_t k, double tau, double sigma, double* xh, double* yh, double* xn,
+                        double* yn) {
+  const HostProblem& P = lp->P;
+  DevMem& D = lp->D;
+  uc_engine* E = lp->eng;
+  hipStream_t s = E->stream;
+  const int prec = sizeof(T) == 4 ? 1 : 0;
+  Vecs<T>& V = prec ? *(Vecs<T>*)&D.f : *(Vecs<T>*)&D.d;
+  int rc;
+  if ((rc = put_vec<T>(V.x, x, P.ni, s)) || (rc = put_vec<T>(V.x0, x0, P.ni, s)) ||
+      (rc = put_vec<T>(V.y, y, P.mi, s)) || (rc = put_vec<T>(V.y0, y0, P.mi, s)))
+    return rc;
+  SlotDev S = make_slot(lp);
+  S.tau[0] = tau;
+  S.sigma[0] = sigma;
+  S.k0[0] = k;
+  S.active[0] = 1;
+  std::vector<Tile> tl;
+  for (int b = 0; b < S.t_nblk; ++b) tl.push_back({0, b});
+  for (int b = 0; b < S.a_nblk; ++b) tl.push_back({0, b});
+  if ((rc = engine_tables(E, tl.size()))) return rc;
+  HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(E->d_tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+  const Tile* TT = E->d_tiles;
+  const Tile* TA = E->d_tiles + S.t_nblk;
+  // check-mode half-steps write x_hat, y_hat and keep x, y; the finish kernel
+  // then applies the Halpern step exactly as in the solve
+  launch_primal(prec, true, E->d_slots, TT, S.t_nblk, 0, 1, s);
+  launch_dual(prec, true, E->d_slots, TA, S.a_nblk, 0, 1, s);
+  launch_finish(prec, E->d_slots, TT, S.t_nblk, TA, S.a_nblk, 0, 1, s);
+  HIPOK(hipGetLastError());
+  HIPOK(hipStreamSynchronize(s));
+  if ((rc = get_vec<T>(xh, V.xhat, P.ni, s)) || (rc = get_vec<T>(yh, V.yhat, P.mi, s)) ||
+      (rc = get_vec<T>(xn, V.x, P.ni, s)) || (rc = get_vec<T>(yn, V.y, P.mi, s)))
+    return rc;
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_debug_step(uc_lp* lp, int32_t precision, const double* x, const double* y,
+                                const double* x0, const double* y0, int64_t k, double tau, double sigma,
+                                double* x_hat, double* y_hat, double* x_next, double* y_next) {
+  g_err.clear();
+  int rc = debug_ready(lp);
+  if (rc) return rc;
+  if (!x || !y || !x0 || !y0 || !x_hat || !y_hat || !x_next || !y_next)
+    return fail(UC_LP_EINVAL, "NULL vector");
+  if (k < 0 || !(tau > 0) || !(sigma > 0)) return fail(UC_LP_EINVAL, "k, tau, sigma");
+  if (precision == UC_LP_FP64) return debug_step_t<double>(lp, x, y, x0, y0, k, tau, sigma, x_hat, y_hat, x_next, y_next);
+  if (precision == UC_LP_FP32_MIXED)
+    return debug_step_t<float>(lp, x, y, x0, y0, k, tau, sigma, x_hat, y_hat, x_next, y_next);
+  return fail(UC_LP_ENOTSUP, "precision %d", precision);
+}
+
+extern "C" int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp_info* out) {
+  g_err.clear();
+  int rc = debug_ready(lp);
+  if (rc) return rc;
+  if (!x || !y || !out) return fail(UC_LP_EINVAL, "NULL argument");
+  const HostProblem& P = lp->P;
+  DevMem& D = lp->D;
+  uc_engine* E = lp->eng;
+  hipStream_t s = E->stream;
+  // internal scaled point: x_hat = x / D_c, y_hat = y / D_r (sign of 'L' rows flipped)
+  std::vector<double> dr(P.mi), dc(P.ni), xi(P.ni), yi(P.mi);
+  if (P.mi) HIPOK(hipMemcpyAsync(dr.data(), D.dr, sizeof(double) * P.mi, hipMemcpyDeviceToHost, s));
+  HIPOK(hipMemcpyAsync(dc.data(), D.dc, sizeof(double) * P.ni, hipMemcpyDeviceToHost, s));
+  HIPOK(hipStreamSynchronize(s));
+  for (int j = 0; j < P.ni; ++j) xi[j] = x[P.col_map[j]] / dc[j];
+  for (int i = 0; i < P.mi; ++i) {
+    const int enc = P.row_map[i];
+    yi[i] = (enc >= 0 ? y[enc] : -y[-enc - 1]) / dr[i];
+  }
+  Vecs<double>& V = D.d;
+  for (double* dst : {V.x, V.x0, V.xhat})
+    if ((rc = put_vec<double>(dst, xi.data(), P.ni, s))) return rc;
+  for (double* dst : {V.y, V.y0, V.yhat})
+    if ((rc = put_vec<double>(dst, yi.data(), P.mi, s))) return rc;
+  SlotDev S = make_slot(lp);
+  std::vector<Tile> tl;
+  for (int b = 0; b < S.t_nblk; ++b) tl.push_back({0, b});
+  for (int b = 0; b < S.a_nblk; ++b) tl.push_back({0, b});
+  if ((rc = engine_tables(E, tl.size()))) return rc;
+  HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(E->d_tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+  int zero = 0;
+  HIPOK(hipMemcpyAsync(E->d_ids, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+  launch_kkt(0, E->d_slots, E->d_tiles, S.t_nblk, E->d_tiles + S.t_nblk, S.a_nblk, 1, s);
+  launch_reduce(E->d_slots, E->d_ids, 1, 1, s);
+  double q[kScal];
+  HIPOK(hipMemcpyAsync(q, D.scal, sizeof q, hipMemcpyDeviceToHost, s));
+  HIPOK(hipStreamSynchronize(s));
+  HIPOK(hipGetLastError());
+  uc_lp_info in;
+  std::memset(&in, 0, sizeof in);
+  kkt_from_scalars(lp, q, in);
+  // fixed columns and removed rows contribute nothing to the residuals when
+  // x sits at the fixed value; report violations of those separately
+  for (int32_t j = 0; j < P.n; ++j)
+    if (P.int_col[j] < 0 && x[j] != P.o_lb[j]) in.abs_primal_inf = std::max(in.abs_primal_inf, std::fabs(x[j] - P.o_lb[j]));
+  in.status = lp->status.load();
+  *out = in;
+  return UC_LP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// standalone SpMV and bandwidth probes
+// ---------------------------------------------------------------------------
+
+struct SpmvDev {
+  int *ptr = nullptr, *col = nullptr, *blk = nullptr, *crow = nullptr;
+  void *val = nullptr, *x = nullptr, *y = nullptr, *cval = nullptr;
+  int nblk = 0;
+};
+
+static void spmv_free(SpmvDev& S) {
+  for (void* p : {(void*)S.ptr, (void*)S.col, (void*)S.blk, (void*)S.crow, S.val, S.x, S.y, S.cval})
+    if (p) (void)hipFree(p);
+}
+
+static int spmv_prepare(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const double* v,
+                        int prec, const double* x, SpmvDev& S, hipStream_t s) {
+  std::vector<int> ptr(rp, rp + m + 1), blk;
+  partition_rows(ptr, m, blk);
+  S.nblk = (int)blk.size() - 1;
+  const size_t vs = prec == UC_LP_FP64 ? 8 : 4;
+  HIPOK(hipMalloc(&S.ptr, sizeof(int) * (m + 1)));
+  HIPOK(hipMalloc(&S.col, sizeof(int) * std::max<int64_t>(nnz, 1)));
+  HIPOK(hipMalloc(&S.blk, sizeof(int) * blk.size()));
+  HIPOK(hipMalloc(&S.val, vs * std::max<int64_t>(nnz, 1)));
+  HIPOK(hipMalloc(&S.x, vs * n));
+  HIPOK(hipMalloc(&S.y, vs * m));
+  const int nc = merge_carry_count(m, nnz);
+  HIPOK(hipMalloc(&S.crow, sizeof(int) * std::max(nc, 1)));
+  HIPOK(hipMalloc(&S.cval, vs * std::max(nc, 1)));
+  HIPOK(hipMemcpyAsync(S.ptr, rp, sizeof(int) * (m + 1), hipMemcpyHostToDevice, s));
+  if (nnz) HIPOK(hipMemcpyAsync(S.col, ci, sizeof(int) * nnz, hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(S.blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice, s));
+  if (prec == UC_LP_FP64) {
+    if (nnz) HIPOK(hipMemcpyAsync(S.val, v, 8 * nnz, hipMemcpyHostToDevice, s));
+    if (x) HIPOK(hipMemcpyAsync(S.x, x, 8 * n, hipMemcpyHostToDevice, s));
+    HIPOK(hipStreamSynchronize(s));
+  } else {
+    std::vector<float> fv(v, v + nnz);
+    std::vector<float> fx(n, 0.0f);
+    if (x)
+      for (int j = 0; j < n; ++j) fx[j] = (float)x[j];
+    else
+      for (int j = 0; j < n; ++j) fx[j] = 1.0f;
+    if (nnz) HIPOK(hipMemcpyAsync(S.val, fv.data(), 4 * nnz, hipMemcpyHostToDevice, s));
+    HIPOK(hipMemcpyAsync(S.x, fx.data(), 4 * n, hipMemcpyHostToDevice, s));
+    HIPOK(hipStreamSynchronize(s));
+  }
+  if (prec == UC_LP_FP64 && !x) {
+    std::vector<double> ones(n, 1.0);
+    HIPOK(hipMemcpy(S.x, ones.data(), 8 * n, hipMemcpyHostToDevice));
+  }
+  return UC_LP_OK;
+}
+
+static void spmv_launch(const SpmvDev& S, int32_t m, int64_t nnz, int prec, int algo, hipStream_t s) {
+  if (prec == UC_LP_FP64) {
+    if (algo == UC_LP_SPMV_MERGEPATH)
+      launch_spmv_merge64(S.ptr, S.col, (const double*)S.val, (const double*)S.x, (double*)S.y, m, nnz, S.crow,
+                          (double*)S.cval, s);
+    else
+      launch_spmv64(S.ptr, S.col, (const double*)S.val, (const double*)S.x, (double*)S.y, S.blk, S.nblk, s);
+  } else {
+    if (algo == UC_LP_SPMV_MERGEPATH)
+      launch_spmv_merge32(S.ptr, S.col, (const float*)S.val, (const float*)S.x, (float*)S.y, m, nnz, S.crow,
+                          (float*)S.cval, s);
+    else
+      launch_spmv32(S.ptr, S.col, (const float*)S.val, (const float*)S.x, (float*)S.y, S.blk, S.nblk, s);
+  }
+}
+
+extern "C" int uc_spmv(int device, int32_t m, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                       const int32_t* col_idx, const double* val, const double* x, double* y, int32_t precision,
+                       int32_t algo) {
+  g_err.clear();
+  int rc = validate_csr(m, n, nnz, row_ptr, col_idx, val);
+  if (rc) return rc;
+  if (!x || !y) return fail(UC_LP_EINVAL, "NULL vector");
+  if (precision != UC_LP_FP64 && precision != UC_LP_FP32_MIXED) return fail(UC_LP_ENOTSUP, "precision");
+  if (algo != UC_LP_SPMV_ROWSPLIT && algo != UC_LP_SPMV_MERGEPATH) return fail(UC_LP_ENOTSUP, "algo");
+  HIPOK(hipSetDevice(device));
+  hipStream_t s;
+  HIPOK(hipStreamCreate(&s));
+  SpmvDev S;
+  rc = spmv_prepare(m, n, nnz, row_ptr, col_idx, val, precision, x, S, s);
+  if (rc == UC_LP_OK) {
+    spmv_launch(S, m, nnz, precision, algo, s);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) rc = fail(UC_LP_EHIP, "spmv: %s", hipGetErrorString(e));
+  }
+  if (rc == UC_LP_OK) {
+    if (precision == UC_LP_FP64) {
+      if (hipMemcpy(y, S.y, 8 * m, hipMemcpyDeviceToHost) != hipSuccess) rc = fail(UC_LP_EHIP, "copy y");
+    } else {
+      std::vector<float> fy(m);
+      if (hipMemcpy(fy.data(), S.y, 4 * m, hipMemcpyDeviceToHost) != hipSuccess) rc = fail(UC_LP_EHIP, "copy y");
+      for (int i = 0; i < m; ++i) y[i] = fy[i];
+    }
+  }
+  spmv_free(S);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+extern "C" int uc_spmv_bench(int device, int32_t m, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                             const int32_t* col_idx, const double* val, int32_t precision, int32_t algo,
+                             int32_t copies, int32_t reps, double* us_per_spmv) {
+  g_err.clear();
+  int rc = validate_csr(m, n, nnz, row_ptr, col_idx, val);
+  if (rc) return rc;
+  if (!us_per_spmv || copies < 1 || copies > 64 || reps < 1) return fail(UC_LP_EINVAL, "copies/reps/out");
+  if (precision != UC_LP_FP64 && precision != UC_LP_FP32_MIXED) return fail(UC_LP_ENOTSUP, "precision");
+  if (algo != UC_LP_SPMV_ROWSPLIT && algo != UC_LP_SPMV_MERGEPATH) return fail(UC_LP_ENOTSUP, "algo");
+  HIPOK(hipSetDevice(device));
+  hipStream_t s;
+  HIPOK(hipStreamCreate(&s));
+  std::vector<SpmvDev> C(copies);
+  for (int i = 0; i < copies && rc == UC_LP_OK; ++i)
+    rc = spmv_prepare(m, n, nnz, row_ptr, col_idx, val, precision, nullptr, C[i], s);
+  if (rc == UC_LP_OK) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    for (int i = 0; i < copies; ++i) spmv_launch(C[i], m, nnz, precision, algo, s);  // warm-up
+    (void)hipEventRecord(a, s);
+    for (int r = 0; r < reps; ++r) spmv_launch(C[r % copies], m, nnz, precision, algo, s);
+    (void)hipEventRecord(b, s);
+    hipError_t e = hipEventSynchronize(b);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) rc = fail(UC_LP_EHIP, "spmv bench: %s", hipGetErrorString(e));
+    else *us_per_spmv = 1e3 * ms / reps;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  for (auto& S : C) spmv_free(S);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+extern "C" int uc_copy_bench(int device, size_t bytes, int32_t reps, double* gbps) {
+  g_err.clear();
+  if (!gbps || reps < 1 || bytes < 16) return fail(UC_LP_EINVAL, "bytes/reps/out");
+  HIPOK(hipSetDevice(device));
+  const size_t n4 = bytes / 16;
+  void *a = nullptr, *b = nullptr;
+  HIPOK(hipMalloc(&a, n4 * 16));
+  if (hipMalloc(&b, n4 * 16) != hipSuccess) {
+    (void)hipFree(a);
+    return fail(UC_LP_ENOMEM, "copy buffer");
+  }
+  hipStream_t s;
+  HIPOK(hipStreamCreate(&s));
+  (void)hipMemsetAsync(a, 0, n4 * 16, s);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  launch_copy_kernel((const float4*)a, (float4*)b, (int64_t)n4, s);
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; ++r)
+    launch_copy_kernel((const float4*)((r & 1) ? b : a), (float4*)((r & 1) ? a : b), (int64_t)n4, s);
+  (void)hipEventRecord(e1, s);
+  hipError_t e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  int rc = UC_LP_OK;
+  if (e != hipSuccess) rc = fail(UC_LP_EHIP, "copy bench: %s", hipGetErrorString(e));
+  else *gbps = 2.0 * (double)n4 * 16.0 * reps / (ms * 1e-3) / 1e9;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  return rc;
+}
+
+extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* c, const double* b,
+                                     const double* lb, const double* ub, const double* x0, const double* y0,
+                                     double* x, double* y, uc_lp_info* info) {
+  g_err.clear();
+  (void)base; (void)n_scen; (void)c; (void)b; (void)lb; (void)ub; (void)x0; (void)y0; (void)x; (void)y; (void)info;
+  return fail(UC_LP_ENOTSUP, "scenario batches are not built yet");
+}

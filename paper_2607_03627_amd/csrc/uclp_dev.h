@@ -1,0 +1,132 @@
+// Structures shared by the device kernels (kernels.hip) and the host runtime
+// (uclp.cpp) of libuclp.  Internal; not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace uclp {
+
+// Row blocks: at most kRowsPerBlock rows and kNnzTile entries, except a
+// block holding one row longer than kNnzTile (handled by a block-wide loop).
+constexpr int kThreads = 256;
+constexpr int kRowsPerBlock = 256;
+constexpr int kNnzTile = 2048;
+constexpr int kMaxScen = 16;
+
+// Per-block partial sums written by the KKT check kernels.
+enum RowQ { RQ_RES2 = 0, RQ_BY, RQ_DY2, RQ_DYADX, RQ_DY0, RQ_RESMAX, RQ_N };
+enum ColQ { CQ_DRES2 = 0, CQ_LBUB, CQ_CX, CQ_DX2, CQ_DX0, CQ_N };
+// Per-slot scalars after the final reduction: row quantities then column ones.
+constexpr int kScal = 16;
+
+template <typename T>
+struct Vecs {
+  T* x;      // current iterate (n)
+  T* x0;     // Halpern anchor (n)
+  T* xbar;   // 2 x_hat - x, gathered by the dual half-step (n)
+  T* xhat;   // x_hat, written on check iterations (n)
+  T* y;      // (m)
+  T* y0;
+  T* yhat;
+  const T* c;   // scaled problem data
+  const T* l;
+  const T* u;
+  const T* b;
+  const T* tv;  // scaled values of A^T
+  const T* av;  // scaled values of A
+};
+
+// Everything a kernel needs to know about one resident instance (a "slot").
+// nscen > 1: vectors hold nscen interleaved scenarios (element i of scenario
+// s at i * nscen + s) and c, l, u, b are per scenario; tau/sigma per scenario.
+struct SlotDev {
+  const int* a_ptr;
+  const int* a_col;
+  const int* t_ptr;
+  const int* t_col;
+  const int* a_blk;  // row-block boundaries of A   (a_nblk + 1)
+  const int* t_blk;  // row-block boundaries of A^T (t_nblk + 1)
+  int m, n, m_eq, nscen;
+  int a_nblk, t_nblk;
+  const double* dr;  // D_r (m)
+  const double* dc;  // D_c (n)
+  Vecs<float> f;
+  Vecs<double> d;
+  double* part_a;    // [a_nblk * RQ_N * nscen]
+  double* part_t;    // [t_nblk * CQ_N * nscen]
+  double* scal;      // [kScal * nscen]
+  long long k0[kMaxScen];       // inner iteration index at the epoch start
+  double tau[kMaxScen];
+  double sigma[kMaxScen];
+  int restart[kMaxScen];        // set by the host before the finish kernel
+  int active[kMaxScen];         // 0: scenario frozen (converged)
+};
+
+struct Tile {
+  int slot;
+  int blk;
+};
+
+// ---- launchers (kernels.hip) --------------------------------------------
+// prec: 0 = FP64, 1 = FP32.  All launches go to `s`.
+void launch_primal(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
+                   int jiter, int nscen, hipStream_t s);
+void launch_dual(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
+                 int jiter, int nscen, hipStream_t s);
+void launch_kkt(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles,
+                const Tile* atiles, int natiles, int nscen, hipStream_t s);
+void launch_reduce(const SlotDev* slots, const int* slot_ids, int nslots, int nscen, hipStream_t s);
+void launch_finish(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles,
+                   const Tile* atiles, int natiles, int kk, int nscen, hipStream_t s);
+void launch_promote(const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
+                    int natiles, int nscen, hipStream_t s);
+
+// setup
+void launch_expand_rows(const int* ptr, int m, int* row_of, hipStream_t s);
+void launch_gather_transpose(const int* perm, const int* row_of, const double* val, int64_t nnz,
+                             int* t_col, double* t_val, hipStream_t s);
+size_t radix_sort_temp_bytes(int64_t nnz, int n);
+int radix_sort_pairs(void* temp, size_t temp_bytes, const int* keys_in, int* keys_out,
+                     const int* vals_in, int* vals_out, int64_t nnz, int n, hipStream_t s);
+void launch_iota(int* v, int64_t n, hipStream_t s);
+// op 0: row max |a| D_r D_c ; op 1: row sum of |a| D_r D_c.  Result -> fac[r] = 1/sqrt(v) or 1.
+void launch_scale_factor(int op, const int* ptr, const int* col, const double* val, const double* drow,
+                         const double* dcol, const int* blk, int nblk, int rows, double* fac,
+                         hipStream_t s);
+void launch_mul_inplace(double* d, const double* f, int n, hipStream_t s);
+void launch_scale_values(const int* ptr, const int* col, const double* raw, const double* drow,
+                         const double* dcol, int rows, double* v64, float* v32, hipStream_t s);
+void launch_fill(double* d, double v, int64_t n, hipStream_t s);
+// c_hat = c*dc, l_hat = l/dc, u_hat = u/dc (n); b_hat = b*dr (m); FP32 copies; per scenario.
+void launch_scale_vectors(const double* c, const double* l, const double* u, const double* b,
+                          const double* dc, const double* dr, int n, int m, int nscen,
+                          double* c64, double* l64, double* u64, double* b64, float* c32,
+                          float* l32, float* u32, float* b32, hipStream_t s);
+// plain SpMV y = A x on one matrix (FP64 values and accumulation)
+void launch_spmv64(const int* ptr, const int* col, const double* val, const double* x, double* y,
+                   const int* blk, int nblk, hipStream_t s);
+void launch_spmv32(const int* ptr, const int* col, const float* val, const float* x, float* y,
+                   const int* blk, int nblk, hipStream_t s);
+// merge-path SpMV: carries[] sized merge_carry_count(m, nnz)
+int merge_carry_count(int m, int64_t nnz);
+void launch_spmv_merge64(const int* ptr, const int* col, const double* val, const double* x,
+                         double* y, int m, int64_t nnz, int* carry_row, double* carry_val,
+                         hipStream_t s);
+void launch_spmv_merge32(const int* ptr, const int* col, const float* val, const float* x, float* y,
+                         int m, int64_t nnz, int* carry_row, float* carry_val, hipStream_t s);
+// sum of squares of v (n) into *out (deterministic two-pass); part sized >= 1024
+void launch_norm2(const double* v, int64_t n, double* part, double* out, hipStream_t s);
+// v = w / sqrt(*nrm2)
+void launch_normalize(const double* w, const double* nrm2, double* v, int64_t n, hipStream_t s);
+void launch_hash_vector(double* v, int64_t n, uint32_t seed, hipStream_t s);
+// initial iterates: x = clamp(x_in/dc or 0), y = y_in/dr or 0 (projected), anchors = start
+void launch_init_iterates(const SlotDev* slot, int prec, const double* x_in, const double* y_in,
+                          int n, int m, int m_eq, int nscen, hipStream_t s);
+// x_out = dc * x_hat ; y_out = dr * y_hat (FP64 outputs, per scenario interleaved)
+void launch_unscale(const SlotDev* slot, int prec, double* x_out, double* y_out, int n, int m,
+                    int nscen, hipStream_t s);
+void launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
+void launch_copy_kernel(const float4* a, float4* b, int64_t n4, hipStream_t s);
+
+}  // namespace uclp

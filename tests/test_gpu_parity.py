@@ -1,0 +1,346 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every input is a seeded synthetic instance; every expected value comes from
+oracle/ (at run time, or stored in tests/golden/objectives.json by
+tests/golden/make_golden.py)."""
+
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import pdhg_steps as ps
+from oracle.kkt import kkt
+from oracle.simplex import simplex_solve
+from paper_2607_03627_amd import uclp
+from paper_2607_03627_amd.instances import LP, make_instance
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "objectives.json")))
+U32 = np.finfo(np.float32).eps / 2
+U64 = np.finfo(np.float64).eps / 2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    uclp.load()
+
+
+class Handle:
+    def __init__(self, lp, **opts):
+        self.lp = lp
+        self.h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(**opts))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        uclp.uc_lp_destroy(self.h)
+
+
+def internal_oracle(lp):
+    ip = ps.internal_problem(lp)
+    A = ip.matrix()
+    Dr, Dc, Ah = ps.ruiz_pc_scaling(A)
+    return ip, A, Dr, Dc, Ah
+
+
+# ---------------------------------------------------------------------------
+# a1 presolve + transpose, a2 scaling, a3 operator norm
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,seed", [("tiny", 0), ("medium", 1)])
+def test_presolve_and_transpose_bit_exact(shape, seed):
+    lp = make_instance(shape, seed)
+    say("case", shape, seed)
+    ip = ps.internal_problem(lp)
+    with Handle(lp) as H:
+        d = uclp.uc_lp_internal_dims(H.h)
+        assert (d["m"], d["n"], d["nnz"], d["m_eq"]) == (ip.m, ip.n, len(ip.col_idx), ip.m_eq)
+        assert np.array_equal(d["row_map"], ip.row_map) and np.array_equal(d["col_map"], ip.col_map)
+        tp, tc, tv = uclp.uc_lp_get_transpose(H.h, d["n"], d["nnz"])
+    rp, rc, rv = ps.csr_transpose(ip.row_ptr, ip.col_idx, ip.val, ip.n)
+    assert np.array_equal(tp, rp) and np.array_equal(tc, rc)
+    assert np.array_equal(tv, rv)
+
+
+@pytest.mark.parametrize("shape,seed", [("tiny", 0), ("medium", 0)])
+def test_scaling_and_operator_norm(shape, seed):
+    lp = make_instance(shape, seed)
+    say("case", shape, seed)
+    ip, A, Dr, Dc, Ah = internal_oracle(lp)
+    with Handle(lp) as H:
+        dr, dc, nrm = uclp.uc_lp_get_scaling(H.h, ip.m, ip.n)
+    assert np.max(np.abs(dr / Dr - 1)) <= 1e-12
+    assert np.max(np.abs(dc / Dc - 1)) <= 1e-12
+    true = ps.spectral_norm(Ah)
+    # power iteration approaches the largest singular value from below
+    assert nrm <= true * (1 + 1e-10)
+    assert nrm >= 0.97 * true
+    assert true <= 1 + 1e-12      # the Pock-Chambolle bound
+
+
+# ---------------------------------------------------------------------------
+# a4-a6: one PDHG step with the Halpern update
+# ---------------------------------------------------------------------------
+
+def step_inputs(ip, Dc, Dr, seed):
+    rng = np.random.default_rng(seed)
+    l, u = ip.l / Dc, ip.u / Dc
+    x = np.clip(rng.normal(0, 1, ip.n), l, u)
+    x0 = np.clip(rng.normal(0, 1, ip.n), l, u)
+    y = rng.normal(0, 1, ip.m)
+    y[ip.m_eq:] = np.abs(y[ip.m_eq:])
+    y0 = rng.normal(0, 1, ip.m)
+    y0[ip.m_eq:] = np.abs(y0[ip.m_eq:])
+    return x, y, x0, y0
+
+
+@pytest.mark.parametrize("shape,seed", [("tiny", 1), ("medium", 2)])
+@pytest.mark.parametrize("prec", [uclp.UC_LP_FP64, uclp.UC_LP_FP32_MIXED])
+def test_pdhg_step_elementwise(shape, seed, prec):
+    lp = make_instance(shape, seed)
+    say("case", shape, seed, prec)
+    ip, A, Dr, Dc, Ah = internal_oracle(lp)
+    c, b, l, u = ip.c * Dc, ip.b * Dr, ip.l / Dc, ip.u / Dc
+    x, y, x0, y0 = step_inputs(ip, Dc, Dr, seed)
+    tau, sigma, k = 0.37, 1.9, 5
+    with Handle(lp) as H:
+        xh, yh, xn, yn = uclp.uc_lp_debug_step(H.h, prec, x, y, x0, y0, k, tau, sigma)
+    if prec == uclp.UC_LP_FP32_MIXED:
+        # the FP32 path works on FP32-rounded inputs and data
+        f = lambda v: v.astype(np.float32).astype(np.float64)
+        x, y, x0, y0, c, b, l, u = map(f, (x, y, x0, y0, c, b, l, u))
+        Ah = sp.csr_matrix((f(Ah.data), Ah.indices, Ah.indptr), shape=Ah.shape)
+    rx, ry = ps.pdhg_step(Ah, c, b, l, u, ip.m_eq, x, y, tau, sigma)
+    rxn = ps.halpern_update(x, rx, x0, k)
+    ryn = ps.halpern_update(y, ry, y0, k)
+    absA = abs(Ah)
+    rowlen = np.diff(Ah.indptr).max()
+    if prec == uclp.UC_LP_FP64:
+        # scaled data differ from the oracle's in the last bits of D_r, D_c
+        ex = 1e-12 * (np.abs(x) + tau * (np.abs(c) + absA.T @ np.abs(y)) + 1)
+        ey = 1e-12 * (np.abs(y) + sigma * (np.abs(b) + absA @ (2 * np.abs(rx) + np.abs(x))) + 1)
+    else:
+        g = (rowlen + 4) * U32
+        ex = 4 * g * (np.abs(x) + tau * (np.abs(c) + absA.T @ np.abs(y))) + 1e-30
+        exb = 2 * ex + U32 * (2 * np.abs(rx) + np.abs(x))
+        ey = 4 * g * (np.abs(y) + sigma * (np.abs(b) + absA @ (2 * np.abs(rx) + np.abs(x)))) \
+            + sigma * (absA @ exb) + 1e-30
+    assert np.all(np.abs(xh - rx) <= ex)
+    assert np.all(np.abs(yh - ry) <= ey)
+    w = (k + 1) / (k + 2)
+    assert np.all(np.abs(xn - rxn) <= 2 * w * ex + 4 * U32 * (np.abs(rxn) + np.abs(x) + np.abs(x0)) + 1e-30)
+    assert np.all(np.abs(yn - ryn) <= 2 * w * ey + 4 * U32 * (np.abs(ryn) + np.abs(y) + np.abs(y0)) + 1e-30)
+    # projections hold exactly
+    assert np.all(xh >= l) and np.all(xh <= u) and np.all(yh[ip.m_eq:] >= 0)
+
+
+# ---------------------------------------------------------------------------
+# a7: the FP64 KKT check kernels
+# ---------------------------------------------------------------------------
+
+def test_kkt_kernels_match_oracle():
+    lp = make_instance("tiny", 0)
+    say("case tiny 0 kkt")
+    res = simplex_solve(lp)
+    rng = np.random.default_rng(3)
+    with Handle(lp) as H:
+        for scale in (0.0, 1e-6, 1e-2):
+            x = np.clip(res.x + scale * rng.normal(size=lp.n), lp.lb, lp.ub)
+            fixed = lp.lb == lp.ub
+            x[fixed] = lp.lb[fixed]
+            y = res.y + scale * rng.normal(size=lp.m)
+            g = uclp.uc_lp_eval_kkt(H.h, x, y)
+            o = kkt(lp, x, y)
+            nb, nc = np.linalg.norm(lp.b), np.linalg.norm(lp.c)
+            A = sp.csr_matrix((lp.val, lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n))
+            sp_scale = np.linalg.norm(abs(A) @ np.abs(x) + np.abs(lp.b))
+            sd_scale = np.linalg.norm(abs(A).T @ np.abs(y) + np.abs(lp.c))
+            assert abs(g.rel_primal - o.rel_p) <= 1e-12 * (1 + sp_scale) / (1 + nb)
+            assert abs(g.rel_dual - o.rel_d) <= 1e-12 * (1 + sd_scale) / (1 + nc)
+            objscale = np.abs(lp.c) @ np.abs(x) + np.abs(lp.b) @ np.abs(y) + \
+                np.nan_to_num(np.abs(lp.lb) + np.abs(lp.ub), posinf=0) @ (abs(A).T @ np.abs(y) + np.abs(lp.c))
+            assert abs(g.pobj - o.pobj) <= 1e-12 * objscale
+            assert abs(g.dobj - o.dobj) <= 1e-12 * objscale
+            assert abs(g.abs_primal_inf - o.max_primal_violation) <= 1e-12 * (1 + np.max(abs(A) @ np.abs(x)))
+
+
+# ---------------------------------------------------------------------------
+# standalone SpMV kernels on adversarial row-length mixes
+# ---------------------------------------------------------------------------
+
+def adversarial(kind, rng):
+    if kind == "uc":
+        lp = make_instance("medium", 0)
+        return sp.csr_matrix((lp.val, lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n))
+    if kind == "empty_rows":
+        A = sp.random(3000, 2000, density=0.002, random_state=1, format="lil")
+        A[::7, :] = 0
+        return A.tocsr()
+    if kind == "one_long_row":
+        A = sp.random(5000, 120000, density=0.00002, random_state=2, format="lil")
+        A[1234, :] = rng.normal(size=120000)
+        return A.tocsr()
+    if kind == "length_one":
+        n = 70001
+        return sp.csr_matrix((rng.normal(size=n), rng.integers(0, 5000, n), np.arange(n + 1)), shape=(n, 5000))
+    if kind == "ragged":
+        lens = rng.integers(0, 3000, 400)
+        lens[::5] = 0
+        rows = np.repeat(np.arange(400), lens)
+        cols = np.concatenate([rng.choice(4000, L, replace=False) for L in lens])
+        A = sp.csr_matrix((rng.normal(size=len(rows)), (rows, cols)), shape=(400, 4000))
+        return A
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", ["uc", "empty_rows", "one_long_row", "length_one", "ragged"])
+@pytest.mark.parametrize("algo", [uclp.UC_LP_SPMV_ROWSPLIT, uclp.UC_LP_SPMV_MERGEPATH])
+def test_spmv_kernels(kind, algo):
+    rng = np.random.default_rng(11)
+    A = adversarial(kind, rng)
+    A.sort_indices()
+    A.sum_duplicates()
+    say("case spmv", kind, algo, A.shape, A.nnz)
+    x = rng.normal(size=A.shape[1])
+    ref = ps.csr_matvec(A.indptr, A.indices, A.data, x)
+    bound = abs(A) @ np.abs(x)
+    k = max(int(np.diff(A.indptr).max()), 1)
+    y64 = uclp.uc_spmv(A.shape[0], A.shape[1], A.indptr, A.indices, A.data, x, uclp.UC_LP_FP64, algo)
+    assert np.all(np.abs(y64 - ref) <= 2 * k * U64 * bound + 1e-300)
+    y32 = uclp.uc_spmv(A.shape[0], A.shape[1], A.indptr, A.indices, A.data, x, uclp.UC_LP_FP32_MIXED, algo)
+    # inputs rounded to FP32 (relative 2u each), then k-term FP32 accumulation
+    assert np.all(np.abs(y32 - ref) <= (k + 4) * U32 * 1.01 * bound + 1e-30)
+
+
+# ---------------------------------------------------------------------------
+# whole solves: objective against the oracle, KKT recomputed by the oracle
+# ---------------------------------------------------------------------------
+
+def solve(lp, **opts):
+    x, y, info = uclp.solve(lp, uclp.uc_lp_opts_default(**opts), timeout_s=300)
+    return x, y, info
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_tiny_fp64_matches_simplex_oracle(seed):
+    lp = make_instance("tiny", seed)
+    say("case tiny fp64", seed)
+    z = GOLDEN[f"tiny/{seed}"]["obj"]
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP64, eps_rel=1e-8)
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    k = kkt(lp, x, y)
+    assert k.rel_kkt <= 1e-8 * 1.001
+    assert abs(k.rel_kkt - info["rel_kkt"]) <= 1e-10
+    assert abs(k.pobj - z) <= 1e-6 * abs(z)
+    assert np.all(x >= lp.lb) and np.all(x <= lp.ub)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_tiny_fp32_modes(seed):
+    lp = make_instance("tiny", seed)
+    say("case tiny fp32", seed)
+    z = GOLDEN[f"tiny/{seed}"]["obj"]
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP32_MIXED)
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    k = kkt(lp, x, y)
+    assert k.rel_kkt <= 1e-4
+    # a relative gap below 1e-4 bounds the objective error to the same order
+    assert abs(k.pobj - z) <= 1e-3 * abs(z)
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP32_MIXED_POLISH)
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    k = kkt(lp, x, y)
+    assert k.rel_kkt <= 1e-8 * 1.001
+    assert abs(k.pobj - z) <= 1e-6 * abs(z)
+    assert info["iters_fp64"] < info["iters"]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_medium_polish_matches_highs_oracle(seed):
+    lp = make_instance("medium", seed)
+    say("case medium polish", seed)
+    z = GOLDEN[f"medium/{seed}"]["obj"]
+    t = time.time()
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP32_MIXED_POLISH)
+    say("  ", info["status_name"], info["iters"], info["iters_fp64"], info["t_total_s"], time.time() - t)
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    k = kkt(lp, x, y)
+    assert k.rel_kkt <= 1e-8 * 1.001
+    assert abs(k.pobj - z) <= 1e-6 * abs(z)
+    assert info["t_to_eps_s"] > 0 and info["rel_kkt_at_eps"] <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# boundary behaviour
+# ---------------------------------------------------------------------------
+
+def test_status_cancel_and_errors():
+    lp = make_instance("medium", 0)
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-12))
+    try:
+        with pytest.raises(uclp.UcLpError) as e:
+            uclp.uc_lp_get_solution(h, lp.n, lp.m)
+        assert e.value.code == uclp.UC_LP_ESTATE
+        uclp.uc_lp_solve(h)
+        with pytest.raises(uclp.UcLpError) as e:
+            uclp.uc_lp_solve(h)
+        assert e.value.code == uclp.UC_LP_ESTATE
+        time.sleep(0.3)
+        assert uclp.uc_lp_status(h).status == uclp.UC_LP_RUNNING
+        uclp.uc_lp_cancel(h)
+        assert uclp.uc_lp_wait(h, 30)
+        info = uclp.uc_lp_status(h)
+        assert info.status == uclp.UC_LP_CANCELLED and info.iters > 0
+        x, y = uclp.uc_lp_get_solution(h, lp.n, lp.m)
+        assert np.all(np.isfinite(x)) and np.all(np.isfinite(y))
+    finally:
+        uclp.uc_lp_destroy(h)
+
+
+def test_iteration_limit_and_warm_start():
+    lp = make_instance("tiny", 4)
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP64, iter_limit=128, eps_rel=1e-12)
+    assert info["status"] == uclp.UC_LP_ITER_LIMIT and info["iters"] == 128
+    # warm start from a converged point stops at the first check
+    xs, ys, info = solve(lp, precision=uclp.UC_LP_FP64, eps_rel=1e-7)
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-6))
+    try:
+        uclp.uc_lp_solve(h, xs, ys)
+        uclp.uc_lp_wait(h, 60)
+        assert uclp.uc_lp_status(h).iters == 64
+    finally:
+        uclp.uc_lp_destroy(h)
+
+
+def test_update_data_and_infeasible_empty_row():
+    lp = make_instance("tiny", 5)
+    z = GOLDEN["tiny/5"]["obj"]
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-8))
+    try:
+        uclp.uc_lp_update_data(h, c=2.0 * lp.c)
+        uclp.uc_lp_solve(h)
+        uclp.uc_lp_wait(h, 120)
+        info = uclp.uc_lp_status(h)
+        assert info.status == uclp.UC_LP_OPTIMAL
+        assert abs(info.pobj - 2 * z) <= 1e-6 * 2 * z
+    finally:
+        uclp.uc_lp_destroy(h)
+    # an empty 'E' row with a non-zero right-hand side is infeasible
+    A = sp.csr_matrix((lp.val, lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n))
+    A = sp.vstack([A, sp.csr_matrix((1, lp.n))]).tocsr()
+    bad = LP(m=lp.m + 1, n=lp.n, row_ptr=A.indptr, col_idx=A.indices, val=A.data, c=lp.c,
+             b=np.append(lp.b, 1.0), sense=np.append(lp.sense, ord("E")).astype(np.uint8), lb=lp.lb, ub=lp.ub)
+    x, y, info = solve(bad)
+    assert info["status"] == uclp.UC_LP_INFEASIBLE

@@ -1,0 +1,102 @@
+"""CPU-side checks of the C ABI library: it loads without a GPU, exports
+every entry point declared in include/uc_lp.h, and rejects malformed input
+before touching any device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2607_03627_amd import uclp
+from paper_2607_03627_amd.instances import LP, make_instance
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "uc_lp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(uc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("uc_lp_create", "uc_lp_solve", "uc_lp_status", "uc_lp_cancel", "uc_lp_get_solution",
+                 "uc_lp_destroy", "uc_engine_create", "uc_lp_solve_scenarios"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = uclp.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(declared_functions()) == sorted(uclp.EXPORTS)
+
+
+def test_binding_structs_match_header_layout():
+    # the two structs are passed by pointer; their sizes must agree with the C layout
+    assert ctypes.sizeof(uclp.uc_lp_opts) == 4 * 4 + 8 + 5 * 8 + 4 * 4
+    o = uclp.uc_lp_opts_default()
+    assert o.precision == uclp.UC_LP_FP32_MIXED_POLISH and o.kkt_every == 64
+    assert o.iter_limit == 100000 and o.eps_rel == 1e-4 and o.eps_polish == 1e-8
+
+
+def small():
+    lp = make_instance("tiny", 0, n_periods=2)
+    return lp
+
+
+def mutated(**kw):
+    lp = small()
+    fields = dict(m=lp.m, n=lp.n, row_ptr=lp.row_ptr.copy(), col_idx=lp.col_idx.copy(),
+                  val=lp.val.copy(), c=lp.c.copy(), b=lp.b.copy(), sense=lp.sense.copy(),
+                  lb=lp.lb.copy(), ub=lp.ub.copy())
+    for k, f in kw.items():
+        fields[k] = f(fields[k])
+    return LP(**fields)
+
+
+def _set(i, v):
+    def f(a):
+        a = a.copy()
+        a[i] = v
+        return a
+    return f
+
+
+@pytest.mark.parametrize("case", [
+    dict(row_ptr=_set(0, 1)),
+    dict(row_ptr=_set(5, 10**6)),
+    dict(col_idx=_set(3, -1)),
+    dict(col_idx=lambda a: np.where(np.arange(len(a)) == 1, a[0], a)),   # duplicate in row 0
+    dict(val=_set(2, np.nan)),
+    dict(c=_set(0, np.inf)),
+    dict(b=_set(0, np.nan)),
+    dict(lb=_set(0, 5.0), ub=_set(0, 1.0)),
+    dict(sense=_set(0, ord("X"))),
+    dict(lb=_set(0, np.inf)),
+])
+def test_create_rejects_malformed_input_without_a_device(case):
+    lp = mutated(**case)
+    rc, h = uclp.uc_lp_create(lp, raw=True)
+    assert rc == uclp.UC_LP_EINVAL and h is None
+    assert uclp.uc_lp_last_error() != ""
+
+
+def test_bad_options_are_rejected():
+    lp = small()
+    for kw, code in ((dict(precision=7), uclp.UC_LP_ENOTSUP), (dict(kkt_every=0), uclp.UC_LP_EINVAL),
+                     (dict(step_scale=1.5), uclp.UC_LP_EINVAL), (dict(eps_rel=-1.0), uclp.UC_LP_EINVAL)):
+        rc, h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(**kw), raw=True)
+        assert rc == code and h is None
+
+
+def test_null_handles_are_safe():
+    lib = uclp.load()
+    lib.uc_lp_destroy(None)
+    lib.uc_engine_destroy(None)
+    assert lib.uc_lp_cancel(None) == uclp.UC_LP_EINVAL
+    assert lib.uc_lp_status(None, None) == uclp.UC_LP_EINVAL
