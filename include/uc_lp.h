@@ -88,16 +88,26 @@ typedef struct {
   int32_t power_iters;   /* power-iteration steps for ||A||_2, default 64      */
   int64_t iter_limit;    /* total iteration limit, default 100000              */
   double eps_rel;        /* relative KKT stopping tolerance, default 1e-4      */
-  double eps_abs_feas;   /* absolute feasibility tolerance (inf-norm of the
-                            unscaled row violation) also required, default 1e-5;
-                            0 disables                                          */
+  double eps_abs_feas;   /* optional extra stopping requirement: inf-norm of
+                            the unscaled row violation <= this; default 0 (off).
+                            The paper's PDHG runs set 1e-5 (Sec. II-D).        */
   double eps_polish;     /* relative KKT target of the FP64 polish, 1e-8       */
   double time_limit_s;   /* wall-clock limit of one solve, default 3600        */
   double step_scale;     /* eta = step_scale / ||A_hat||_2, default 0.99       */
-  int32_t spmv_algo;     /* uc_lp_spmv_algo, default UC_LP_SPMV_ROWSPLIT       */
+  int32_t spmv_algo;     /* uc_lp_spmv_algo; the PDHG half-steps support
+                            UC_LP_SPMV_ROWSPLIT only (ENOTSUP otherwise)       */
   int32_t verbose;       /* 0 = silent, 1 = one line per check on stderr       */
-  int32_t timing;        /* 1 = time sampled kernel launches with HIP events   */
-  int32_t reserved;
+  int32_t timing;        /* 1 = time the first primal and dual launch of each
+                            check interval with dispatch-attached HIP events   */
+  int32_t restart_to_current; /* 0: restart at the PDHG output T(z) (default);
+                            1: restart at the current Halpern iterate z         */
+  /* adaptive restart on the fixed-point residual r = ||z - T(z)||_P, checked
+     every kkt_every iterations (Applegate et al. 2021; Lu & Yang 2024) */
+  double restart_sufficient;  /* restart if r <= this * r(restart start), 0.2 */
+  double restart_necessary;   /* ... or r <= this * r(start) and r grew, 0.8  */
+  double restart_artificial;  /* ... or inner iterations >= this * total, 0.36 */
+  double pw_smoothing;   /* primal weight: log w <- s log(dy/dx) + (1-s) log w
+                            at each restart, default 0.5; 0 keeps w fixed      */
 } uc_lp_opts;
 
 typedef struct {
@@ -117,6 +127,7 @@ typedef struct {
   double abs_primal_inf;   /* inf-norm of unscaled row violations             */
   double pobj_at_eps;      /* primal objective at the eps_rel milestone       */
   double rel_kkt_at_eps;
+  int64_t iters_at_eps;    /* iterations at the eps_rel milestone             */
   double norm_a_est;       /* power-iteration estimate of ||A_hat||_2         */
   double omega;            /* current primal weight                           */
   double primal_kernel_us; /* mean duration of timed primal half-step kernels  */

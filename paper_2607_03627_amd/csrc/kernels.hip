@@ -15,6 +15,7 @@
 // tile index is remapped so that each XCD walks one contiguous eighth of the
 // tiles, which keeps the gathered vector window of that range in its own L2.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 #include <math.h>
@@ -131,6 +132,47 @@ __device__ inline bool block_row_sum(const int* __restrict__ ptr, int r0, int r1
 // PDHG half-steps (one scenario per slot)
 // ---------------------------------------------------------------------------
 
+// Staging of one row block's products val[k] * g[col[k]] into LDS.  Every
+// thread first issues all of its (at most kItems) column-index and value
+// loads, then all gathers, so each wave keeps many independent loads in
+// flight before the block barrier.
+constexpr int kItems = kNnzTile / kThreads;
+
+template <typename T, typename G>
+__device__ inline void stage_products(const int* __restrict__ col, const T* __restrict__ val,
+                                      const G* __restrict__ g, int nz, T* lds) {
+  int c[kItems];
+  T v[kItems];
+#pragma unroll
+  for (int u = 0; u < kItems; ++u) {
+    const int k = threadIdx.x + u * kThreads;
+    if (k < nz) {
+      c[u] = col[k];
+      v[u] = val[k];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kItems; ++u) {
+    const int k = threadIdx.x + u * kThreads;
+    if (k < nz) lds[k] = v[u] * (T)g[c[u]];
+  }
+}
+
+// Sum of one long row (above kNnzTile entries) by the whole block; valid in thread 0.
+template <typename T, typename G>
+__device__ inline T long_row_sum(const int* __restrict__ col, const T* __restrict__ val,
+                                 const G* __restrict__ g, int nz, T* red) {
+  T s = 0;
+  for (int k = threadIdx.x; k < nz; k += kThreads) s += val[k] * (T)g[col[k]];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  T t = red[0];
+  for (int w = 1; w < kThreads / 64; ++w) t += red[w];
+  return t;
+}
+
 // Primal half-step over the rows of A^T (= columns j of A):
 //   g = c_j - (A^T y)_j ; x_hat = clamp(x - tau g, l, u) ; xbar = 2 x_hat - x
 //   non-check: x <- w xbar + (1 - w) x0,  w = (k + 1)/(k + 2), 1 - w = 1/(k + 2)
@@ -148,17 +190,35 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   const Vecs<T>& V = vecs<T>(S);
   const int r0 = S.t_blk[tl.blk];
   const int r1 = S.t_blk[tl.blk + 1];
-  const int* __restrict__ col = S.t_col;
-  const T* __restrict__ val = V.tv;
-  const T* __restrict__ y = V.y;
-  int j;
-  T s;
-  if (!block_row_sum<T>(S.t_ptr, r0, r1, lds, red, [&](int k) { return val[k] * y[col[k]]; }, j, s))
-    return;
+  const int* __restrict__ ptr = S.t_ptr;
+  const int k0 = ptr[r0];
+  const int nz = ptr[r1] - k0;
+  const int j = r0 + threadIdx.x;
+  const bool own = j < r1;
+  // epilogue operands first, so their loads overlap the gathers
+  int a = 0, b = 0;
+  T c = 0, l = 0, u = 0, x = 0, xa = 0;
+  if (own) {
+    a = ptr[j] - k0;
+    b = ptr[j + 1] - k0;
+    c = V.c[j];
+    l = V.l[j];
+    u = V.u[j];
+    x = V.x[j];
+    if (!CHECK) xa = V.x0[j];
+  }
+  T s = 0;
+  if (nz <= kNnzTile) {
+    stage_products<T, T>(S.t_col + k0, V.tv + k0, V.y, nz, lds);
+    __syncthreads();
+    if (!own) return;
+    for (int k = a; k < b; ++k) s += lds[k];
+  } else {
+    s = long_row_sum<T, T>(S.t_col + k0, V.tv + k0, V.y, nz, red);
+    if (threadIdx.x != 0) return;
+  }
   const T tau = (T)S.tau[0];
-  const T g = V.c[j] - s;
-  const T x = V.x[j];
-  const T xh = clampv<T>(x - tau * g, V.l[j], V.u[j]);
+  const T xh = clampv<T>(x - tau * (c - s), l, u);
   const T xb = (T)2 * xh - x;
   V.xbar[j] = xb;
   if (CHECK) {
@@ -167,7 +227,7 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
     const double kk = (double)(S.k0[0] + jiter);
     const T w = (T)((kk + 1.0) / (kk + 2.0));
     const T wa = (T)(1.0 / (kk + 2.0));
-    V.x[j] = w * xb + wa * V.x0[j];
+    V.x[j] = w * xb + wa * xa;
   }
 }
 
@@ -187,16 +247,32 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
   const Vecs<T>& V = vecs<T>(S);
   const int r0 = S.a_blk[tl.blk];
   const int r1 = S.a_blk[tl.blk + 1];
-  const int* __restrict__ col = S.a_col;
-  const T* __restrict__ val = V.av;
-  const T* __restrict__ xb = V.xbar;
-  int i;
-  T s;
-  if (!block_row_sum<T>(S.a_ptr, r0, r1, lds, red, [&](int k) { return val[k] * xb[col[k]]; }, i, s))
-    return;
+  const int* __restrict__ ptr = S.a_ptr;
+  const int k0 = ptr[r0];
+  const int nz = ptr[r1] - k0;
+  const int i = r0 + threadIdx.x;
+  const bool own = i < r1;
+  int a = 0, b = 0;
+  T bi = 0, y = 0, ya = 0;
+  if (own) {
+    a = ptr[i] - k0;
+    b = ptr[i + 1] - k0;
+    bi = V.b[i];
+    y = V.y[i];
+    if (!CHECK) ya = V.y0[i];
+  }
+  T s = 0;
+  if (nz <= kNnzTile) {
+    stage_products<T, T>(S.a_col + k0, V.av + k0, V.xbar, nz, lds);
+    __syncthreads();
+    if (!own) return;
+    for (int k = a; k < b; ++k) s += lds[k];
+  } else {
+    s = long_row_sum<T, T>(S.a_col + k0, V.av + k0, V.xbar, nz, red);
+    if (threadIdx.x != 0) return;
+  }
   const T sigma = (T)S.sigma[0];
-  const T y = V.y[i];
-  T yh = y + sigma * (V.b[i] - s);
+  T yh = y + sigma * (bi - s);
   if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
   if (CHECK) {
     V.yhat[i] = yh;
@@ -204,7 +280,7 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
     const double kk = (double)(S.k0[0] + jiter);
     const T w = (T)((kk + 1.0) / (kk + 2.0));
     const T wa = (T)(1.0 / (kk + 2.0));
-    V.y[i] = w * ((T)2 * yh - y) + wa * V.y0[i];
+    V.y[i] = w * ((T)2 * yh - y) + wa * ya;
   }
 }
 
@@ -232,8 +308,8 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict
   const int k0 = ptr[r0];
   const int k1 = ptr[r1];
   const int nz = k1 - k0;
-  double q[RQ_N] = {0, 0, 0, 0, 0, 0};
-  const bool is_max[RQ_N] = {false, false, false, false, false, true};
+  double q[RQ_N] = {0, 0, 0, 0, 0, 0, 0};
+  const bool is_max[RQ_N] = {false, false, false, false, false, false, true};
   int row = -1;
   double s1 = 0, s2 = 0;
   if (nz <= kNnzTile) {
@@ -292,6 +368,9 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict
     q[RQ_DY2] = dy * dy;
     q[RQ_DYADX] = dy * s2;
     q[RQ_DY0] = d0 * d0;
+    // dual sign violation of an inequality row, unscaled (zero for projected iterates)
+    const double yneg = row >= S.m_eq && yh < 0.0 ? yh * S.dr[row] : 0.0;
+    q[RQ_YNEG2] = yneg * yneg;
     q[RQ_RESMAX] = fabs(ru);
   }
   __syncthreads();
@@ -385,7 +464,8 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const SlotDev* __restrict__
   }
 }
 
-// After a check: either restart at (x_hat, y_hat) or take the Halpern step.
+// After a check: restart at (x_hat, y_hat) (flag 1), take the Halpern step and
+// restart there (flag 2), or take the Halpern step (flag 0).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_finish_x(const SlotDev* __restrict__ slots,
                                                        const Tile* __restrict__ tiles, int ntiles,
@@ -397,7 +477,7 @@ __global__ __launch_bounds__(kThreads) void k_finish_x(const SlotDev* __restrict
   const Vecs<T>& V = vecs<T>(S);
   const int j = S.t_blk[tl.blk] + threadIdx.x;
   if (j >= S.t_blk[tl.blk + 1]) return;
-  if (S.restart[0]) {
+  if (S.restart[0] == 1) {
     const T xh = V.xhat[j];
     V.x[j] = xh;
     V.x0[j] = xh;
@@ -405,7 +485,9 @@ __global__ __launch_bounds__(kThreads) void k_finish_x(const SlotDev* __restrict
     const double k = (double)(S.k0[0] + kk);
     const T w = (T)((k + 1.0) / (k + 2.0));
     const T wa = (T)(1.0 / (k + 2.0));
-    V.x[j] = w * V.xbar[j] + wa * V.x0[j];
+    const T xn = w * V.xbar[j] + wa * V.x0[j];
+    V.x[j] = xn;
+    if (S.restart[0] == 2) V.x0[j] = xn;
   }
 }
 
@@ -420,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void k_finish_y(const SlotDev* __restrict
   const Vecs<T>& V = vecs<T>(S);
   const int i = S.a_blk[tl.blk] + threadIdx.x;
   if (i >= S.a_blk[tl.blk + 1]) return;
-  if (S.restart[0]) {
+  if (S.restart[0] == 1) {
     const T yh = V.yhat[i];
     V.y[i] = yh;
     V.y0[i] = yh;
@@ -428,7 +510,9 @@ __global__ __launch_bounds__(kThreads) void k_finish_y(const SlotDev* __restrict
     const double k = (double)(S.k0[0] + kk);
     const T w = (T)((k + 1.0) / (k + 2.0));
     const T wa = (T)(1.0 / (k + 2.0));
-    V.y[i] = w * ((T)2 * V.yhat[i] - V.y[i]) + wa * V.y0[i];
+    const T yn = w * ((T)2 * V.yhat[i] - V.y[i]) + wa * V.y0[i];
+    V.y[i] = yn;
+    if (S.restart[0] == 2) V.y0[i] = yn;
   }
 }
 
@@ -459,6 +543,304 @@ __global__ __launch_bounds__(kThreads) void k_promote_y(const SlotDev* __restric
   S.d.y[i] = v;
   S.d.y0[i] = v;
   S.d.yhat[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// scenario batches: several right-hand sides / costs / bounds over one matrix
+// ---------------------------------------------------------------------------
+// Vectors are interleaved (element j of scenario s at j * nscen + s).  A
+// workgroup stages the column indices and values of its row block in LDS
+// once; lane s of each 16-lane group then walks one row for scenario s, so
+// the 16 scenarios of a gathered element form one contiguous 64-byte (FP32)
+// access, and one read of the matrix serves every scenario.
+constexpr int kLanes = 16;                       // lanes per row (>= nscen)
+constexpr int kRowsPerPass = kThreads / kLanes;  // rows per pass of the block
+
+template <typename T>
+__device__ inline void stage_entries(const int* __restrict__ col, const T* __restrict__ val, int nz,
+                                     int* lc, T* lv) {
+  for (int k = threadIdx.x; k < nz; k += kThreads) {
+    lc[k] = col[k];
+    lv[k] = val[k];
+  }
+}
+
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(kThreads) void k_primal_ms(const SlotDev* __restrict__ slots,
+                                                        const Tile* __restrict__ tiles, int ntiles,
+                                                        int jiter) {
+  __shared__ int lc[kNnzTile];
+  __shared__ T lv[kNnzTile];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const Vecs<T>& V = vecs<T>(S);
+  const int r0 = S.t_blk[tl.blk], r1 = S.t_blk[tl.blk + 1];
+  const int* __restrict__ ptr = S.t_ptr;
+  const int k0 = ptr[r0];
+  const int nz = ptr[r1] - k0;
+  const bool staged = nz <= kNnzTile;
+  if (staged) stage_entries<T>(S.t_col + k0, V.tv + k0, nz, lc, lv);
+  __syncthreads();
+  const int ns = S.nscen;
+  const int sc = threadIdx.x % kLanes;
+  if (sc >= ns || !S.active[sc]) return;
+  const T tau = (T)S.tau[sc];
+  const double kk = (double)(S.k0[sc] + jiter);
+  const T w = (T)((kk + 1.0) / (kk + 2.0));
+  const T wa = (T)(1.0 / (kk + 2.0));
+  const T* __restrict__ y = V.y;
+  for (int j = r0 + threadIdx.x / kLanes; j < r1; j += kRowsPerPass) {
+    const int a = ptr[j], b = ptr[j + 1];
+    T acc = 0;
+    if (staged)
+      for (int k = a - k0; k < b - k0; ++k) acc += lv[k] * y[(size_t)lc[k] * ns + sc];
+    else
+      for (int k = a; k < b; ++k) acc += V.tv[k] * y[(size_t)S.t_col[k] * ns + sc];
+    const size_t e = (size_t)j * ns + sc;
+    const T x = V.x[e];
+    const T xh = clampv<T>(x - tau * (V.c[e] - acc), V.l[e], V.u[e]);
+    const T xb = (T)2 * xh - x;
+    V.xbar[e] = xb;
+    if (CHECK) V.xhat[e] = xh;
+    else V.x[e] = w * xb + wa * V.x0[e];
+  }
+}
+
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(kThreads) void k_dual_ms(const SlotDev* __restrict__ slots,
+                                                      const Tile* __restrict__ tiles, int ntiles,
+                                                      int jiter) {
+  __shared__ int lc[kNnzTile];
+  __shared__ T lv[kNnzTile];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const Vecs<T>& V = vecs<T>(S);
+  const int r0 = S.a_blk[tl.blk], r1 = S.a_blk[tl.blk + 1];
+  const int* __restrict__ ptr = S.a_ptr;
+  const int k0 = ptr[r0];
+  const int nz = ptr[r1] - k0;
+  const bool staged = nz <= kNnzTile;
+  if (staged) stage_entries<T>(S.a_col + k0, V.av + k0, nz, lc, lv);
+  __syncthreads();
+  const int ns = S.nscen;
+  const int sc = threadIdx.x % kLanes;
+  if (sc >= ns || !S.active[sc]) return;
+  const T sigma = (T)S.sigma[sc];
+  const double kk = (double)(S.k0[sc] + jiter);
+  const T w = (T)((kk + 1.0) / (kk + 2.0));
+  const T wa = (T)(1.0 / (kk + 2.0));
+  const T* __restrict__ xb = V.xbar;
+  for (int i = r0 + threadIdx.x / kLanes; i < r1; i += kRowsPerPass) {
+    const int a = ptr[i], b = ptr[i + 1];
+    T acc = 0;
+    if (staged)
+      for (int k = a - k0; k < b - k0; ++k) acc += lv[k] * xb[(size_t)lc[k] * ns + sc];
+    else
+      for (int k = a; k < b; ++k) acc += V.av[k] * xb[(size_t)S.a_col[k] * ns + sc];
+    const size_t e = (size_t)i * ns + sc;
+    const T y = V.y[e];
+    T yh = y + sigma * (V.b[e] - acc);
+    if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
+    if (CHECK) V.yhat[e] = yh;
+    else V.y[e] = w * ((T)2 * yh - y) + wa * V.y0[e];
+  }
+}
+
+// Per-scenario KKT partials of one row block, summed over the block's rows in
+// a fixed order; part[((blk * NQ) + q) * kMaxScen + s].
+template <int NQ>
+__device__ inline void scen_block_partials(double (&q)[NQ], const bool (&is_max)[NQ], double* red,
+                                           double* out_blk) {
+  const int sc = threadIdx.x % kLanes;
+  const int rl = threadIdx.x / kLanes;
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) red[(rl * kLanes + sc) * NQ + k] = q[k];
+  __syncthreads();
+  if (threadIdx.x < kLanes * NQ) {
+    const int s2 = threadIdx.x / NQ;
+    const int k = threadIdx.x % NQ;
+    double acc = red[s2 * NQ + k];
+    for (int r = 1; r < kRowsPerPass; ++r) {
+      const double v = red[(r * kLanes + s2) * NQ + k];
+      acc = is_max[k] ? fmax(acc, v) : acc + v;
+    }
+    out_blk[k * kMaxScen + s2] = acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_kkt_rows_ms(const SlotDev* __restrict__ slots,
+                                                          const Tile* __restrict__ tiles, int ntiles) {
+  __shared__ int lc[kNnzTile];
+  __shared__ double lv[kNnzTile];
+  __shared__ double red[kThreads * RQ_N];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const Vecs<T>& V = vecs<T>(S);
+  const int r0 = S.a_blk[tl.blk], r1 = S.a_blk[tl.blk + 1];
+  const int* __restrict__ ptr = S.a_ptr;
+  const int k0 = ptr[r0];
+  const int nz = ptr[r1] - k0;
+  const bool staged = nz <= kNnzTile;
+  if (staged) stage_entries<double>(S.a_col + k0, S.d.av + k0, nz, lc, lv);
+  __syncthreads();
+  const int ns = S.nscen;
+  const int sc = threadIdx.x % kLanes;
+  double q[RQ_N] = {0, 0, 0, 0, 0, 0, 0};
+  const bool is_max[RQ_N] = {false, false, false, false, false, false, true};
+  if (sc < ns) {
+    for (int i = r0 + threadIdx.x / kLanes; i < r1; i += kRowsPerPass) {
+      double s1 = 0, s2 = 0;
+      for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const int c = staged ? lc[k - k0] : S.a_col[k];
+        const double v = staged ? lv[k - k0] : S.d.av[k];
+        const size_t e = (size_t)c * ns + sc;
+        const double xh = (double)V.xhat[e];
+        s1 += v * xh;
+        s2 += v * (xh - (double)V.x[e]);
+      }
+      const size_t e = (size_t)i * ns + sc;
+      double r = S.d.b[e] - s1;
+      if (i >= S.m_eq) r = r > 0.0 ? r : 0.0;
+      const double ru = r / S.dr[i];
+      const double yh = (double)V.yhat[e];
+      const double dy = yh - (double)V.y[e];
+      const double d0 = yh - (double)V.y0[e];
+      const double yneg = i >= S.m_eq && yh < 0.0 ? yh * S.dr[i] : 0.0;
+      q[RQ_RES2] += ru * ru;
+      q[RQ_BY] += S.d.b[e] * yh;
+      q[RQ_DY2] += dy * dy;
+      q[RQ_DYADX] += dy * s2;
+      q[RQ_DY0] += d0 * d0;
+      q[RQ_YNEG2] += yneg * yneg;
+      q[RQ_RESMAX] = fmax(q[RQ_RESMAX], fabs(ru));
+    }
+  }
+  scen_block_partials<RQ_N>(q, is_max, red, S.part_a + (size_t)tl.blk * RQ_N * kMaxScen);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_kkt_cols_ms(const SlotDev* __restrict__ slots,
+                                                          const Tile* __restrict__ tiles, int ntiles) {
+  __shared__ int lc[kNnzTile];
+  __shared__ double lv[kNnzTile];
+  __shared__ double red[kThreads * CQ_N];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const SlotDev& S = slots[tl.slot];
+  const Vecs<T>& V = vecs<T>(S);
+  const int r0 = S.t_blk[tl.blk], r1 = S.t_blk[tl.blk + 1];
+  const int* __restrict__ ptr = S.t_ptr;
+  const int k0 = ptr[r0];
+  const int nz = ptr[r1] - k0;
+  const bool staged = nz <= kNnzTile;
+  if (staged) stage_entries<double>(S.t_col + k0, S.d.tv + k0, nz, lc, lv);
+  __syncthreads();
+  const int ns = S.nscen;
+  const int sc = threadIdx.x % kLanes;
+  double q[CQ_N] = {0, 0, 0, 0, 0};
+  const bool is_max[CQ_N] = {false, false, false, false, false};
+  if (sc < ns) {
+    for (int j = r0 + threadIdx.x / kLanes; j < r1; j += kRowsPerPass) {
+      double acc = 0;
+      for (int k = ptr[j]; k < ptr[j + 1]; ++k) {
+        const int c = staged ? lc[k - k0] : S.t_col[k];
+        const double v = staged ? lv[k - k0] : S.d.tv[k];
+        acc += v * (double)V.yhat[(size_t)c * ns + sc];
+      }
+      const size_t e = (size_t)j * ns + sc;
+      const double c = S.d.c[e], l = S.d.l[e], u = S.d.u[e];
+      const double dh = c - acc;
+      const bool fl = isfinite(l), fu = isfinite(u);
+      double lam = 0.0;
+      if (fl && fu) lam = dh;
+      else if (fl) lam = dh > 0.0 ? dh : 0.0;
+      else if (fu) lam = dh < 0.0 ? dh : 0.0;
+      const double dres = (dh - lam) / S.dc[j];
+      const double xhv = (double)V.xhat[e];
+      const double dx = xhv - (double)V.x[e];
+      const double d0 = xhv - (double)V.x0[e];
+      q[CQ_DRES2] += dres * dres;
+      q[CQ_LBUB] += (lam > 0.0 ? l * lam : 0.0) + (lam < 0.0 ? u * lam : 0.0);
+      q[CQ_CX] += c * xhv;
+      q[CQ_DX2] += dx * dx;
+      q[CQ_DX0] += d0 * d0;
+    }
+  }
+  scen_block_partials<CQ_N>(q, is_max, red, S.part_t + (size_t)tl.blk * CQ_N * kMaxScen);
+}
+
+// scal[s * kScal + q]: thread (q, s) sums its partial over all blocks in order
+__global__ __launch_bounds__(kThreads) void k_reduce_ms(const SlotDev* __restrict__ slots) {
+  const SlotDev& S = slots[0];
+  const int tq = threadIdx.x / kLanes;  // 0 .. 15
+  const int sc = threadIdx.x % kLanes;
+  if (tq >= RQ_N + CQ_N || sc >= S.nscen) return;
+  double acc = 0.0;
+  if (tq < RQ_N) {
+    const bool mx = tq == RQ_RESMAX;
+    for (int b = 0; b < S.a_nblk; ++b) {
+      const double v = S.part_a[((size_t)b * RQ_N + tq) * kMaxScen + sc];
+      acc = mx ? fmax(acc, v) : acc + v;
+    }
+  } else {
+    const int k = tq - RQ_N;
+    for (int b = 0; b < S.t_nblk; ++b) acc += S.part_t[((size_t)b * CQ_N + k) * kMaxScen + sc];
+  }
+  S.scal[sc * kScal + tq] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_finish_ms(const SlotDev* __restrict__ slots, int64_t n_elems,
+                                                        int which, int kk) {
+  // which 0: x over n * nscen elements, 1: y over m * nscen
+  const SlotDev& S = *slots;
+  const Vecs<T>& V = vecs<T>(S);
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= n_elems) return;
+  const int sc = (int)(e % S.nscen);
+  if (!S.active[sc]) return;
+  const int flag = S.restart[sc];
+  T* z = which ? V.y : V.x;
+  T* z0 = which ? V.y0 : V.x0;
+  const T zh = which ? V.yhat[e] : V.xhat[e];
+  if (flag == 1) {
+    z[e] = zh;
+    z0[e] = zh;
+    return;
+  }
+  const double k = (double)(S.k0[sc] + kk);
+  const T w = (T)((k + 1.0) / (k + 2.0));
+  const T wa = (T)(1.0 / (k + 2.0));
+  const T refl = which ? (T)2 * zh - z[e] : V.xbar[e];
+  const T zn = w * refl + wa * z0[e];
+  z[e] = zn;
+  if (flag == 2) z0[e] = zn;
+}
+
+__global__ __launch_bounds__(kThreads) void k_promote_ms(const SlotDev* __restrict__ slots, int64_t nx,
+                                                         int64_t ny) {
+  const SlotDev& S = *slots;
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e < nx) {
+    const double v = (double)S.f.xhat[e];
+    S.d.x[e] = v;
+    S.d.x0[e] = v;
+    S.d.xhat[e] = v;
+  } else if (e < nx + ny) {
+    const int64_t i = e - nx;
+    const double v = (double)S.f.yhat[i];
+    S.d.y[i] = v;
+    S.d.y0[i] = v;
+    S.d.yhat[i] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -776,9 +1158,21 @@ __global__ void k_to_f32(const double* a, float* b, int64_t n) {
   if (i < n) b[i] = (float)a[i];
 }
 
-__global__ void k_copy(const float4* __restrict__ a, float4* __restrict__ b, int64_t n4) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
-    b[i] = a[i];
+// Plain stream copy, 4 x 16 B per thread and iteration, grid-stride.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kThreads) void k_copy(const v4f* __restrict__ a, v4f* __restrict__ b,
+                                                   int64_t n4) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads * 4;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads * 4 + threadIdx.x; i < n4; i += stride) {
+    v4f v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * kThreads < n4) v[u] = __builtin_nontemporal_load(a + i + u * kThreads);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * kThreads < n4) __builtin_nontemporal_store(v[u], b + i + u * kThreads);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -787,31 +1181,37 @@ __global__ void k_copy(const float4* __restrict__ a, float4* __restrict__ b, int
 
 static inline int nb(int64_t n, int t = kThreads) { return (int)((n + t - 1) / t); }
 
+template <typename K>
+static void launch_tiles(K kern, int ntiles, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                         const SlotDev* slots, const Tile* tiles, int jiter) {
+  const dim3 g(xcd_grid(ntiles));
+  if (e0 && e1) hipExtLaunchKernelGGL(kern, g, dim3(kThreads), 0, s, e0, e1, 0, slots, tiles, ntiles, jiter);
+  else kern<<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+}
+
 void launch_primal(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
-                   int jiter, int nscen, hipStream_t s) {
+                   int jiter, int nscen, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (ntiles <= 0) return;
   (void)nscen;
-  dim3 g(xcd_grid(ntiles));
   if (prec == 1) {
-    if (check) k_primal<float, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
-    else k_primal<float, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    if (check) launch_tiles(k_primal<float, true>, ntiles, s, e0, e1, slots, tiles, jiter);
+    else launch_tiles(k_primal<float, false>, ntiles, s, e0, e1, slots, tiles, jiter);
   } else {
-    if (check) k_primal<double, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
-    else k_primal<double, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    if (check) launch_tiles(k_primal<double, true>, ntiles, s, e0, e1, slots, tiles, jiter);
+    else launch_tiles(k_primal<double, false>, ntiles, s, e0, e1, slots, tiles, jiter);
   }
 }
 
 void launch_dual(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
-                 int jiter, int nscen, hipStream_t s) {
+                 int jiter, int nscen, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (ntiles <= 0) return;
   (void)nscen;
-  dim3 g(xcd_grid(ntiles));
   if (prec == 1) {
-    if (check) k_dual<float, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
-    else k_dual<float, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    if (check) launch_tiles(k_dual<float, true>, ntiles, s, e0, e1, slots, tiles, jiter);
+    else launch_tiles(k_dual<float, false>, ntiles, s, e0, e1, slots, tiles, jiter);
   } else {
-    if (check) k_dual<double, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
-    else k_dual<double, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    if (check) launch_tiles(k_dual<double, true>, ntiles, s, e0, e1, slots, tiles, jiter);
+    else launch_tiles(k_dual<double, false>, ntiles, s, e0, e1, slots, tiles, jiter);
   }
 }
 
@@ -982,9 +1382,63 @@ void launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
 }
 
 void launch_copy_kernel(const float4* a, float4* b, int64_t n4, hipStream_t s) {
-  int g = nb(n4);
-  if (g > 8192) g = 8192;
-  if (g > 0) k_copy<<<g, kThreads, 0, s>>>(a, b, n4);
+  int g = nb(n4, kThreads * 4);
+  if (g > 256 * 64) g = 256 * 64;
+  if (g > 0) k_copy<<<g, kThreads, 0, s>>>((const v4f*)a, (v4f*)b, n4);
+}
+
+// ---- scenario-batch launchers -------------------------------------------------
+
+void launch_primal_ms(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles, int jiter,
+                      hipStream_t s) {
+  if (ntiles <= 0) return;
+  const dim3 g(xcd_grid(ntiles));
+  if (prec == 1) {
+    if (check) k_primal_ms<float, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    else k_primal_ms<float, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+  } else {
+    if (check) k_primal_ms<double, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    else k_primal_ms<double, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+  }
+}
+
+void launch_dual_ms(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles, int jiter,
+                    hipStream_t s) {
+  if (ntiles <= 0) return;
+  const dim3 g(xcd_grid(ntiles));
+  if (prec == 1) {
+    if (check) k_dual_ms<float, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    else k_dual_ms<float, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+  } else {
+    if (check) k_dual_ms<double, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    else k_dual_ms<double, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+  }
+}
+
+void launch_kkt_ms(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
+                   int natiles, hipStream_t s) {
+  if (prec == 1) {
+    if (natiles > 0) k_kkt_rows_ms<float><<<xcd_grid(natiles), kThreads, 0, s>>>(slots, atiles, natiles);
+    if (nttiles > 0) k_kkt_cols_ms<float><<<xcd_grid(nttiles), kThreads, 0, s>>>(slots, ttiles, nttiles);
+  } else {
+    if (natiles > 0) k_kkt_rows_ms<double><<<xcd_grid(natiles), kThreads, 0, s>>>(slots, atiles, natiles);
+    if (nttiles > 0) k_kkt_cols_ms<double><<<xcd_grid(nttiles), kThreads, 0, s>>>(slots, ttiles, nttiles);
+  }
+  k_reduce_ms<<<1, kThreads, 0, s>>>(slots);
+}
+
+void launch_finish_ms(int prec, const SlotDev* slots, int64_t nx, int64_t ny, int kk, hipStream_t s) {
+  if (prec == 1) {
+    if (nx > 0) k_finish_ms<float><<<nb(nx), kThreads, 0, s>>>(slots, nx, 0, kk);
+    if (ny > 0) k_finish_ms<float><<<nb(ny), kThreads, 0, s>>>(slots, ny, 1, kk);
+  } else {
+    if (nx > 0) k_finish_ms<double><<<nb(nx), kThreads, 0, s>>>(slots, nx, 0, kk);
+    if (ny > 0) k_finish_ms<double><<<nb(ny), kThreads, 0, s>>>(slots, ny, 1, kk);
+  }
+}
+
+void launch_promote_ms(const SlotDev* slots, int64_t nx, int64_t ny, hipStream_t s) {
+  if (nx + ny > 0) k_promote_ms<<<nb(nx + ny), kThreads, 0, s>>>(slots, nx, ny);
 }
 
 }  // namespace uclp

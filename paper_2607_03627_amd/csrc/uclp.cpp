@@ -91,6 +91,11 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->spmv_algo = UC_LP_SPMV_ROWSPLIT;
   o->verbose = 0;
   o->timing = 0;
+  o->restart_to_current = 0;
+  o->restart_sufficient = 0.2;
+  o->restart_necessary = 0.8;
+  o->restart_artificial = 0.36;
+  o->pw_smoothing = 0.5;
 }
 
 static int check_opts(const uc_lp_opts& o) {
@@ -104,6 +109,10 @@ static int check_opts(const uc_lp_opts& o) {
   if (!(o.time_limit_s > 0)) return fail(UC_LP_EINVAL, "time_limit_s");
   if (!(o.step_scale > 0 && o.step_scale < 1)) return fail(UC_LP_EINVAL, "step_scale in (0,1)");
   if (o.spmv_algo != UC_LP_SPMV_ROWSPLIT) return fail(UC_LP_ENOTSUP, "spmv_algo %d for PDHG", o.spmv_algo);
+  if (!(o.restart_sufficient > 0 && o.restart_sufficient <= o.restart_necessary && o.restart_necessary < 1) ||
+      !(o.restart_artificial > 0 && o.restart_artificial <= 1) || !(o.pw_smoothing >= 0 && o.pw_smoothing <= 1) ||
+      (o.restart_to_current != 0 && o.restart_to_current != 1))
+    return fail(UC_LP_EINVAL, "restart / primal-weight parameters out of range");
   return UC_LP_OK;
 }
 
@@ -428,7 +437,13 @@ struct uc_engine {
   size_t tile_cap = 0;
   int* d_ids = nullptr;
   double* h_scal = nullptr;  // pinned, max_slots * kScal
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  double* d_scal = nullptr;  // device, max_slots * kScal (one copy per check)
+  // tile layout of the current active set, rebuilt when the set or a
+  // precision changes
+  std::vector<std::pair<const uc_lp*, int>> layout;
+  size_t off_t0 = 0, off_a1 = 0, off_a0 = 0;
+  int nT1 = 0, nT0 = 0, nA1 = 0, nA0 = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<SlotDev> h_slots;
   std::string err;
 };
@@ -652,7 +667,9 @@ static int fetch_solution(uc_lp* lp, int prec) {
   lp->sol_y.assign(P.m, 0.0);
   for (int32_t j = 0; j < P.n; ++j)
     if (P.int_col[j] < 0) lp->sol_x[j] = P.o_lb[j];
-  for (int j = 0; j < P.ni; ++j) lp->sol_x[P.col_map[j]] = xi[j];
+  // x_hat lies in the scaled box; unscaling can overshoot a bound by an ulp,
+  // so the original-space value is clamped back into [lb, ub]
+  for (int j = 0; j < P.ni; ++j) lp->sol_x[P.col_map[j]] = std::min(std::max(xi[j], P.l[j]), P.u[j]);
   for (int i = 0; i < P.mi; ++i) {
     const int enc = P.row_map[i];
     if (enc >= 0) lp->sol_y[enc] = yi[i];
@@ -670,27 +687,31 @@ struct CheckOut {
   bool promote = false;
 };
 
-static void kkt_from_scalars(const uc_lp* lp, const double* q, uc_lp_info& in) {
-  const HostProblem& P = lp->P;
+static void kkt_scalars(const double* q, double offset, double norm_b, double norm_c, uc_lp_info& in) {
   const double rho_p = std::sqrt(std::max(q[RQ_RES2], 0.0));
-  const double rho_d = std::sqrt(std::max(q[RQ_N + CQ_DRES2], 0.0));
-  const double pobj = q[RQ_N + CQ_CX] + P.obj_offset;
-  const double dobj = q[RQ_BY] + q[RQ_N + CQ_LBUB] + P.obj_offset;
+  const double rho_d = std::sqrt(std::max(q[RQ_N + CQ_DRES2] + q[RQ_YNEG2], 0.0));
+  const double pobj = q[RQ_N + CQ_CX] + offset;
+  const double dobj = q[RQ_BY] + q[RQ_N + CQ_LBUB] + offset;
   in.pobj = pobj;
   in.dobj = dobj;
-  in.rel_primal = rho_p / (1.0 + P.norm_b);
-  in.rel_dual = rho_d / (1.0 + P.norm_c);
+  in.rel_primal = rho_p / (1.0 + norm_b);
+  in.rel_dual = rho_d / (1.0 + norm_c);
   in.rel_gap = std::fabs(pobj - dobj) / (1.0 + std::fabs(pobj) + std::fabs(dobj));
   in.rel_kkt = std::max(in.rel_primal, std::max(in.rel_dual, in.rel_gap));
   in.abs_primal_inf = q[RQ_RESMAX];
 }
 
-static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
-  PdhgState& st = lp->st;
-  const uc_lp_opts& o = lp->opts;
+static void kkt_from_scalars(const uc_lp* lp, const double* q, uc_lp_info& in) {
+  kkt_scalars(q, lp->P.obj_offset, lp->P.norm_b, lp->P.norm_c, in);
+}
+
+// One check of one PDHG run: KKT from the FP64 scalars, the eps milestone,
+// termination, and the restart / primal-weight decision.  `in` carries the
+// run's info between checks.
+static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, int K, double tnow,
+                           double offset, double norm_b, double norm_c, bool cancel, uc_lp_info& in) {
   CheckOut out;
-  uc_lp_info in = get_info(lp);
-  kkt_from_scalars(lp, q, in);
+  kkt_scalars(q, offset, norm_b, norm_c, in);
   st.iters += K;
   if (st.prec == 0) st.iters64 += K;
   st.phase_total += K;
@@ -712,6 +733,7 @@ static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
       in.t_to_eps_s = tnow - st.t_start;
       in.pobj_at_eps = in.pobj;
       in.rel_kkt_at_eps = in.rel_kkt;
+      in.iters_at_eps = st.iters;
     }
     const bool polish_phase = o.precision == UC_LP_FP32_MIXED_POLISH && st.prec == 0;
     const double target = polish_phase ? o.eps_polish : o.eps_rel;
@@ -731,25 +753,27 @@ static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
       out.terminate = true;
       out.status = UC_LP_TIME_LIMIT;
     }
-    if (!out.terminate && lp->cancel.load()) {
+    if (!out.terminate && cancel) {
       out.terminate = true;
       out.status = UC_LP_CANCELLED;
     }
   }
+  if (out.terminate) out.promote = false;
   if (!out.terminate && !out.promote) {
     if (!st.r_start_set) {
       st.r_start = rfp;
       st.r_start_set = true;
     }
-    bool rs = rfp <= 0.2 * st.r_start;
-    if (!rs && rfp <= 0.8 * st.r_start && st.r_prev_set && rfp > st.r_prev) rs = true;
-    if (!rs && (double)k_end >= 0.36 * (double)st.phase_total) rs = true;
+    bool rs = rfp <= o.restart_sufficient * st.r_start;
+    if (!rs && rfp <= o.restart_necessary * st.r_start && st.r_prev_set && rfp > st.r_prev) rs = true;
+    if (!rs && (double)k_end >= o.restart_artificial * (double)st.phase_total) rs = true;
     st.r_prev = rfp;
     st.r_prev_set = true;
     if (rs) {
       const double dX = std::sqrt(std::max(q[RQ_N + CQ_DX0], 0.0));
       const double dY = std::sqrt(std::max(q[RQ_DY0], 0.0));
-      if (dX > 1e-10 && dY > 1e-10) st.omega = std::exp(0.5 * std::log(dY / dX) + 0.5 * std::log(st.omega));
+      const double th = o.pw_smoothing;
+      if (dX > 1e-10 && dY > 1e-10) st.omega = std::exp(th * std::log(dY / dX) + (1.0 - th) * std::log(st.omega));
       st.k_inner = 0;
       st.r_start_set = false;
       st.r_prev_set = false;
@@ -769,15 +793,22 @@ static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
   }
   in.restarts = st.restarts;
   in.omega = st.omega;
+  if (o.verbose)
+    fprintf(stderr, "[uclp] it %lld prec %s kkt %.2e (p %.1e d %.1e g %.1e) pobj %.10g omega %.3g rfp %.3e rs %lld\n",
+            st.iters, st.prec ? "fp32" : "fp64", in.rel_kkt, in.rel_primal, in.rel_dual, in.rel_gap, in.pobj,
+            st.omega, rfp, st.restarts);
+  return out;
+}
+
+static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
+  uc_lp_info in = get_info(lp);
+  CheckOut out = check_core(lp->st, lp->opts, q, K, tnow, lp->P.obj_offset, lp->P.norm_b, lp->P.norm_c,
+                            lp->cancel.load(), in);
   if (lp->timed_n > 0) {
     in.primal_kernel_us = 1e3 * lp->timed_primal_ms / lp->timed_n;
     in.dual_kernel_us = 1e3 * lp->timed_dual_ms / lp->timed_n;
     in.timed_launches = lp->timed_n;
   }
-  if (o.verbose)
-    fprintf(stderr, "[uclp] it %lld prec %s kkt %.2e (p %.1e d %.1e g %.1e) pobj %.10g omega %.3g rfp %.3e rs %lld\n",
-            st.iters, st.prec ? "fp32" : "fp64", in.rel_kkt, in.rel_primal, in.rel_dual, in.rel_gap, in.pobj,
-            st.omega, rfp, st.restarts);
   set_info(lp, in);
   return out;
 }
@@ -787,6 +818,7 @@ static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
 static int engine_tables(uc_engine* E, size_t ntiles) {
   if (ntiles > E->tile_cap) {
     if (E->d_tiles) (void)hipFree(E->d_tiles);
+  if (E->d_scal) (void)hipFree(E->d_scal);
     E->d_tiles = nullptr;
     size_t cap = std::max<size_t>(ntiles, 2 * E->tile_cap);
     HIPOK(hipMalloc(&E->d_tiles, cap * sizeof(Tile)));
@@ -868,78 +900,94 @@ static void run_epochs(uc_engine* E) {
   const int A = (int)E->active.size();
   int K = 1 << 30;
   for (auto* lp : E->active) K = std::min(K, lp->opts.kkt_every);
-  std::vector<Tile> tt[2], at[2];
-  std::vector<int> ids(A);
   E->h_slots.resize(std::max<size_t>(E->h_slots.size(), (size_t)A));
+  std::vector<std::pair<const uc_lp*, int>> sig(A);
   for (int a = 0; a < A; ++a) {
     uc_lp* lp = E->active[a];
     lp->slot = a;
-    ids[a] = a;
     SlotDev S = make_slot(lp);
+    S.scal = E->d_scal + (size_t)a * kScal;
     S.tau[0] = lp->st.eta / lp->st.omega;
     S.sigma[0] = lp->st.eta * lp->st.omega;
     S.k0[0] = lp->st.k_inner;
     S.restart[0] = 0;
     S.active[0] = 1;
     E->h_slots[a] = S;
-    const int p = lp->st.prec;
-    for (int b = 0; b < S.t_nblk; ++b) tt[p].push_back({a, b});
-    for (int b = 0; b < S.a_nblk; ++b) at[p].push_back({a, b});
+    sig[a] = {lp, lp->st.prec};
   }
-  const size_t off_t1 = 0, off_t0 = tt[1].size(), off_a1 = off_t0 + tt[0].size(),
-               off_a0 = off_a1 + at[1].size(), total = off_a0 + at[0].size();
-  if (engine_tables(E, total) != UC_LP_OK) {
-    for (auto* lp : E->active) worker_fail(E, lp);
-    E->active.clear();
-    return;
-  }
-  std::vector<Tile> all;
-  all.reserve(total);
-  all.insert(all.end(), tt[1].begin(), tt[1].end());
-  all.insert(all.end(), tt[0].begin(), tt[0].end());
-  all.insert(all.end(), at[1].begin(), at[1].end());
-  all.insert(all.end(), at[0].begin(), at[0].end());
   hipError_t e = hipSuccess;
-  if (total) e = hipMemcpyAsync(E->d_tiles, all.data(), total * sizeof(Tile), hipMemcpyHostToDevice, s);
+  std::vector<Tile> all;
+  if (sig != E->layout) {
+    std::vector<Tile> tt[2], at[2];
+    std::vector<int> ids(A);
+    for (int a = 0; a < A; ++a) {
+      ids[a] = a;
+      const int p = sig[a].second;
+      for (int b = 0; b < E->h_slots[a].t_nblk; ++b) tt[p].push_back({a, b});
+      for (int b = 0; b < E->h_slots[a].a_nblk; ++b) at[p].push_back({a, b});
+    }
+    E->nT1 = (int)tt[1].size();
+    E->nT0 = (int)tt[0].size();
+    E->nA1 = (int)at[1].size();
+    E->nA0 = (int)at[0].size();
+    E->off_t0 = tt[1].size();
+    E->off_a1 = E->off_t0 + tt[0].size();
+    E->off_a0 = E->off_a1 + at[1].size();
+    const size_t total = E->off_a0 + at[0].size();
+    if (engine_tables(E, total) != UC_LP_OK) {
+      for (auto* lp : E->active) worker_fail(E, lp);
+      E->active.clear();
+      E->layout.clear();
+      return;
+    }
+    all.reserve(total);
+    all.insert(all.end(), tt[1].begin(), tt[1].end());
+    all.insert(all.end(), tt[0].begin(), tt[0].end());
+    all.insert(all.end(), at[1].begin(), at[1].end());
+    all.insert(all.end(), at[0].begin(), at[0].end());
+    if (total) e = hipMemcpyAsync(E->d_tiles, all.data(), total * sizeof(Tile), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(E->d_ids, ids.data(), A * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors die at scope end
+    E->layout = sig;
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(E->d_slots, E->h_slots.data(), A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(E->d_ids, ids.data(), A * sizeof(int), hipMemcpyHostToDevice, s);
-  const Tile* T1 = E->d_tiles + off_t1;
-  const Tile* T0 = E->d_tiles + off_t0;
-  const Tile* A1 = E->d_tiles + off_a1;
-  const Tile* A0 = E->d_tiles + off_a0;
-  const int nT1 = (int)tt[1].size(), nT0 = (int)tt[0].size(), nA1 = (int)at[1].size(), nA0 = (int)at[0].size();
+  const Tile* T1 = E->d_tiles;
+  const Tile* T0 = E->d_tiles + E->off_t0;
+  const Tile* A1 = E->d_tiles + E->off_a1;
+  const Tile* A0 = E->d_tiles + E->off_a0;
+  const int nT1 = E->nT1, nT0 = E->nT0, nA1 = E->nA1, nA0 = E->nA0;
   bool timing = false;
   for (auto* lp : E->active) timing |= lp->opts.timing != 0;
   for (int j = 0; j < K && e == hipSuccess; ++j) {
     const bool check = j == K - 1;
+    // the first iteration of an epoch carries dispatch-attached timing events
+    // on the first non-empty precision group
     const bool tj = timing && j == 0;
-    if (tj) (void)hipEventRecord(E->ev[0], s);
-    launch_primal(1, check, E->d_slots, T1, nT1, j, 1, s);
-    launch_primal(0, check, E->d_slots, T0, nT0, j, 1, s);
-    if (tj) (void)hipEventRecord(E->ev[1], s);
-    launch_dual(1, check, E->d_slots, A1, nA1, j, 1, s);
-    launch_dual(0, check, E->d_slots, A0, nA0, j, 1, s);
-    if (tj) (void)hipEventRecord(E->ev[2], s);
+    const bool t1 = tj && nT1 > 0, t0 = tj && nT1 == 0;
+    launch_primal(1, check, E->d_slots, T1, nT1, j, 1, s, t1 ? E->ev[0] : nullptr, t1 ? E->ev[1] : nullptr);
+    launch_primal(0, check, E->d_slots, T0, nT0, j, 1, s, t0 ? E->ev[0] : nullptr, t0 ? E->ev[1] : nullptr);
+    launch_dual(1, check, E->d_slots, A1, nA1, j, 1, s, t1 ? E->ev[2] : nullptr, t1 ? E->ev[3] : nullptr);
+    launch_dual(0, check, E->d_slots, A0, nA0, j, 1, s, t0 ? E->ev[2] : nullptr, t0 ? E->ev[3] : nullptr);
   }
   launch_kkt(1, E->d_slots, T1, nT1, A1, nA1, 1, s);
   launch_kkt(0, E->d_slots, T0, nT0, A0, nA0, 1, s);
   launch_reduce(E->d_slots, E->d_ids, A, 1, s);
-  for (int a = 0; a < A && e == hipSuccess; ++a)
-    e = hipMemcpyAsync(E->h_scal + (size_t)a * kScal, E->active[a]->D.scal, kScal * sizeof(double),
-                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(E->h_scal, E->d_scal, (size_t)A * kScal * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) {
     fail(UC_LP_EHIP, "epoch failed: %s", hipGetErrorString(e));
     for (auto* lp : E->active) worker_fail(E, lp);
     E->active.clear();
+    E->layout.clear();
     return;
   }
   if (timing) {
     float t01 = 0, t12 = 0;
     if (hipEventElapsedTime(&t01, E->ev[0], E->ev[1]) == hipSuccess &&
-        hipEventElapsedTime(&t12, E->ev[1], E->ev[2]) == hipSuccess) {
+        hipEventElapsedTime(&t12, E->ev[2], E->ev[3]) == hipSuccess) {
       for (auto* lp : E->active)
         if (lp->opts.timing) {
           lp->timed_primal_ms += t01;
@@ -954,7 +1002,7 @@ static void run_epochs(uc_engine* E) {
     uc_lp* lp = E->active[a];
     // the finish kernel needs the epoch-start k0 and the restart decision
     outs[a] = process_check(lp, E->h_scal + (size_t)a * kScal, K, tnow);
-    E->h_slots[a].restart[0] = outs[a].restart ? 1 : 0;
+    E->h_slots[a].restart[0] = outs[a].restart ? (lp->opts.restart_to_current ? 2 : 1) : 0;
   }
   e = hipMemcpyAsync(E->d_slots, E->h_slots.data(), A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
   launch_finish(1, E->d_slots, T1, nT1, A1, nA1, K - 1, 1, s);
@@ -970,6 +1018,8 @@ static void run_epochs(uc_engine* E) {
     // reuse the tile buffer after the epoch's kernels (same stream, ordered)
     both = pt;
     both.insert(both.end(), pa.begin(), pa.end());
+    // the promote tiles overwrite the cached layout, which is rebuilt next epoch
+    E->layout.clear();
     if (engine_tables(E, both.size()) == UC_LP_OK) {
       (void)hipMemcpyAsync(E->d_tiles, both.data(), both.size() * sizeof(Tile), hipMemcpyHostToDevice, s);
       launch_promote(E->d_slots, E->d_tiles, (int)pt.size(), E->d_tiles + pt.size(), (int)pa.size(), 1, s);
@@ -982,6 +1032,8 @@ static void run_epochs(uc_engine* E) {
     if (outs[a].terminate) retire(E, lp, outs[a].status);
     else keep.push_back(lp);
   }
+  // a retired handle's address may be reused by a later instance
+  if (keep.size() != E->active.size()) E->layout.clear();
   E->active.swap(keep);
 }
 
@@ -1033,6 +1085,7 @@ static int engine_init(uc_engine* E) {
   HIPOK(hipMalloc(&E->d_slots, sizeof(SlotDev) * E->max_slots));
   HIPOK(hipMalloc(&E->d_ids, sizeof(int) * E->max_slots));
   HIPOK(hipHostMalloc((void**)&E->h_scal, sizeof(double) * kScal * E->max_slots, hipHostMallocDefault));
+  HIPOK(hipMalloc(&E->d_scal, sizeof(double) * kScal * E->max_slots));
   for (auto& ev : E->ev) HIPOK(hipEventCreate(&ev));
   E->worker = std::thread(worker_main, E);
   return UC_LP_OK;
@@ -1050,6 +1103,7 @@ static void engine_free(uc_engine* E) {
   if (E->d_slots) (void)hipFree(E->d_slots);
   if (E->d_ids) (void)hipFree(E->d_ids);
   if (E->d_tiles) (void)hipFree(E->d_tiles);
+  if (E->d_scal) (void)hipFree(E->d_scal);
   if (E->h_scal) (void)hipHostFree(E->h_scal);
   for (auto& ev : E->ev)
     if (ev) (void)hipEventDestroy(ev);
@@ -1134,6 +1188,10 @@ extern "C" int uc_lp_create(uc_engine* eng, int32_t m, int32_t n, int64_t nnz, c
   lp->need_bytes = arena_bytes(P, 1);
   std::memset(&lp->info, 0, sizeof lp->info);
   lp->info.t_to_eps_s = -1;
+  lp->info.m_presolved = P.mi;
+  lp->info.n_presolved = P.ni;
+  lp->info.nnz_presolved = P.nnzi;
+  lp->info.device_bytes = (int64_t)lp->need_bytes;
   if (eng) {
     if (lp->need_bytes > eng->budget)
       return fail(UC_LP_EBUDGET, "instance needs %zu bytes, engine budget is %zu", lp->need_bytes, eng->budget);
@@ -1390,6 +1448,7 @@ static int debug_step_t(uc_lp* lp, const double* x, const double* y, const doubl
   std::vector<Tile> tl;
   for (int b = 0; b < S.t_nblk; ++b) tl.push_back({0, b});
   for (int b = 0; b < S.a_nblk; ++b) tl.push_back({0, b});
+  E->layout.clear();  // the engine's tile and slot tables are overwritten below
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(E->d_tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
@@ -1451,6 +1510,7 @@ extern "C" int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp
   std::vector<Tile> tl;
   for (int b = 0; b < S.t_nblk; ++b) tl.push_back({0, b});
   for (int b = 0; b < S.a_nblk; ++b) tl.push_back({0, b});
+  E->layout.clear();  // the engine's tile and slot tables are overwritten below
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(E->d_tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
@@ -1652,10 +1712,272 @@ extern "C" int uc_copy_bench(int device, size_t bytes, int32_t reps, double* gbp
   return rc;
 }
 
+// ---------------------------------------------------------------------------
+// scenario batches over one matrix
+// ---------------------------------------------------------------------------
+
+struct ScenArena {
+  Arena ar;
+  double *c_in, *l_in, *u_in, *b_in, *x_out, *y_out, *x_warm, *y_warm;
+  double *part_a, *part_t, *scal;
+  Vecs<float> f;
+  Vecs<double> d;
+  SlotDev* slot_dev;
+  Tile* tiles;
+};
+
+static void carve_scen(ScenArena& A, const HostProblem& P, int S) {
+  Arena& a = A.ar;
+  const int n = P.ni, m = P.mi;
+  A.c_in = a.take<double>((size_t)n * S);
+  A.l_in = a.take<double>((size_t)n * S);
+  A.u_in = a.take<double>((size_t)n * S);
+  A.b_in = a.take<double>((size_t)m * S);
+  A.x_out = a.take<double>((size_t)n * S);
+  A.y_out = a.take<double>((size_t)m * S);
+  A.x_warm = a.take<double>((size_t)n * S);
+  A.y_warm = a.take<double>((size_t)m * S);
+  A.part_a = a.take<double>(P.a_blk.size() * RQ_N * kMaxScen);
+  A.part_t = a.take<double>(P.t_blk.size() * CQ_N * kMaxScen);
+  A.scal = a.take<double>((size_t)kScal * kMaxScen);
+  carve_vecs(a, A.f, n, m, S);
+  carve_vecs(a, A.d, n, m, S);
+  A.slot_dev = a.take<SlotDev>(1);
+  A.tiles = a.take<Tile>(P.a_blk.size() + P.t_blk.size());
+}
+
 extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* c, const double* b,
                                      const double* lb, const double* ub, const double* x0, const double* y0,
                                      double* x, double* y, uc_lp_info* info) {
   g_err.clear();
-  (void)base; (void)n_scen; (void)c; (void)b; (void)lb; (void)ub; (void)x0; (void)y0; (void)x; (void)y; (void)info;
-  return fail(UC_LP_ENOTSUP, "scenario batches are not built yet");
+  if (!base) return fail(UC_LP_EINVAL, "NULL handle");
+  if (n_scen < 1 || n_scen > kMaxScen) return fail(UC_LP_ENOTSUP, "n_scen %d not in 1..%d", n_scen, kMaxScen);
+  if (!c || !b || !lb || !ub || !info) return fail(UC_LP_EINVAL, "NULL scenario array");
+  const HostProblem& P = base->P;
+  const int S = n_scen, n = P.n, m = P.m, ni = P.ni, mi = P.mi;
+  // per-scenario validation and minimal presolve (same fixed-column structure as the base)
+  std::vector<HostProblem> SP(S);
+  for (int s = 0; s < S; ++s) {
+    const double *cs = c + (size_t)s * n, *bs = b + (size_t)s * m, *ls = lb + (size_t)s * n, *us = ub + (size_t)s * n;
+    int rc = validate_data(m, n, cs, bs, P.o_sense.data(), ls, us);
+    if (rc) return rc;
+    for (int32_t j = 0; j < n; ++j)
+      if ((ls[j] == us[j]) != (P.int_col[j] < 0))
+        return fail(UC_LP_ENOTSUP, "scenario %d: column %d differs from the base in being fixed", s, j);
+    HostProblem& Q = SP[s];
+    Q.m = m;
+    Q.n = n;
+    Q.o_ptr = P.o_ptr;
+    Q.o_col = P.o_col;
+    Q.o_val = P.o_val;
+    Q.o_sense = P.o_sense;
+    Q.o_c.assign(cs, cs + n);
+    Q.o_b.assign(bs, bs + m);
+    Q.o_lb.assign(ls, ls + n);
+    Q.o_ub.assign(us, us + n);
+    Q.int_col = P.int_col;
+    Q.col_map = P.col_map;
+    Q.row_map = P.row_map;
+    Q.ni = ni;
+    Q.mi = mi;
+    Q.b.assign(mi, 0.0);
+    Q.c.assign(ni, 0.0);
+    Q.l.assign(ni, 0.0);
+    Q.u.assign(ni, 0.0);
+    presolve_data(Q);
+    if (Q.infeasible) return fail(UC_LP_EINVAL, "scenario %d is infeasible by its empty rows", s);
+  }
+  int rc = debug_ready(base);
+  if (rc) return rc;
+  base->cancel.store(false);  // uc_lp_cancel from another thread stops the batch
+  uc_engine* E = base->eng;
+  hipStream_t st = E->stream;
+  const uc_lp_opts& o = base->opts;
+  ScenArena A;
+  std::memset((void*)&A, 0, sizeof A);
+  carve_scen(A, P, S);
+  const size_t bytes = A.ar.used + 256;
+  void* mem = nullptr;
+  if (hipMalloc(&mem, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(UC_LP_ENOMEM, "scenario arena of %zu bytes", bytes);
+  }
+  A.ar = Arena();
+  A.ar.base = (char*)mem;
+  A.ar.bytes = bytes;
+  carve_scen(A, P, S);
+  auto cleanup = [&]() { (void)hipFree(mem); };
+#define SCEN_HIP(call)                                                                           \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) {                                                                      \
+      cleanup();                                                                                 \
+      return fail(UC_LP_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));                    \
+    }                                                                                            \
+  } while (0)
+  // scenario-major internal data -> interleaved scaled data on the device
+  {
+    std::vector<double> hc((size_t)ni * S), hl((size_t)ni * S), hu((size_t)ni * S), hb((size_t)mi * S);
+    for (int s = 0; s < S; ++s) {
+      std::copy(SP[s].c.begin(), SP[s].c.end(), hc.begin() + (size_t)s * ni);
+      std::copy(SP[s].l.begin(), SP[s].l.end(), hl.begin() + (size_t)s * ni);
+      std::copy(SP[s].u.begin(), SP[s].u.end(), hu.begin() + (size_t)s * ni);
+      std::copy(SP[s].b.begin(), SP[s].b.end(), hb.begin() + (size_t)s * mi);
+    }
+    SCEN_HIP(hipMemcpyAsync(A.c_in, hc.data(), hc.size() * 8, hipMemcpyHostToDevice, st));
+    SCEN_HIP(hipMemcpyAsync(A.l_in, hl.data(), hl.size() * 8, hipMemcpyHostToDevice, st));
+    SCEN_HIP(hipMemcpyAsync(A.u_in, hu.data(), hu.size() * 8, hipMemcpyHostToDevice, st));
+    if (mi) SCEN_HIP(hipMemcpyAsync(A.b_in, hb.data(), hb.size() * 8, hipMemcpyHostToDevice, st));
+    launch_scale_vectors(A.c_in, A.l_in, A.u_in, A.b_in, base->D.dc, base->D.dr, ni, mi, S, (double*)A.d.c,
+                         (double*)A.d.l, (double*)A.d.u, (double*)A.d.b, (float*)A.f.c, (float*)A.f.l,
+                         (float*)A.f.u, (float*)A.f.b, st);
+    SCEN_HIP(hipStreamSynchronize(st));
+  }
+  // primal weights from the scaled data
+  std::vector<double> dr(mi), dc(ni);
+  if (mi) SCEN_HIP(hipMemcpyAsync(dr.data(), base->D.dr, 8 * mi, hipMemcpyDeviceToHost, st));
+  SCEN_HIP(hipMemcpyAsync(dc.data(), base->D.dc, 8 * ni, hipMemcpyDeviceToHost, st));
+  SCEN_HIP(hipStreamSynchronize(st));
+  std::vector<PdhgState> ps(S);
+  std::vector<uc_lp_info> inf(S);
+  std::vector<int> done(S, 0), status(S, UC_LP_RUNNING);
+  const double t0 = now_s();
+  for (int s = 0; s < S; ++s) {
+    double cn = 0, bn = 0;
+    for (int j = 0; j < ni; ++j) cn += (SP[s].c[j] * dc[j]) * (SP[s].c[j] * dc[j]);
+    for (int i = 0; i < mi; ++i) bn += (SP[s].b[i] * dr[i]) * (SP[s].b[i] * dr[i]);
+    ps[s].eta = base->st.eta;
+    ps[s].omega = (cn > 0 && bn > 0) ? std::sqrt(cn) / std::sqrt(bn) : 1.0;
+    ps[s].prec = o.precision == UC_LP_FP64 ? 0 : 1;
+    ps[s].t_start = t0;
+    std::memset(&inf[s], 0, sizeof inf[s]);
+    inf[s].t_to_eps_s = -1;
+    inf[s].norm_a_est = get_info(base).norm_a_est;
+    inf[s].m_presolved = mi;
+    inf[s].n_presolved = ni;
+    inf[s].nnz_presolved = P.nnzi;
+    inf[s].device_bytes = (int64_t)bytes;
+  }
+  SlotDev SD = make_slot(base);
+  SD.nscen = S;
+  SD.f = A.f;
+  SD.d = A.d;
+  SD.f.av = base->D.a_v32;
+  SD.f.tv = base->D.t_v32;
+  SD.d.av = base->D.a_v64;
+  SD.d.tv = base->D.t_v64;
+  SD.part_a = A.part_a;
+  SD.part_t = A.part_t;
+  SD.scal = A.scal;
+  SCEN_HIP(hipMemcpyAsync(A.slot_dev, &SD, sizeof SD, hipMemcpyHostToDevice, st));
+  // warm start (the same point for every scenario), interleaved
+  const double *xin = nullptr, *yin = nullptr;
+  std::vector<double> wx, wy;
+  if (x0 || y0) {
+    wx.assign((size_t)ni * S, 0.0);
+    wy.assign((size_t)mi * S, 0.0);
+    for (int j = 0; j < ni; ++j)
+      for (int s = 0; s < S; ++s) wx[(size_t)j * S + s] = x0 ? x0[P.col_map[j]] : 0.0;
+    for (int i = 0; i < mi; ++i) {
+      const int enc = P.row_map[i];
+      const double v = y0 ? (enc >= 0 ? y0[enc] : -y0[-enc - 1]) : 0.0;
+      for (int s = 0; s < S; ++s) wy[(size_t)i * S + s] = v;
+    }
+    SCEN_HIP(hipMemcpyAsync(A.x_warm, wx.data(), wx.size() * 8, hipMemcpyHostToDevice, st));
+    if (mi) SCEN_HIP(hipMemcpyAsync(A.y_warm, wy.data(), wy.size() * 8, hipMemcpyHostToDevice, st));
+    xin = A.x_warm;
+    yin = A.y_warm;
+  }
+  int phase = o.precision == UC_LP_FP64 ? 0 : 1;
+  launch_init_iterates(A.slot_dev, phase, xin, yin, ni, mi, P.m_eq, S, st);
+  std::vector<Tile> tl;
+  const int nt = (int)P.t_blk.size() - 1, na = (int)P.a_blk.size() - 1;
+  for (int bb = 0; bb < nt; ++bb) tl.push_back({0, bb});
+  for (int bb = 0; bb < na; ++bb) tl.push_back({0, bb});
+  SCEN_HIP(hipMemcpyAsync(A.tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+  SCEN_HIP(hipStreamSynchronize(st));
+  const Tile* TT = A.tiles;
+  const Tile* TA = A.tiles + nt;
+  const int K = o.kkt_every;
+  const int64_t NX = (int64_t)ni * S, NY = (int64_t)mi * S;
+  std::vector<double> q((size_t)kScal * S);
+  for (;;) {
+    for (int s = 0; s < S; ++s) {
+      SD.tau[s] = ps[s].eta / ps[s].omega;
+      SD.sigma[s] = ps[s].eta * ps[s].omega;
+      SD.k0[s] = ps[s].k_inner;
+      SD.restart[s] = 0;
+      SD.active[s] = done[s] ? 0 : 1;
+    }
+    SCEN_HIP(hipMemcpyAsync(A.slot_dev, &SD, sizeof SD, hipMemcpyHostToDevice, st));
+    for (int j = 0; j < K; ++j) {
+      const bool check = j == K - 1;
+      launch_primal_ms(phase, check, A.slot_dev, TT, nt, j, st);
+      launch_dual_ms(phase, check, A.slot_dev, TA, na, j, st);
+    }
+    launch_kkt_ms(phase, A.slot_dev, TT, nt, TA, na, st);
+    SCEN_HIP(hipMemcpyAsync(q.data(), A.scal, q.size() * 8, hipMemcpyDeviceToHost, st));
+    SCEN_HIP(hipStreamSynchronize(st));
+    SCEN_HIP(hipGetLastError());
+    const double tnow = now_s();
+    bool promote_ready = true, all_done = true;
+    for (int s = 0; s < S; ++s) {
+      if (done[s]) continue;
+      CheckOut out = check_core(ps[s], o, &q[(size_t)s * kScal], K, tnow, SP[s].obj_offset, SP[s].norm_b,
+                                SP[s].norm_c, base->cancel.load(), inf[s]);
+      SD.restart[s] = out.restart ? (o.restart_to_current ? 2 : 1) : 0;
+      if (out.terminate) {
+        done[s] = 1;
+        status[s] = out.status;
+      } else if (out.promote) {
+        done[s] = 2;  // waits, frozen, for the other scenarios of this phase
+      }
+    }
+    for (int s = 0; s < S; ++s) {
+      SD.active[s] = done[s] ? 0 : 1;
+      promote_ready &= done[s] != 0;
+      all_done &= done[s] == 1;
+    }
+    SCEN_HIP(hipMemcpyAsync(A.slot_dev, &SD, sizeof SD, hipMemcpyHostToDevice, st));
+    launch_finish_ms(phase, A.slot_dev, NX, NY, K - 1, st);
+    if (all_done) break;
+    if (promote_ready) {
+      // every scenario finished its FP32 phase: continue all waiting ones in FP64
+      launch_promote_ms(A.slot_dev, NX, NY, st);
+      phase = 0;
+      for (int s = 0; s < S; ++s)
+        if (done[s] == 2) done[s] = 0;
+    }
+  }
+  launch_unscale(A.slot_dev, phase, A.x_out, A.y_out, ni, mi, S, st);
+  std::vector<double> hx((size_t)ni * S), hy((size_t)mi * S);
+  SCEN_HIP(hipMemcpyAsync(hx.data(), A.x_out, hx.size() * 8, hipMemcpyDeviceToHost, st));
+  if (mi) SCEN_HIP(hipMemcpyAsync(hy.data(), A.y_out, hy.size() * 8, hipMemcpyDeviceToHost, st));
+  SCEN_HIP(hipStreamSynchronize(st));
+  cleanup();
+#undef SCEN_HIP
+  for (int s = 0; s < S; ++s) {
+    inf[s].status = status[s];
+    inf[s].t_total_s = now_s() - t0;
+    info[s] = inf[s];
+    const HostProblem& Q = SP[s];
+    if (x) {
+      double* xs = x + (size_t)s * n;
+      for (int32_t j = 0; j < n; ++j)
+        if (P.int_col[j] < 0) xs[j] = Q.o_lb[j];
+      for (int j = 0; j < ni; ++j)
+        xs[P.col_map[j]] = std::min(std::max(hx[(size_t)j * S + s], Q.l[j]), Q.u[j]);
+    }
+    if (y) {
+      double* ys = y + (size_t)s * m;
+      std::fill(ys, ys + m, 0.0);
+      for (int i = 0; i < mi; ++i) {
+        const int enc = P.row_map[i];
+        const double v = hy[(size_t)i * S + s];
+        if (enc >= 0) ys[enc] = v;
+        else ys[-enc - 1] = -v;
+      }
+    }
+  }
+  return UC_LP_OK;
 }

@@ -15,7 +15,7 @@ constexpr int kNnzTile = 2048;
 constexpr int kMaxScen = 16;
 
 // Per-block partial sums written by the KKT check kernels.
-enum RowQ { RQ_RES2 = 0, RQ_BY, RQ_DY2, RQ_DYADX, RQ_DY0, RQ_RESMAX, RQ_N };
+enum RowQ { RQ_RES2 = 0, RQ_BY, RQ_DY2, RQ_DYADX, RQ_DY0, RQ_YNEG2, RQ_RESMAX, RQ_N };
 enum ColQ { CQ_DRES2 = 0, CQ_LBUB, CQ_CX, CQ_DX2, CQ_DX0, CQ_N };
 // Per-slot scalars after the final reduction: row quantities then column ones.
 constexpr int kScal = 16;
@@ -53,9 +53,9 @@ struct SlotDev {
   const double* dc;  // D_c (n)
   Vecs<float> f;
   Vecs<double> d;
-  double* part_a;    // [a_nblk * RQ_N * nscen]
-  double* part_t;    // [t_nblk * CQ_N * nscen]
-  double* scal;      // [kScal * nscen]
+  double* part_a;    // [a_nblk * RQ_N] (scenario batches: [a_nblk * RQ_N * kMaxScen])
+  double* part_t;    // [t_nblk * CQ_N] (scenario batches: [t_nblk * CQ_N * kMaxScen])
+  double* scal;      // [kScal] (scenario batches: [nscen * kScal])
   long long k0[kMaxScen];       // inner iteration index at the epoch start
   double tau[kMaxScen];
   double sigma[kMaxScen];
@@ -70,10 +70,13 @@ struct Tile {
 
 // ---- launchers (kernels.hip) --------------------------------------------
 // prec: 0 = FP64, 1 = FP32.  All launches go to `s`.
+// e0/e1 (optional): events that record the start and end of the kernel itself
 void launch_primal(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
-                   int jiter, int nscen, hipStream_t s);
+                   int jiter, int nscen, hipStream_t s, hipEvent_t e0 = nullptr,
+                   hipEvent_t e1 = nullptr);
 void launch_dual(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
-                 int jiter, int nscen, hipStream_t s);
+                 int jiter, int nscen, hipStream_t s, hipEvent_t e0 = nullptr,
+                 hipEvent_t e1 = nullptr);
 void launch_kkt(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles,
                 const Tile* atiles, int natiles, int nscen, hipStream_t s);
 void launch_reduce(const SlotDev* slots, const int* slot_ids, int nslots, int nscen, hipStream_t s);
@@ -81,6 +84,17 @@ void launch_finish(int prec, const SlotDev* slots, const Tile* ttiles, int nttil
                    const Tile* atiles, int natiles, int kk, int nscen, hipStream_t s);
 void launch_promote(const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
                     int natiles, int nscen, hipStream_t s);
+
+// scenario batches (nscen <= kMaxScen interleaved scenarios in slot 0)
+void launch_primal_ms(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles, int jiter,
+                      hipStream_t s);
+void launch_dual_ms(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles, int jiter,
+                    hipStream_t s);
+// KKT partials and their reduction into slots[0].scal[s * kScal + q]
+void launch_kkt_ms(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
+                   int natiles, hipStream_t s);
+void launch_finish_ms(int prec, const SlotDev* slots, int64_t nx, int64_t ny, int kk, hipStream_t s);
+void launch_promote_ms(const SlotDev* slots, int64_t nx, int64_t ny, hipStream_t s);
 
 // setup
 void launch_expand_rows(const int* ptr, int m, int* row_of, hipStream_t s);

@@ -1,0 +1,116 @@
+"""Continuous-batching request loop over one libuclp engine.
+
+Requests (unit-commitment LPs of different sizes) arrive on a timeline.  At
+its arrival time a request is created against the engine and submitted; the
+engine admits queued requests into free slots whenever the HBM budget allows
+and iterates every resident instance together, one batched launch per PDHG
+half-step.  Finished solves leave their slot at the next check, and the slot
+and budget go to the next queued request.  The loop records arrival, admission
+and completion times; latency is completion minus arrival.
+
+Only argument marshalling and bookkeeping happen here; every step of the
+solve runs in the library.
+"""
+
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import uclp
+
+
+@dataclass
+class Served:
+    index: int
+    arrival_s: float            # scheduled arrival, relative to stream start
+    submit_s: float             # when the loop submitted it (>= arrival)
+    done_s: float               # when the loop observed completion
+    info: dict
+    x: Optional[np.ndarray] = None
+    y: Optional[np.ndarray] = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+@dataclass
+class StreamResult:
+    served: List[Served]
+    makespan_s: float
+    engine_slots: int
+    budget_bytes: int
+    stats: dict = field(default_factory=dict)
+
+
+def nearest_rank(values: Sequence[float], q: float) -> float:
+    v = sorted(values)
+    if not v:
+        return float("nan")
+    k = max(1, int(np.ceil(q / 100.0 * len(v))))
+    return v[k - 1]
+
+
+def run_stream(lps: Sequence, arrivals_s: Sequence[float], opts: uclp.uc_lp_opts, *,
+               max_slots: int = 64, hbm_budget_bytes: int = 200 << 30, keep_solutions: bool = False,
+               poll_s: float = 0.0005, device: int = 0, timeout_s: float = 600.0) -> StreamResult:
+    """Serve `lps` arriving at `arrivals_s` (seconds from start) on one engine."""
+    order = np.argsort(np.asarray(arrivals_s), kind="stable")
+    eng = uclp.uc_engine_create(device, int(hbm_budget_bytes), int(max_slots))
+    handles = {}
+    submit = {}
+    done = {}
+    infos = {}
+    sols = {}
+    try:
+        t0 = time.perf_counter()
+        nxt = 0
+        while len(done) < len(lps):
+            now = time.perf_counter() - t0
+            if now > timeout_s:
+                raise TimeoutError(f"stream not finished after {timeout_s} s")
+            while nxt < len(order) and arrivals_s[order[nxt]] <= now:
+                i = int(order[nxt])
+                h = uclp.uc_lp_create(lps[i], opts, engine=eng)
+                uclp.uc_lp_solve(h)
+                handles[i] = h
+                submit[i] = time.perf_counter() - t0
+                nxt += 1
+            for i, h in list(handles.items()):
+                if i in done:
+                    continue
+                info = uclp.uc_lp_status(h)
+                if info.status in uclp.TERMINAL:
+                    done[i] = time.perf_counter() - t0
+                    infos[i] = info.as_dict()
+                    if keep_solutions and info.status not in (uclp.UC_LP_INFEASIBLE, uclp.UC_LP_FAILED):
+                        sols[i] = uclp.uc_lp_get_solution(h, lps[i].n, lps[i].m)
+                    uclp.uc_lp_destroy(h)
+                    handles[i] = None
+            if len(done) < len(lps):
+                wait = poll_s
+                if nxt < len(order) and not any(h for h in handles.values()):
+                    wait = max(poll_s, arrivals_s[order[nxt]] - (time.perf_counter() - t0))
+                time.sleep(wait)
+        makespan = max(done.values()) - min(arrivals_s)
+    finally:
+        for h in handles.values():
+            if h:
+                uclp.uc_lp_destroy(h)
+        uclp.uc_engine_destroy(eng)
+    served = []
+    for i in range(len(lps)):
+        x, y = sols.get(i, (None, None))
+        served.append(Served(i, float(arrivals_s[i]), submit[i], done[i], infos[i], x, y))
+    lat = [s.latency_s for s in served]
+    stats = dict(n=len(served), p50_s=nearest_rank(lat, 50), p99_s=nearest_rank(lat, 99),
+                 max_s=max(lat), mean_s=float(np.mean(lat)), solves_per_s=len(served) / makespan,
+                 makespan_s=makespan,
+                 statuses={k: sum(1 for s in served if s.info["status_name"] == k)
+                           for k in sorted({s.info["status_name"] for s in served})},
+                 iters_total=int(sum(s.info["iters"] for s in served)))
+    return StreamResult(served, makespan, max_slots, hbm_budget_bytes, stats)

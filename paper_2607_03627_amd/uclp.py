@@ -35,7 +35,9 @@ class uc_lp_opts(C.Structure):
                 ("power_iters", C.c_int32), ("iter_limit", C.c_int64), ("eps_rel", C.c_double),
                 ("eps_abs_feas", C.c_double), ("eps_polish", C.c_double), ("time_limit_s", C.c_double),
                 ("step_scale", C.c_double), ("spmv_algo", C.c_int32), ("verbose", C.c_int32),
-                ("timing", C.c_int32), ("reserved", C.c_int32)]
+                ("timing", C.c_int32), ("restart_to_current", C.c_int32),
+                ("restart_sufficient", C.c_double), ("restart_necessary", C.c_double),
+                ("restart_artificial", C.c_double), ("pw_smoothing", C.c_double)]
 
 
 class uc_lp_info(C.Structure):
@@ -45,7 +47,8 @@ class uc_lp_info(C.Structure):
                 ("pobj", C.c_double), ("dobj", C.c_double), ("rel_primal", C.c_double),
                 ("rel_dual", C.c_double), ("rel_gap", C.c_double), ("rel_kkt", C.c_double),
                 ("abs_primal_inf", C.c_double), ("pobj_at_eps", C.c_double),
-                ("rel_kkt_at_eps", C.c_double), ("norm_a_est", C.c_double), ("omega", C.c_double),
+                ("rel_kkt_at_eps", C.c_double), ("iters_at_eps", C.c_int64),
+                ("norm_a_est", C.c_double), ("omega", C.c_double),
                 ("primal_kernel_us", C.c_double), ("dual_kernel_us", C.c_double),
                 ("timed_launches", C.c_int64), ("m_presolved", C.c_int32), ("n_presolved", C.c_int32),
                 ("nnz_presolved", C.c_int64), ("device_bytes", C.c_int64)]

@@ -1,0 +1,99 @@
+"""GPU tests of scenario batches: many LPs sharing one matrix, solved with one
+read of the matrix per half-step, against the oracle and against their own
+single-scenario solves."""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.kkt import kkt
+from paper_2607_03627_amd import uclp
+from paper_2607_03627_amd.instances import make_instance, scenario_data
+
+pytestmark = pytest.mark.gpu
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "objectives.json")))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def stack(lp, seeds):
+    data = [scenario_data(lp, s) for s in seeds]
+    return [np.stack([d[k] for d in data]) for k in range(4)]
+
+
+def batch(lp, seeds, **opts):
+    c, b, lb, ub = stack(lp, seeds)
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(**opts))
+    try:
+        return uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, c, b, lb, ub)
+    finally:
+        uclp.uc_lp_destroy(h)
+
+
+def test_medium_scenarios_match_highs_oracle():
+    lp = make_instance("medium", 0)
+    seeds = [1, 2, 3, 4]
+    say("case medium scenarios", seeds)
+    x, y, infos = batch(lp, seeds, precision=uclp.UC_LP_FP32_MIXED_POLISH, eps_polish=1e-8, iter_limit=400000)
+    for k, s in enumerate(seeds):
+        info = infos[k].as_dict()
+        say("  scen", s, info["status_name"], info["iters"], info["rel_kkt"])
+        assert info["status"] == uclp.UC_LP_OPTIMAL
+        c, b, lb, ub = scenario_data(lp, s)
+        sl = lp.with_data(c=c, b=b, lb=lb, ub=ub)
+        o = kkt(sl, x[k], y[k])
+        assert o.rel_kkt <= 1e-8 * 1.001
+        z = GOLDEN[f"medium_scen/0/{s}"]["obj"]
+        assert abs(o.pobj - z) <= 1e-6 * abs(z)
+
+
+def test_batch_equals_single_scenario_bitwise():
+    lp = make_instance("tiny", 6)
+    seeds = list(range(1, 17))
+    say("case tiny 16 scenarios")
+    opts = dict(precision=uclp.UC_LP_FP32_MIXED_POLISH, eps_polish=1e-7, iter_limit=200000)
+    x, y, infos = batch(lp, seeds, **opts)
+    for k in (0, 7, 15):
+        xs, ys, i1 = batch(lp, [seeds[k]], **opts)
+        assert infos[k].iters == i1[0].iters and infos[k].status == i1[0].status == uclp.UC_LP_OPTIMAL
+        assert np.array_equal(x[k], xs[0]) and np.array_equal(y[k], ys[0])
+    for k, s in enumerate(seeds):
+        c, b, lb, ub = scenario_data(lp, s)
+        o = kkt(lp.with_data(c=c, b=b, lb=lb, ub=ub), x[k], y[k])
+        assert o.rel_kkt <= 1e-7 * 1.001
+
+
+def test_warm_start_from_nominal_solution():
+    lp = make_instance("tiny", 7)
+    xn, yn, info = uclp.solve(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-8))
+    assert info["status"] == uclp.UC_LP_OPTIMAL
+    c, b, lb, ub = stack(lp, [1, 2, 3])
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED))
+    try:
+        cold = uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, c, b, lb, ub)
+        warm = uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, c, b, lb, ub, xn, yn)
+    finally:
+        uclp.uc_lp_destroy(h)
+    for k in range(3):
+        assert warm[2][k].status == uclp.UC_LP_OPTIMAL
+        cc, bb, ll, uu = scenario_data(lp, k + 1)
+        assert kkt(lp.with_data(c=cc, b=bb, lb=ll, ub=uu), warm[0][k], warm[1][k]).rel_kkt <= 1e-4
+    assert sum(i.iters for i in warm[2]) <= sum(i.iters for i in cold[2])
+
+
+def test_scenario_count_limits():
+    lp = make_instance("tiny", 0, n_periods=2)
+    c, b, lb, ub = stack(lp, range(1, 18))
+    h = uclp.uc_lp_create(lp)
+    try:
+        with pytest.raises(uclp.UcLpError) as e:
+            uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, c, b, lb, ub)
+        assert e.value.code == uclp.UC_LP_ENOTSUP
+    finally:
+        uclp.uc_lp_destroy(h)
