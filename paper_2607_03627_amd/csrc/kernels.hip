@@ -1274,6 +1274,9 @@ size_t radix_sort_temp_bytes(int64_t nnz, int n) {
   size_t bytes = 0;
   (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const int*)nullptr, (int*)nullptr,
                                      (const int*)nullptr, (int*)nullptr, (int)nnz, 0, key_bits(n));
+  // the size query may leave a non-sticky error behind; do not let a later
+  // hipGetLastError() (the sort itself ends with one) report it
+  (void)hipGetLastError();
   return bytes;
 }
 
@@ -1282,7 +1285,7 @@ int radix_sort_pairs(void* temp, size_t temp_bytes, const int* keys_in, int* key
   if (nnz == 0) return 0;
   hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in,
                                                     vals_out, (int)nnz, 0, key_bits(n), s);
-  return e == hipSuccess ? 0 : -1;
+  return (int)e;
 }
 
 void launch_scale_factor(int op, const int* ptr, const int* col, const double* val, const double* drow,

@@ -581,10 +581,23 @@ static int setup_device(uc_lp* lp) {
   HIPOK(hipMemcpyAsync(D.u_in, P.u.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
   if (m) HIPOK(hipMemcpyAsync(D.b_in, P.b.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
   // a1: A^T by a stable radix sort of the column indices
+  {
+    // an error left by an earlier call would otherwise be reported by the
+    // sort's own final hipGetLastError(); name it here instead
+    const hipError_t stale = hipGetLastError();
+    if (stale != hipSuccess)
+      return fail(UC_LP_EHIP, "an earlier HIP call failed before setup: %s", hipGetErrorName(stale));
+  }
   launch_expand_rows(D.a_ptr, m, D.row_of, s);
   launch_iota(D.perm_in, z, s);
-  if (radix_sort_pairs(D.sort_temp, D.sort_bytes, D.keys_in, D.keys_out, D.perm_in, D.perm_out, z, n, s))
-    return fail(UC_LP_EHIP, "radix sort failed");
+  HIPOK(hipGetLastError());
+  {
+    const int se = radix_sort_pairs(D.sort_temp, D.sort_bytes, D.keys_in, D.keys_out, D.perm_in, D.perm_out,
+                                    z, n, s);
+    if (se != 0)
+      return fail(UC_LP_EHIP, "radix sort of %lld column indices failed: %s (temp %zu bytes)", (long long)z,
+                  hipGetErrorName((hipError_t)se), D.sort_bytes);
+  }
   launch_gather_transpose(D.perm_out, D.row_of, D.a_raw, z, D.t_col, D.t_raw, s);
   // a2: Ruiz equilibration then Pock-Chambolle (alpha = 1)
   launch_fill(D.dr, 1.0, m, s);
@@ -818,7 +831,6 @@ static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
 static int engine_tables(uc_engine* E, size_t ntiles) {
   if (ntiles > E->tile_cap) {
     if (E->d_tiles) (void)hipFree(E->d_tiles);
-  if (E->d_scal) (void)hipFree(E->d_scal);
     E->d_tiles = nullptr;
     size_t cap = std::max<size_t>(ntiles, 2 * E->tile_cap);
     HIPOK(hipMalloc(&E->d_tiles, cap * sizeof(Tile)));

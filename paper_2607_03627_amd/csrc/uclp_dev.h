@@ -101,6 +101,7 @@ void launch_expand_rows(const int* ptr, int m, int* row_of, hipStream_t s);
 void launch_gather_transpose(const int* perm, const int* row_of, const double* val, int64_t nnz,
                              int* t_col, double* t_val, hipStream_t s);
 size_t radix_sort_temp_bytes(int64_t nnz, int n);
+// returns the hipError_t of the sort (0 = hipSuccess)
 int radix_sort_pairs(void* temp, size_t temp_bytes, const int* keys_in, int* keys_out,
                      const int* vals_in, int* vals_out, int64_t nnz, int n, hipStream_t s);
 void launch_iota(int* v, int64_t n, hipStream_t s);
