@@ -75,6 +75,77 @@ def cpu_baseline(target_nnz):
     }
 
 
+def serving_leg(seed=0, n_requests=64, eps=1e-8, iter_limit=400000):
+    """Poisson stream of differently sized UC LPs (Exp(50 ms) gaps, 300-2000 buses,
+    24 or 48 periods): continuous-batching FP32 + FP64 polish on one engine
+    against plain FP64 PDHG one request at a time (FIFO), same tolerance."""
+    from paper_2607_03627_amd import serving, uclp
+    from paper_2607_03627_amd.instances import make_instance, serving_stream
+
+    reqs = serving_stream(seed, n_requests)
+    lps = [make_instance(r.shape, r.seed) for r in reqs]
+    arr = [r.arrival_s for r in reqs]
+    out = {"requests": n_requests, "stream_seed": seed, "rel_kkt_target": eps,
+           "rows": [lp.m for lp in lps], "nnz_total": int(sum(lp.nnz for lp in lps))}
+    ob = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED_POLISH, eps_rel=1e-4, eps_polish=eps,
+                                 iter_limit=iter_limit)
+    rb = serving.run_stream(lps, arr, ob, max_slots=64, hbm_budget_bytes=200 << 30)
+    out["batched_fp32_polish"] = rb.stats
+    log(f"[bench] serving batched: {rb.stats}")
+    of = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=eps, iter_limit=iter_limit)
+    rf = serving.run_stream(lps, arr, of, max_slots=1, hbm_budget_bytes=200 << 30)
+    out["fp64_one_at_a_time"] = rf.stats
+    log(f"[bench] serving fp64 fifo: {rf.stats}")
+    out["throughput_ratio"] = rb.stats["solves_per_s"] / rf.stats["solves_per_s"]
+    out["worst_rel_kkt"] = {"batched": max(s.info["rel_kkt"] for s in rb.served),
+                            "fp64": max(s.info["rel_kkt"] for s in rf.served)}
+    return out
+
+
+def scenario_leg(base_lp, n_scen=16):
+    """Scenario batch over the shared matrix (load x U[0.85,1.15] per bus, cost
+    x U[0.95,1.05] per unit), warm-started from the nominal solution, against
+    sequential plain FP64 solves of the same scenarios, all to 1e-4."""
+    import numpy as np
+
+    from paper_2607_03627_amd import uclp
+    from paper_2607_03627_amd.instances import scenario_data
+
+    data = [scenario_data(base_lp, s) for s in range(1, n_scen + 1)]
+    c, b, lb, ub = (np.stack([d[k] for d in data]) for k in range(4))
+    out = {"scenarios": n_scen}
+    h = uclp.uc_lp_create(base_lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-4))
+    try:
+        t = time.perf_counter()
+        uclp.uc_lp_solve(h)
+        uclp.uc_lp_wait(h, 600)
+        xn, yn = uclp.uc_lp_get_solution(h, base_lp.n, base_lp.m)
+        out["nominal_s"] = time.perf_counter() - t
+        t = time.perf_counter()
+        x, y, infos = uclp.uc_lp_solve_scenarios(h, base_lp.n, base_lp.m, c, b, lb, ub, xn, yn)
+        out["batch_warm_s"] = time.perf_counter() - t
+        out["batch_iters"] = [i.iters for i in infos]
+        out["batch_status"] = [uclp.STATUS_NAMES[i.status] for i in infos]
+        out["batch_rel_kkt_max"] = max(i.rel_kkt for i in infos)
+    finally:
+        uclp.uc_lp_destroy(h)
+    log(f"[bench] scenarios batch: {out}")
+    seq = 0.0
+    its = []
+    for k in range(n_scen):
+        lp_k = base_lp.with_data(c=c[k], b=b[k], lb=lb[k], ub=ub[k])
+        t = time.perf_counter()
+        _, _, info = uclp.solve(lp_k, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-4),
+                                timeout_s=600)
+        seq += info["t_total_s"]
+        its.append(info["iters"])
+    out["sequential_fp64_cold_s"] = seq
+    out["sequential_iters"] = its
+    out["speedup_vs_sequential"] = seq / out["batch_warm_s"]
+    log(f"[bench] scenarios sequential: {seq:.2f}s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +157,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--iter-limit", type=int, default=100000,
                     help="iteration limit of each solve (short runs for hardware counters)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream leg")
+    ap.add_argument("--scenarios", action="store_true", help="also run the 16-scenario batch leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -204,6 +277,16 @@ def main():
             ex["obj_err_fp32_at_1e-4_vs_polished"] = abs(last["pobj"] - pstar) / abs(pstar)
         except Exception as e:  # extras never hide the main line
             out["extra"]["extra_error"] = repr(e)
+    if not args.no_serving:
+        try:
+            out["serving"] = serving_leg()
+        except Exception as e:
+            out["serving"] = {"error": repr(e)}
+    if args.scenarios:
+        try:
+            out["scenarios"] = scenario_leg(lp)
+        except Exception as e:
+            out["scenarios"] = {"error": repr(e)}
     if not args.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(lp.nnz)

@@ -3,9 +3,10 @@
  * relaxations on one AMD Instinct MI355X (gfx950).
  *
  * The problem is the continuous relaxation that both legs of the paper's
- * concurrent GPU-CPU solver hand to their LP method (Sec. II-C: the GPU leg
- * solves "the relaxed linear problem" with PDHG, the CPU leg the same problem
- * with barrier; Sec. III-C: PDHG replaces the barrier solve):
+ * concurrent GPU-CPU solver hand to their LP method (Sec. II-C: PDHG on the
+ * GPU and barrier on CPU threads work on the same LP relaxation of the unit
+ * commitment MILP; Sec. III-C: in the GPU pipeline PDHG takes the place of
+ * the barrier solve):
  *
  *     min c'x   s.t.  a_i'x  = b_i   (sense 'E')
  *                     a_i'x >= b_i   (sense 'G')
@@ -104,10 +105,13 @@ typedef struct {
   /* adaptive restart on the fixed-point residual r = ||z - T(z)||_P, checked
      every kkt_every iterations (Applegate et al. 2021; Lu & Yang 2024) */
   double restart_sufficient;  /* restart if r <= this * r(restart start), 0.2 */
-  double restart_necessary;   /* ... or r <= this * r(start) and r grew, 0.8  */
+  double restart_necessary;   /* ... or r <= this * r(start) and r grew, 0.9  */
   double restart_artificial;  /* ... or inner iterations >= this * total, 0.36 */
   double pw_smoothing;   /* primal weight: log w <- s log(dy/dx) + (1-s) log w
-                            at each restart, default 0.5; 0 keeps w fixed      */
+                            at each restart, default 0.8; 0 keeps w fixed.
+                            (The published PDLP values are 0.8 necessary and
+                            0.5 smoothing; 0.9 / 0.8 took fewer iterations to
+                            1e-4 on every synthetic UC family measured.)      */
 } uc_lp_opts;
 
 typedef struct {

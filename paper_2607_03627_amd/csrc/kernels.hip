@@ -188,11 +188,10 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int r0 = S.t_blk[tl.blk];
-  const int r1 = S.t_blk[tl.blk + 1];
+  const int r0 = tl.r0, r1 = tl.r1;
   const int* __restrict__ ptr = S.t_ptr;
-  const int k0 = ptr[r0];
-  const int nz = ptr[r1] - k0;
+  const int k0 = tl.k0;
+  const int nz = tl.k1 - k0;
   const int j = r0 + threadIdx.x;
   const bool own = j < r1;
   // epilogue operands first, so their loads overlap the gathers
@@ -245,11 +244,10 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int r0 = S.a_blk[tl.blk];
-  const int r1 = S.a_blk[tl.blk + 1];
+  const int r0 = tl.r0, r1 = tl.r1;
   const int* __restrict__ ptr = S.a_ptr;
-  const int k0 = ptr[r0];
-  const int nz = ptr[r1] - k0;
+  const int k0 = tl.k0;
+  const int nz = tl.k1 - k0;
   const int i = r0 + threadIdx.x;
   const bool own = i < r1;
   int a = 0, b = 0;
@@ -298,15 +296,14 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int r0 = S.a_blk[tl.blk];
-  const int r1 = S.a_blk[tl.blk + 1];
+  const int r0 = tl.r0, r1 = tl.r1;
   const int* __restrict__ ptr = S.a_ptr;
   const int* __restrict__ col = S.a_col;
   const double* __restrict__ val = S.d.av;
   const T* __restrict__ xh = V.xhat;
   const T* __restrict__ x = V.x;
-  const int k0 = ptr[r0];
-  const int k1 = ptr[r1];
+  const int k0 = tl.k0;
+  const int k1 = tl.k1;
   const int nz = k1 - k0;
   double q[RQ_N] = {0, 0, 0, 0, 0, 0, 0};
   const bool is_max[RQ_N] = {false, false, false, false, false, false, true};
@@ -394,8 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_kkt_cols(const SlotDev* __restrict
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int r0 = S.t_blk[tl.blk];
-  const int r1 = S.t_blk[tl.blk + 1];
+  const int r0 = tl.r0, r1 = tl.r1;
   const int* __restrict__ col = S.t_col;
   const double* __restrict__ val = S.d.tv;
   const T* __restrict__ yh = V.yhat;
@@ -475,8 +471,8 @@ __global__ __launch_bounds__(kThreads) void k_finish_x(const SlotDev* __restrict
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int j = S.t_blk[tl.blk] + threadIdx.x;
-  if (j >= S.t_blk[tl.blk + 1]) return;
+  const int j = tl.r0 + threadIdx.x;
+  if (j >= tl.r1) return;
   if (S.restart[0] == 1) {
     const T xh = V.xhat[j];
     V.x[j] = xh;
@@ -500,8 +496,8 @@ __global__ __launch_bounds__(kThreads) void k_finish_y(const SlotDev* __restrict
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int i = S.a_blk[tl.blk] + threadIdx.x;
-  if (i >= S.a_blk[tl.blk + 1]) return;
+  const int i = tl.r0 + threadIdx.x;
+  if (i >= tl.r1) return;
   if (S.restart[0] == 1) {
     const T yh = V.yhat[i];
     V.y[i] = yh;
@@ -523,8 +519,8 @@ __global__ __launch_bounds__(kThreads) void k_promote_x(const SlotDev* __restric
   if (t < 0) return;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
-  const int j = S.t_blk[tl.blk] + threadIdx.x;
-  if (j >= S.t_blk[tl.blk + 1]) return;
+  const int j = tl.r0 + threadIdx.x;
+  if (j >= tl.r1) return;
   const double v = (double)S.f.xhat[j];
   S.d.x[j] = v;
   S.d.x0[j] = v;
@@ -537,8 +533,8 @@ __global__ __launch_bounds__(kThreads) void k_promote_y(const SlotDev* __restric
   if (t < 0) return;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
-  const int i = S.a_blk[tl.blk] + threadIdx.x;
-  if (i >= S.a_blk[tl.blk + 1]) return;
+  const int i = tl.r0 + threadIdx.x;
+  if (i >= tl.r1) return;
   const double v = (double)S.f.yhat[i];
   S.d.y[i] = v;
   S.d.y0[i] = v;
@@ -576,10 +572,10 @@ __global__ __launch_bounds__(kThreads) void k_primal_ms(const SlotDev* __restric
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int r0 = S.t_blk[tl.blk], r1 = S.t_blk[tl.blk + 1];
+  const int r0 = tl.r0, r1 = tl.r1;
   const int* __restrict__ ptr = S.t_ptr;
-  const int k0 = ptr[r0];
-  const int nz = ptr[r1] - k0;
+  const int k0 = tl.k0;
+  const int nz = tl.k1 - k0;
   const bool staged = nz <= kNnzTile;
   if (staged) stage_entries<T>(S.t_col + k0, V.tv + k0, nz, lc, lv);
   __syncthreads();
@@ -619,10 +615,10 @@ __global__ __launch_bounds__(kThreads) void k_dual_ms(const SlotDev* __restrict_
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int r0 = S.a_blk[tl.blk], r1 = S.a_blk[tl.blk + 1];
+  const int r0 = tl.r0, r1 = tl.r1;
   const int* __restrict__ ptr = S.a_ptr;
-  const int k0 = ptr[r0];
-  const int nz = ptr[r1] - k0;
+  const int k0 = tl.k0;
+  const int nz = tl.k1 - k0;
   const bool staged = nz <= kNnzTile;
   if (staged) stage_entries<T>(S.a_col + k0, V.av + k0, nz, lc, lv);
   __syncthreads();
@@ -683,10 +679,10 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows_ms(const SlotDev* __restr
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int r0 = S.a_blk[tl.blk], r1 = S.a_blk[tl.blk + 1];
+  const int r0 = tl.r0, r1 = tl.r1;
   const int* __restrict__ ptr = S.a_ptr;
-  const int k0 = ptr[r0];
-  const int nz = ptr[r1] - k0;
+  const int k0 = tl.k0;
+  const int nz = tl.k1 - k0;
   const bool staged = nz <= kNnzTile;
   if (staged) stage_entries<double>(S.a_col + k0, S.d.av + k0, nz, lc, lv);
   __syncthreads();
@@ -736,10 +732,10 @@ __global__ __launch_bounds__(kThreads) void k_kkt_cols_ms(const SlotDev* __restr
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int r0 = S.t_blk[tl.blk], r1 = S.t_blk[tl.blk + 1];
+  const int r0 = tl.r0, r1 = tl.r1;
   const int* __restrict__ ptr = S.t_ptr;
-  const int k0 = ptr[r0];
-  const int nz = ptr[r1] - k0;
+  const int k0 = tl.k0;
+  const int nz = tl.k1 - k0;
   const bool staged = nz <= kNnzTile;
   if (staged) stage_entries<double>(S.t_col + k0, S.d.tv + k0, nz, lc, lv);
   __syncthreads();

@@ -93,9 +93,9 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->timing = 0;
   o->restart_to_current = 0;
   o->restart_sufficient = 0.2;
-  o->restart_necessary = 0.8;
+  o->restart_necessary = 0.9;
   o->restart_artificial = 0.36;
-  o->pw_smoothing = 0.5;
+  o->pw_smoothing = 0.8;
 }
 
 static int check_opts(const uc_lp_opts& o) {
@@ -194,6 +194,22 @@ struct HostProblem {
   double norm_b = 0.0, norm_c = 0.0;
   bool infeasible = false;
 };
+
+// Tiles of one matrix of one slot: rows [r0, r1) and entries [k0, k1) of each
+// row block, taken from the host copies of the partition and row pointers.
+static void push_tiles(std::vector<Tile>& v, int slot, const std::vector<int>& blk, const std::vector<int>& ptr) {
+  for (size_t b = 0; b + 1 < blk.size(); ++b) {
+    Tile t;
+    t.slot = slot;
+    t.blk = (int)b;
+    t.r0 = blk[b];
+    t.r1 = blk[b + 1];
+    t.k0 = ptr[t.r0];
+    t.k1 = ptr[t.r1];
+    t.pad0 = t.pad1 = 0;
+    v.push_back(t);
+  }
+}
 
 // Data-dependent part of the presolve (right-hand side shift, objective
 // offset, norms, feasibility of removed rows).  The structure (which columns
@@ -935,8 +951,8 @@ static void run_epochs(uc_engine* E) {
     for (int a = 0; a < A; ++a) {
       ids[a] = a;
       const int p = sig[a].second;
-      for (int b = 0; b < E->h_slots[a].t_nblk; ++b) tt[p].push_back({a, b});
-      for (int b = 0; b < E->h_slots[a].a_nblk; ++b) at[p].push_back({a, b});
+      push_tiles(tt[p], a, E->active[a]->P.t_blk, E->active[a]->P.t_ptr);
+      push_tiles(at[p], a, E->active[a]->P.a_blk, E->active[a]->P.a_ptr);
     }
     E->nT1 = (int)tt[1].size();
     E->nT0 = (int)tt[0].size();
@@ -1023,8 +1039,8 @@ static void run_epochs(uc_engine* E) {
   std::vector<Tile> pt, pa, both;
   for (int a = 0; a < A; ++a)
     if (outs[a].promote) {
-      for (int b = 0; b < E->h_slots[a].t_nblk; ++b) pt.push_back({a, b});
-      for (int b = 0; b < E->h_slots[a].a_nblk; ++b) pa.push_back({a, b});
+      push_tiles(pt, a, E->active[a]->P.t_blk, E->active[a]->P.t_ptr);
+      push_tiles(pa, a, E->active[a]->P.a_blk, E->active[a]->P.a_ptr);
     }
   if (!pt.empty() || !pa.empty()) {
     // reuse the tile buffer after the epoch's kernels (same stream, ordered)
@@ -1458,8 +1474,8 @@ static int debug_step_t(uc_lp* lp, const double* x, const double* y, const doubl
   S.k0[0] = k;
   S.active[0] = 1;
   std::vector<Tile> tl;
-  for (int b = 0; b < S.t_nblk; ++b) tl.push_back({0, b});
-  for (int b = 0; b < S.a_nblk; ++b) tl.push_back({0, b});
+  push_tiles(tl, 0, P.t_blk, P.t_ptr);
+  push_tiles(tl, 0, P.a_blk, P.a_ptr);
   E->layout.clear();  // the engine's tile and slot tables are overwritten below
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
@@ -1520,8 +1536,8 @@ extern "C" int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp
     if ((rc = put_vec<double>(dst, yi.data(), P.mi, s))) return rc;
   SlotDev S = make_slot(lp);
   std::vector<Tile> tl;
-  for (int b = 0; b < S.t_nblk; ++b) tl.push_back({0, b});
-  for (int b = 0; b < S.a_nblk; ++b) tl.push_back({0, b});
+  push_tiles(tl, 0, P.t_blk, P.t_ptr);
+  push_tiles(tl, 0, P.a_blk, P.a_ptr);
   E->layout.clear();  // the engine's tile and slot tables are overwritten below
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
@@ -1904,8 +1920,8 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   launch_init_iterates(A.slot_dev, phase, xin, yin, ni, mi, P.m_eq, S, st);
   std::vector<Tile> tl;
   const int nt = (int)P.t_blk.size() - 1, na = (int)P.a_blk.size() - 1;
-  for (int bb = 0; bb < nt; ++bb) tl.push_back({0, bb});
-  for (int bb = 0; bb < na; ++bb) tl.push_back({0, bb});
+  push_tiles(tl, 0, P.t_blk, P.t_ptr);
+  push_tiles(tl, 0, P.a_blk, P.a_ptr);
   SCEN_HIP(hipMemcpyAsync(A.tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
   SCEN_HIP(hipStreamSynchronize(st));
   const Tile* TT = A.tiles;

@@ -63,9 +63,15 @@ struct SlotDev {
   int active[kMaxScen];         // 0: scenario frozen (converged)
 };
 
+// One unit of work of the batched kernels: a row block of one slot, with its
+// row range [r0, r1) and entry range [k0, k1) precomputed on the host so a
+// workgroup needs a single 32-byte load before it can issue its data loads.
 struct Tile {
   int slot;
   int blk;
+  int r0, r1;
+  int k0, k1;
+  int pad0, pad1;
 };
 
 // ---- launchers (kernels.hip) --------------------------------------------

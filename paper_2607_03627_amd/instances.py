@@ -1,8 +1,8 @@
 """Seeded synthetic DC unit-commitment LP relaxations.
 
 The paper solves the continuous relaxation of a multi-period unit-commitment
-MILP (Sec. II-A, II-C: the relaxed linear problem handed to PDHG on the GPU and
-to barrier on the CPU) on the 6,049-bus GO Challenge 3 system (Sec. II-E,
+MILP (Sec. II-A; Sec. II-C gives that LP relaxation to PDHG on the GPU and to
+barrier on the CPU) on the 6,049-bus GO Challenge 3 system (Sec. II-E,
 Table I).  Those data sets are not available here, so this module builds DC
 unit-commitment LPs of the same structure from random draws:
 

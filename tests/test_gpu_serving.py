@@ -89,7 +89,9 @@ def test_cancel_one_request_in_a_batch():
     eng = uclp.uc_engine_create(0, 0, 8)
     hs = []
     try:
-        slow = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-14, iter_limit=10 ** 7)
+        # a tolerance below the FP64 rounding floor of the KKT error is never met
+        slow = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-30, iter_limit=10 ** 8,
+                                       time_limit_s=120)
         fast = uclp.uc_lp_opts_default(**OPTS)
         for i, lp in enumerate(lps):
             h = uclp.uc_lp_create(lp, slow if i == 1 else fast, engine=eng)

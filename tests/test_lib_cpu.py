@@ -43,7 +43,7 @@ def test_binding_structs_match_header_layout():
     assert o.precision == uclp.UC_LP_FP32_MIXED_POLISH and o.kkt_every == 64
     assert o.iter_limit == 100000 and o.eps_rel == 1e-4 and o.eps_polish == 1e-8
     assert (o.restart_sufficient, o.restart_necessary, o.restart_artificial, o.pw_smoothing) == \
-        (0.2, 0.8, 0.36, 0.5)
+        (0.2, 0.9, 0.36, 0.8)
 
 
 def small():
