@@ -98,7 +98,7 @@ typedef struct {
   int32_t spmv_algo;     /* uc_lp_spmv_algo; the PDHG half-steps support
                             UC_LP_SPMV_ROWSPLIT only (ENOTSUP otherwise)       */
   int32_t verbose;       /* 0 = silent, 1 = one line per check on stderr       */
-  int32_t timing;        /* 1 = time the first primal and dual launch of each
+  int32_t timing;        /* 1 = time the middle primal and dual launch of each
                             check interval with dispatch-attached HIP events   */
   int32_t restart_to_current; /* 0: restart at the PDHG output T(z) (default);
                             1: restart at the current Halpern iterate z         */

@@ -2,7 +2,7 @@
 //
 // Every hot kernel walks a list of tiles (slot, row block).  A row block is a
 // run of consecutive CSR rows holding at most kRowsPerBlock rows and
-// kNnzTile entries (or one longer row).  The 256 threads of a workgroup
+// kNnzTile entries (or one longer row).  The kThreads threads of a workgroup
 // first load the block's entries with coalesced reads, multiply them by the
 // gathered vector entries and stage the products in LDS; then thread t sums
 // row r0 + t from LDS in CSR order and runs the per-row epilogue
@@ -87,29 +87,26 @@ __device__ inline void block_reduce(double (&v)[NQ], const bool (&is_max)[NQ], d
 }
 
 // Row sums of one row block: products val[k] * g(k) staged in LDS, then summed
-// per row.  Returns true in the thread that owns a row; `row` and `sum` are
-// set there.  Long rows (one row above kNnzTile) are reduced by the whole
-// block and reported by thread 0.
-template <typename ACC, typename Prod>
-__device__ inline bool block_row_sum(const int* __restrict__ ptr, int r0, int r1, ACC* lds,
-                                     ACC* red, Prod prod, int& row, ACC& sum) {
+// per row in CSR order.  Thread t owns rows r0 + t + q * kThreads; f(row, sum)
+// runs once per owned row.  A long row (one row above kNnzTile) is reduced by
+// the whole block and reported to thread 0.
+template <typename ACC, typename Prod, typename F>
+__device__ inline void block_rows(const int* __restrict__ ptr, int r0, int r1, ACC* lds, ACC* red,
+                                  Prod prod, F f) {
   const int k0 = ptr[r0];
   const int k1 = ptr[r1];
   const int nz = k1 - k0;
   if (nz <= kNnzTile) {
     for (int k = threadIdx.x; k < nz; k += kThreads) lds[k] = prod(k0 + k);
     __syncthreads();
-    const int r = r0 + threadIdx.x;
-    if (r < r1) {
+    for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
       const int a = ptr[r] - k0;
       const int b = ptr[r + 1] - k0;
       ACC s = 0;
       for (int k = a; k < b; ++k) s += lds[k];
-      row = r;
-      sum = s;
-      return true;
+      f(r, s);
     }
-    return false;
+    return;
   }
   // one long row
   ACC s = 0;
@@ -121,11 +118,8 @@ __device__ inline bool block_row_sum(const int* __restrict__ ptr, int r0, int r1
   if (threadIdx.x == 0) {
     ACC t = red[0];
     for (int w = 1; w < kThreads / 64; ++w) t += red[w];
-    row = r0;
-    sum = t;
-    return true;
+    f(r0, t);
   }
-  return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -177,6 +171,7 @@ __device__ inline T long_row_sum(const int* __restrict__ col, const T* __restric
 //   g = c_j - (A^T y)_j ; x_hat = clamp(x - tau g, l, u) ; xbar = 2 x_hat - x
 //   non-check: x <- w xbar + (1 - w) x0,  w = (k + 1)/(k + 2), 1 - w = 1/(k + 2)
 //   check:     x_hat stored, x kept for the residuals
+// Thread t handles rows r0 + t + q * kThreads, q < kRowsPerThread.
 template <typename T, bool CHECK>
 __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__ slots,
                                                      const Tile* __restrict__ tiles, int ntiles,
@@ -192,41 +187,51 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   const int* __restrict__ ptr = S.t_ptr;
   const int k0 = tl.k0;
   const int nz = tl.k1 - k0;
-  const int j = r0 + threadIdx.x;
-  const bool own = j < r1;
   // epilogue operands first, so their loads overlap the gathers
-  int a = 0, b = 0;
-  T c = 0, l = 0, u = 0, x = 0, xa = 0;
-  if (own) {
-    a = ptr[j] - k0;
-    b = ptr[j + 1] - k0;
-    c = V.c[j];
-    l = V.l[j];
-    u = V.u[j];
-    x = V.x[j];
-    if (!CHECK) xa = V.x0[j];
+  int a[kRowsPerThread], b[kRowsPerThread];
+  T c[kRowsPerThread], l[kRowsPerThread], u[kRowsPerThread], x[kRowsPerThread], xa[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int j = r0 + threadIdx.x + q * kThreads;
+    a[q] = b[q] = 0;
+    c[q] = l[q] = u[q] = x[q] = xa[q] = 0;
+    if (j < r1) {
+      a[q] = ptr[j] - k0;
+      b[q] = ptr[j + 1] - k0;
+      c[q] = V.c[j];
+      l[q] = V.l[j];
+      u[q] = V.u[j];
+      x[q] = V.x[j];
+      if (!CHECK) xa[q] = V.x0[j];
+    }
   }
-  T s = 0;
+  T s[kRowsPerThread];
   if (nz <= kNnzTile) {
     stage_products<T, T>(S.t_col + k0, V.tv + k0, V.y, nz, lds);
     __syncthreads();
-    if (!own) return;
-    for (int k = a; k < b; ++k) s += lds[k];
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+      T acc = 0;
+      for (int k = a[q]; k < b[q]; ++k) acc += lds[k];
+      s[q] = acc;
+    }
   } else {
-    s = long_row_sum<T, T>(S.t_col + k0, V.tv + k0, V.y, nz, red);
+    s[0] = long_row_sum<T, T>(S.t_col + k0, V.tv + k0, V.y, nz, red);
     if (threadIdx.x != 0) return;
   }
   const T tau = (T)S.tau[0];
-  const T xh = clampv<T>(x - tau * (c - s), l, u);
-  const T xb = (T)2 * xh - x;
-  V.xbar[j] = xb;
-  if (CHECK) {
-    V.xhat[j] = xh;
-  } else {
-    const double kk = (double)(S.k0[0] + jiter);
-    const T w = (T)((kk + 1.0) / (kk + 2.0));
-    const T wa = (T)(1.0 / (kk + 2.0));
-    V.x[j] = w * xb + wa * xa;
+  const double kk = (double)(S.k0[0] + jiter);
+  const T w = (T)((kk + 1.0) / (kk + 2.0));
+  const T wa = (T)(1.0 / (kk + 2.0));
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int j = r0 + threadIdx.x + q * kThreads;
+    if (j >= r1) break;
+    const T xh = clampv<T>(x[q] - tau * (c[q] - s[q]), l[q], u[q]);
+    const T xb = (T)2 * xh - x[q];
+    V.xbar[j] = xb;
+    if (CHECK) V.xhat[j] = xh;
+    else V.x[j] = w * xb + wa * xa[q];
   }
 }
 
@@ -248,37 +253,47 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
   const int* __restrict__ ptr = S.a_ptr;
   const int k0 = tl.k0;
   const int nz = tl.k1 - k0;
-  const int i = r0 + threadIdx.x;
-  const bool own = i < r1;
-  int a = 0, b = 0;
-  T bi = 0, y = 0, ya = 0;
-  if (own) {
-    a = ptr[i] - k0;
-    b = ptr[i + 1] - k0;
-    bi = V.b[i];
-    y = V.y[i];
-    if (!CHECK) ya = V.y0[i];
+  int a[kRowsPerThread], b[kRowsPerThread];
+  T bi[kRowsPerThread], y[kRowsPerThread], ya[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int i = r0 + threadIdx.x + q * kThreads;
+    a[q] = b[q] = 0;
+    bi[q] = y[q] = ya[q] = 0;
+    if (i < r1) {
+      a[q] = ptr[i] - k0;
+      b[q] = ptr[i + 1] - k0;
+      bi[q] = V.b[i];
+      y[q] = V.y[i];
+      if (!CHECK) ya[q] = V.y0[i];
+    }
   }
-  T s = 0;
+  T s[kRowsPerThread];
   if (nz <= kNnzTile) {
     stage_products<T, T>(S.a_col + k0, V.av + k0, V.xbar, nz, lds);
     __syncthreads();
-    if (!own) return;
-    for (int k = a; k < b; ++k) s += lds[k];
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+      T acc = 0;
+      for (int k = a[q]; k < b[q]; ++k) acc += lds[k];
+      s[q] = acc;
+    }
   } else {
-    s = long_row_sum<T, T>(S.a_col + k0, V.av + k0, V.xbar, nz, red);
+    s[0] = long_row_sum<T, T>(S.a_col + k0, V.av + k0, V.xbar, nz, red);
     if (threadIdx.x != 0) return;
   }
   const T sigma = (T)S.sigma[0];
-  T yh = y + sigma * (bi - s);
-  if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
-  if (CHECK) {
-    V.yhat[i] = yh;
-  } else {
-    const double kk = (double)(S.k0[0] + jiter);
-    const T w = (T)((kk + 1.0) / (kk + 2.0));
-    const T wa = (T)(1.0 / (kk + 2.0));
-    V.y[i] = w * ((T)2 * yh - y) + wa * ya;
+  const double kk = (double)(S.k0[0] + jiter);
+  const T w = (T)((kk + 1.0) / (kk + 2.0));
+  const T wa = (T)(1.0 / (kk + 2.0));
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int i = r0 + threadIdx.x + q * kThreads;
+    if (i >= r1) break;
+    T yh = y[q] + sigma * (bi[q] - s[q]);
+    if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
+    if (CHECK) V.yhat[i] = yh;
+    else V.y[i] = w * ((T)2 * yh - y[q]) + wa * ya[q];
   }
 }
 
@@ -307,8 +322,23 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict
   const int nz = k1 - k0;
   double q[RQ_N] = {0, 0, 0, 0, 0, 0, 0};
   const bool is_max[RQ_N] = {false, false, false, false, false, false, true};
-  int row = -1;
-  double s1 = 0, s2 = 0;
+  auto row_terms = [&](int row, double s1, double s2) {
+    double r = S.d.b[row] - s1;
+    if (row >= S.m_eq) r = r > 0.0 ? r : 0.0;
+    const double ru = r / S.dr[row];
+    const double yh = (double)V.yhat[row];
+    const double dy = yh - (double)V.y[row];
+    const double d0 = yh - (double)V.y0[row];
+    q[RQ_RES2] += ru * ru;
+    q[RQ_BY] += S.d.b[row] * yh;
+    q[RQ_DY2] += dy * dy;
+    q[RQ_DYADX] += dy * s2;
+    q[RQ_DY0] += d0 * d0;
+    // dual sign violation of an inequality row, unscaled (zero for projected iterates)
+    const double yneg = row >= S.m_eq && yh < 0.0 ? yh * S.dr[row] : 0.0;
+    q[RQ_YNEG2] += yneg * yneg;
+    q[RQ_RESMAX] = fmax(q[RQ_RESMAX], fabs(ru));
+  };
   if (nz <= kNnzTile) {
     for (int k = threadIdx.x; k < nz; k += kThreads) {
       const int c = col[k0 + k];
@@ -318,15 +348,16 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict
       lds2[k] = v * (a - (double)x[c]);
     }
     __syncthreads();
-    const int r = r0 + threadIdx.x;
-    if (r < r1) {
+    for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
+      double s1 = 0, s2 = 0;
       for (int k = ptr[r] - k0; k < ptr[r + 1] - k0; ++k) {
         s1 += lds1[k];
         s2 += lds2[k];
       }
-      row = r;
+      row_terms(r, s1, s2);
     }
   } else {
+    double s1 = 0, s2 = 0;
     for (int k = k0 + threadIdx.x; k < k1; k += kThreads) {
       const int c = col[k];
       const double a = (double)xh[c];
@@ -350,25 +381,8 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict
         s1 += lds1[w];
         s2 += lds2[w];
       }
-      row = r0;
+      row_terms(r0, s1, s2);
     }
-  }
-  if (row >= 0) {
-    double r = S.d.b[row] - s1;
-    if (row >= S.m_eq) r = r > 0.0 ? r : 0.0;
-    const double ru = r / S.dr[row];
-    const double yh = (double)V.yhat[row];
-    const double dy = yh - (double)V.y[row];
-    const double d0 = yh - (double)V.y0[row];
-    q[RQ_RES2] = ru * ru;
-    q[RQ_BY] = S.d.b[row] * yh;
-    q[RQ_DY2] = dy * dy;
-    q[RQ_DYADX] = dy * s2;
-    q[RQ_DY0] = d0 * d0;
-    // dual sign violation of an inequality row, unscaled (zero for projected iterates)
-    const double yneg = row >= S.m_eq && yh < 0.0 ? yh * S.dr[row] : 0.0;
-    q[RQ_YNEG2] = yneg * yneg;
-    q[RQ_RESMAX] = fabs(ru);
   }
   __syncthreads();
   block_reduce<RQ_N>(q, is_max, red);
@@ -397,31 +411,28 @@ __global__ __launch_bounds__(kThreads) void k_kkt_cols(const SlotDev* __restrict
   const T* __restrict__ yh = V.yhat;
   double q[CQ_N] = {0, 0, 0, 0, 0};
   const bool is_max[CQ_N] = {false, false, false, false, false};
-  int j = -1;
-  double s = 0;
-  const bool own = block_row_sum<double>(S.t_ptr, r0, r1, lds, red,
-                                         [&](int k) { return val[k] * (double)yh[col[k]]; }, j, s);
-  if (own) {
-    const double c = S.d.c[j];
-    const double l = S.d.l[j];
-    const double u = S.d.u[j];
-    const double dh = c - s;
-    const bool fl = isfinite(l);
-    const bool fu = isfinite(u);
-    double lam = 0.0;
-    if (fl && fu) lam = dh;
-    else if (fl) lam = dh > 0.0 ? dh : 0.0;
-    else if (fu) lam = dh < 0.0 ? dh : 0.0;
-    const double dres = (dh - lam) / S.dc[j];
-    const double xhv = (double)V.xhat[j];
-    const double dx = xhv - (double)V.x[j];
-    const double d0 = xhv - (double)V.x0[j];
-    q[CQ_DRES2] = dres * dres;
-    q[CQ_LBUB] = (lam > 0.0 ? l * lam : 0.0) + (lam < 0.0 ? u * lam : 0.0);
-    q[CQ_CX] = c * xhv;
-    q[CQ_DX2] = dx * dx;
-    q[CQ_DX0] = d0 * d0;
-  }
+  block_rows<double>(S.t_ptr, r0, r1, lds, red, [&](int k) { return val[k] * (double)yh[col[k]]; },
+                     [&](int j, double s) {
+                       const double c = S.d.c[j];
+                       const double l = S.d.l[j];
+                       const double u = S.d.u[j];
+                       const double dh = c - s;
+                       const bool fl = isfinite(l);
+                       const bool fu = isfinite(u);
+                       double lam = 0.0;
+                       if (fl && fu) lam = dh;
+                       else if (fl) lam = dh > 0.0 ? dh : 0.0;
+                       else if (fu) lam = dh < 0.0 ? dh : 0.0;
+                       const double dres = (dh - lam) / S.dc[j];
+                       const double xhv = (double)V.xhat[j];
+                       const double dx = xhv - (double)V.x[j];
+                       const double d0 = xhv - (double)V.x0[j];
+                       q[CQ_DRES2] += dres * dres;
+                       q[CQ_LBUB] += (lam > 0.0 ? l * lam : 0.0) + (lam < 0.0 ? u * lam : 0.0);
+                       q[CQ_CX] += c * xhv;
+                       q[CQ_DX2] += dx * dx;
+                       q[CQ_DX0] += d0 * d0;
+                     });
   __syncthreads();
   block_reduce<CQ_N>(q, is_max, red);
   if (threadIdx.x == 0) {
@@ -471,19 +482,19 @@ __global__ __launch_bounds__(kThreads) void k_finish_x(const SlotDev* __restrict
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int j = tl.r0 + threadIdx.x;
-  if (j >= tl.r1) return;
-  if (S.restart[0] == 1) {
-    const T xh = V.xhat[j];
-    V.x[j] = xh;
-    V.x0[j] = xh;
-  } else {
-    const double k = (double)(S.k0[0] + kk);
-    const T w = (T)((k + 1.0) / (k + 2.0));
-    const T wa = (T)(1.0 / (k + 2.0));
-    const T xn = w * V.xbar[j] + wa * V.x0[j];
-    V.x[j] = xn;
-    if (S.restart[0] == 2) V.x0[j] = xn;
+  const double k = (double)(S.k0[0] + kk);
+  const T w = (T)((k + 1.0) / (k + 2.0));
+  const T wa = (T)(1.0 / (k + 2.0));
+  for (int j = tl.r0 + threadIdx.x; j < tl.r1; j += kThreads) {
+    if (S.restart[0] == 1) {
+      const T xh = V.xhat[j];
+      V.x[j] = xh;
+      V.x0[j] = xh;
+    } else {
+      const T xn = w * V.xbar[j] + wa * V.x0[j];
+      V.x[j] = xn;
+      if (S.restart[0] == 2) V.x0[j] = xn;
+    }
   }
 }
 
@@ -496,19 +507,19 @@ __global__ __launch_bounds__(kThreads) void k_finish_y(const SlotDev* __restrict
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const int i = tl.r0 + threadIdx.x;
-  if (i >= tl.r1) return;
-  if (S.restart[0] == 1) {
-    const T yh = V.yhat[i];
-    V.y[i] = yh;
-    V.y0[i] = yh;
-  } else {
-    const double k = (double)(S.k0[0] + kk);
-    const T w = (T)((k + 1.0) / (k + 2.0));
-    const T wa = (T)(1.0 / (k + 2.0));
-    const T yn = w * ((T)2 * V.yhat[i] - V.y[i]) + wa * V.y0[i];
-    V.y[i] = yn;
-    if (S.restart[0] == 2) V.y0[i] = yn;
+  const double k = (double)(S.k0[0] + kk);
+  const T w = (T)((k + 1.0) / (k + 2.0));
+  const T wa = (T)(1.0 / (k + 2.0));
+  for (int i = tl.r0 + threadIdx.x; i < tl.r1; i += kThreads) {
+    if (S.restart[0] == 1) {
+      const T yh = V.yhat[i];
+      V.y[i] = yh;
+      V.y0[i] = yh;
+    } else {
+      const T yn = w * ((T)2 * V.yhat[i] - V.y[i]) + wa * V.y0[i];
+      V.y[i] = yn;
+      if (S.restart[0] == 2) V.y0[i] = yn;
+    }
   }
 }
 
@@ -519,12 +530,12 @@ __global__ __launch_bounds__(kThreads) void k_promote_x(const SlotDev* __restric
   if (t < 0) return;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
-  const int j = tl.r0 + threadIdx.x;
-  if (j >= tl.r1) return;
-  const double v = (double)S.f.xhat[j];
-  S.d.x[j] = v;
-  S.d.x0[j] = v;
-  S.d.xhat[j] = v;
+  for (int j = tl.r0 + threadIdx.x; j < tl.r1; j += kThreads) {
+    const double v = (double)S.f.xhat[j];
+    S.d.x[j] = v;
+    S.d.x0[j] = v;
+    S.d.xhat[j] = v;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_promote_y(const SlotDev* __restrict__ slots,
@@ -533,12 +544,12 @@ __global__ __launch_bounds__(kThreads) void k_promote_y(const SlotDev* __restric
   if (t < 0) return;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
-  const int i = tl.r0 + threadIdx.x;
-  if (i >= tl.r1) return;
-  const double v = (double)S.f.yhat[i];
-  S.d.y[i] = v;
-  S.d.y0[i] = v;
-  S.d.yhat[i] = v;
+  for (int i = tl.r0 + threadIdx.x; i < tl.r1; i += kThreads) {
+    const double v = (double)S.f.yhat[i];
+    S.d.y[i] = v;
+    S.d.y0[i] = v;
+    S.d.yhat[i] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -656,9 +667,9 @@ __device__ inline void scen_block_partials(double (&q)[NQ], const bool (&is_max)
 #pragma unroll
   for (int k = 0; k < NQ; ++k) red[(rl * kLanes + sc) * NQ + k] = q[k];
   __syncthreads();
-  if (threadIdx.x < kLanes * NQ) {
-    const int s2 = threadIdx.x / NQ;
-    const int k = threadIdx.x % NQ;
+  for (int idx = threadIdx.x; idx < kLanes * NQ; idx += kThreads) {
+    const int s2 = idx / NQ;
+    const int k = idx % NQ;
     double acc = red[s2 * NQ + k];
     for (int r = 1; r < kRowsPerPass; ++r) {
       const double v = red[(r * kLanes + s2) * NQ + k];
@@ -776,21 +787,23 @@ __global__ __launch_bounds__(kThreads) void k_kkt_cols_ms(const SlotDev* __restr
 // scal[s * kScal + q]: thread (q, s) sums its partial over all blocks in order
 __global__ __launch_bounds__(kThreads) void k_reduce_ms(const SlotDev* __restrict__ slots) {
   const SlotDev& S = slots[0];
-  const int tq = threadIdx.x / kLanes;  // 0 .. 15
-  const int sc = threadIdx.x % kLanes;
-  if (tq >= RQ_N + CQ_N || sc >= S.nscen) return;
-  double acc = 0.0;
-  if (tq < RQ_N) {
-    const bool mx = tq == RQ_RESMAX;
-    for (int b = 0; b < S.a_nblk; ++b) {
-      const double v = S.part_a[((size_t)b * RQ_N + tq) * kMaxScen + sc];
-      acc = mx ? fmax(acc, v) : acc + v;
+  for (int idx = threadIdx.x; idx < (RQ_N + CQ_N) * kLanes; idx += kThreads) {
+    const int tq = idx / kLanes;
+    const int sc = idx % kLanes;
+    if (sc >= S.nscen) continue;
+    double acc = 0.0;
+    if (tq < RQ_N) {
+      const bool mx = tq == RQ_RESMAX;
+      for (int b = 0; b < S.a_nblk; ++b) {
+        const double v = S.part_a[((size_t)b * RQ_N + tq) * kMaxScen + sc];
+        acc = mx ? fmax(acc, v) : acc + v;
+      }
+    } else {
+      const int k = tq - RQ_N;
+      for (int b = 0; b < S.t_nblk; ++b) acc += S.part_t[((size_t)b * CQ_N + k) * kMaxScen + sc];
     }
-  } else {
-    const int k = tq - RQ_N;
-    for (int b = 0; b < S.t_nblk; ++b) acc += S.part_t[((size_t)b * CQ_N + k) * kMaxScen + sc];
+    S.scal[sc * kScal + tq] = acc;
   }
-  S.scal[sc * kScal + tq] = acc;
 }
 
 template <typename T>
@@ -882,10 +895,8 @@ __global__ __launch_bounds__(kThreads) void k_scale_factor(int op, const int* __
   const int nz = k1 - k0;
   auto term = [&](int k, int r) { return fabs(val[k]) * (drow[r] * dcol[col[k]]); };
   if (nz <= kNnzTile) {
-    // one thread per row; the row index of each entry is needed for drow,
-    // so each thread walks its own row (rows are short after blocking)
-    const int r = r0 + threadIdx.x;
-    if (r < r1) {
+    // each thread walks its own rows (rows are short after blocking)
+    for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
       double acc = 0.0;
       for (int k = ptr[r]; k < ptr[r + 1]; ++k) {
         const double v = term(k, r);
@@ -982,11 +993,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(const int* __restrict__ ptr, 
   __shared__ ACC red[kThreads / 64];
   const int t = xcd_tile(nblk);
   if (t < 0) return;
-  int r;
-  ACC s;
-  if (block_row_sum<ACC>(ptr, blk[t], blk[t + 1], lds, red,
-                         [&](int k) { return (ACC)val[k] * (ACC)x[col[k]]; }, r, s))
-    y[r] = (V)s;
+  block_rows<ACC>(ptr, blk[t], blk[t + 1], lds, red, [&](int k) { return (ACC)val[k] * (ACC)x[col[k]]; },
+                  [&](int r, ACC s) { y[r] = (V)s; });
 }
 
 // ---- merge-path SpMV (Merrill & Garland, SC'16) -----------------------------
@@ -1156,18 +1164,19 @@ __global__ void k_to_f32(const double* a, float* b, int64_t n) {
 
 // Plain stream copy, 4 x 16 B per thread and iteration, grid-stride.
 typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int kCopyThreads = 256;
 
-__global__ __launch_bounds__(kThreads) void k_copy(const v4f* __restrict__ a, v4f* __restrict__ b,
+__global__ __launch_bounds__(kCopyThreads) void k_copy(const v4f* __restrict__ a, v4f* __restrict__ b,
                                                    int64_t n4) {
-  const int64_t stride = (int64_t)gridDim.x * kThreads * 4;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads * 4 + threadIdx.x; i < n4; i += stride) {
+  const int64_t stride = (int64_t)gridDim.x * kCopyThreads * 4;
+  for (int64_t i = (int64_t)blockIdx.x * kCopyThreads * 4 + threadIdx.x; i < n4; i += stride) {
     v4f v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (i + u * kThreads < n4) v[u] = __builtin_nontemporal_load(a + i + u * kThreads);
+      if (i + u * kCopyThreads < n4) v[u] = __builtin_nontemporal_load(a + i + u * kCopyThreads);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (i + u * kThreads < n4) __builtin_nontemporal_store(v[u], b + i + u * kThreads);
+      if (i + u * kCopyThreads < n4) __builtin_nontemporal_store(v[u], b + i + u * kCopyThreads);
   }
 }
 
@@ -1381,9 +1390,9 @@ void launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
 }
 
 void launch_copy_kernel(const float4* a, float4* b, int64_t n4, hipStream_t s) {
-  int g = nb(n4, kThreads * 4);
+  int g = nb(n4, kCopyThreads * 4);
   if (g > 256 * 64) g = 256 * 64;
-  if (g > 0) k_copy<<<g, kThreads, 0, s>>>((const v4f*)a, (v4f*)b, n4);
+  if (g > 0) k_copy<<<g, kCopyThreads, 0, s>>>((const v4f*)a, (v4f*)b, n4);
 }
 
 // ---- scenario-batch launchers -------------------------------------------------

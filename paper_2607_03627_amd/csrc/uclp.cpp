@@ -989,9 +989,10 @@ static void run_epochs(uc_engine* E) {
   for (auto* lp : E->active) timing |= lp->opts.timing != 0;
   for (int j = 0; j < K && e == hipSuccess; ++j) {
     const bool check = j == K - 1;
-    // the first iteration of an epoch carries dispatch-attached timing events
+    // the middle iteration of an epoch (not the first launch after the host
+    // synchronisation, not the check) carries dispatch-attached timing events
     // on the first non-empty precision group
-    const bool tj = timing && j == 0;
+    const bool tj = timing && j == K / 2;
     const bool t1 = tj && nT1 > 0, t0 = tj && nT1 == 0;
     launch_primal(1, check, E->d_slots, T1, nT1, j, 1, s, t1 ? E->ev[0] : nullptr, t1 ? E->ev[1] : nullptr);
     launch_primal(0, check, E->d_slots, T0, nT0, j, 1, s, t0 ? E->ev[0] : nullptr, t0 ? E->ev[1] : nullptr);
