@@ -152,6 +152,32 @@ __device__ inline void stage_products(const int* __restrict__ col, const T* __re
   }
 }
 
+// The same staging from the block's entries in column order: the gathers of
+// neighbouring lanes fall on neighbouring cache lines, and each product is
+// written to its CSR position dst[k] so the per-row sums keep CSR order.
+template <typename T, typename G>
+__device__ inline void stage_sorted(const int* __restrict__ cs, const T* __restrict__ vs,
+                                    const unsigned short* __restrict__ dst, const G* __restrict__ g,
+                                    int nz, T* lds) {
+  int c[kItems];
+  int d[kItems];
+  T v[kItems];
+#pragma unroll
+  for (int u = 0; u < kItems; ++u) {
+    const int k = threadIdx.x + u * kThreads;
+    if (k < nz) {
+      c[u] = cs[k];
+      v[u] = vs[k];
+      d[u] = dst[k];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kItems; ++u) {
+    const int k = threadIdx.x + u * kThreads;
+    if (k < nz) lds[d[u]] = v[u] * (T)g[c[u]];
+  }
+}
+
 // Sum of one long row (above kNnzTile entries) by the whole block; valid in thread 0.
 template <typename T, typename G>
 __device__ inline T long_row_sum(const int* __restrict__ col, const T* __restrict__ val,
@@ -207,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   }
   T s[kRowsPerThread];
   if (nz <= kNnzTile) {
-    stage_products<T, T>(S.t_col + k0, V.tv + k0, V.y, nz, lds);
+    stage_sorted<T, T>(S.t_cs + k0, V.tvs + k0, S.t_dst + k0, V.y, nz, lds);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kRowsPerThread; ++q) {
@@ -270,7 +296,7 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
   }
   T s[kRowsPerThread];
   if (nz <= kNnzTile) {
-    stage_products<T, T>(S.a_col + k0, V.av + k0, V.xbar, nz, lds);
+    stage_sorted<T, T>(S.a_cs + k0, V.avs + k0, S.a_dst + k0, V.xbar, nz, lds);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kRowsPerThread; ++q) {
@@ -867,6 +893,26 @@ __global__ void k_iota(int* v, int64_t n) {
   if (i < n) v[i] = (int)i;
 }
 
+// One workgroup per segment: values and CSR positions in sorted order.
+__global__ __launch_bounds__(kThreads) void k_gather_sorted(const int* __restrict__ perm,
+                                                            const int* __restrict__ off, int nseg,
+                                                            const double* __restrict__ v64,
+                                                            const float* __restrict__ v32,
+                                                            double* __restrict__ vs64,
+                                                            float* __restrict__ vs32,
+                                                            unsigned short* __restrict__ dst) {
+  const int b = blockIdx.x;
+  if (b >= nseg) return;
+  const int s0 = off[b], s1 = off[b + 1];
+  const bool fits = s1 - s0 <= kNnzTile;  // long-row blocks keep CSR order and never read dst
+  for (int k = s0 + threadIdx.x; k < s1; k += kThreads) {
+    const int p = perm[k];
+    vs64[k] = v64[p];
+    vs32[k] = v32[p];
+    dst[k] = fits ? (unsigned short)(p - s0) : (unsigned short)0;
+  }
+}
+
 __global__ void k_gather_transpose(const int* __restrict__ perm, const int* __restrict__ row_of,
                                    const double* __restrict__ val, int64_t nnz, int* __restrict__ t_col,
                                    double* __restrict__ t_val) {
@@ -1291,6 +1337,30 @@ int radix_sort_pairs(void* temp, size_t temp_bytes, const int* keys_in, int* key
   hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in,
                                                     vals_out, (int)nnz, 0, key_bits(n), s);
   return (int)e;
+}
+
+size_t seg_sort_temp_bytes(int64_t nnz, int nseg, int ncols) {
+  size_t bytes = 0;
+  (void)hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, bytes, (const int*)nullptr, (int*)nullptr,
+                                                    (const int*)nullptr, (int*)nullptr, (int)nnz, nseg,
+                                                    (const int*)nullptr, (const int*)nullptr, 0,
+                                                    key_bits(ncols));
+  (void)hipGetLastError();
+  return bytes;
+}
+
+int seg_sort_pairs(void* temp, size_t temp_bytes, const int* keys_in, int* keys_out, const int* vals_in,
+                   int* vals_out, int64_t nnz, int nseg, const int* off, int ncols, hipStream_t s) {
+  if (nnz == 0 || nseg == 0) return 0;
+  hipError_t e = hipcub::DeviceSegmentedRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in,
+                                                             vals_out, (int)nnz, nseg, off, off + 1, 0,
+                                                             key_bits(ncols), s);
+  return (int)e;
+}
+
+void launch_gather_sorted(const int* perm, const int* off, int nseg, const double* v64, const float* v32,
+                          double* vs64, float* vs32, unsigned short* dst, hipStream_t s) {
+  if (nseg > 0) k_gather_sorted<<<nseg, kThreads, 0, s>>>(perm, off, nseg, v64, v32, vs64, vs32, dst);
 }
 
 void launch_scale_factor(int op, const int* ptr, const int* col, const double* val, const double* drow,

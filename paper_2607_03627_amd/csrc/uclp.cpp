@@ -186,6 +186,7 @@ struct HostProblem {
   int mi = 0, ni = 0, m_eq = 0;
   int64_t nnzi = 0;
   std::vector<int> a_ptr, a_col, t_ptr, a_blk, t_blk;
+  std::vector<int> a_seg, t_seg;  // entry offset of each row block (nblk + 1)
   std::vector<double> a_val, c, b, l, u;
   std::vector<int> row_map;  // internal row -> original row (negative: -(row+1), negated 'L')
   std::vector<int> col_map;  // internal column -> original column
@@ -309,6 +310,10 @@ static void presolve_structure(HostProblem& P) {
   for (int j = 0; j < P.ni; ++j) P.t_ptr[j + 1] += P.t_ptr[j];
   partition_rows(P.a_ptr, P.mi, P.a_blk);
   partition_rows(P.t_ptr, P.ni, P.t_blk);
+  P.a_seg.resize(P.a_blk.size());
+  P.t_seg.resize(P.t_blk.size());
+  for (size_t b = 0; b < P.a_blk.size(); ++b) P.a_seg[b] = P.a_ptr[P.a_blk[b]];
+  for (size_t b = 0; b < P.t_blk.size(); ++b) P.t_seg[b] = P.t_ptr[P.t_blk[b]];
   P.b.assign(P.mi, 0.0);
   P.c.assign(P.ni, 0.0);
   P.l.assign(P.ni, 0.0);
@@ -351,6 +356,10 @@ struct DevMem {
   double *a_raw, *t_raw;
   double *a_v64, *t_v64;
   float *a_v32, *t_v32;
+  int *a_seg, *t_seg, *a_cs, *t_cs;
+  unsigned short *a_dst, *t_dst;
+  double *a_vs64, *t_vs64;
+  float *a_vs32, *t_vs32;
   double *c_in, *b_in, *l_in, *u_in;  // unscaled internal data (scenario-major)
   double *dr, *dc, *fr, *fc;
   double *part_a, *part_t, *scal;
@@ -380,6 +389,16 @@ static void carve(DevMem& D, const HostProblem& P, int ns) {
   D.t_v64 = A.take<double>(z);
   D.a_v32 = A.take<float>(z);
   D.t_v32 = A.take<float>(z);
+  D.a_seg = A.take<int>(P.a_seg.size());
+  D.t_seg = A.take<int>(P.t_seg.size());
+  D.a_cs = A.take<int>(z);
+  D.t_cs = A.take<int>(z);
+  D.a_dst = A.take<unsigned short>(z);
+  D.t_dst = A.take<unsigned short>(z);
+  D.a_vs64 = A.take<double>(z);
+  D.t_vs64 = A.take<double>(z);
+  D.a_vs32 = A.take<float>(z);
+  D.t_vs32 = A.take<float>(z);
   D.c_in = A.take<double>((size_t)n * ns);
   D.l_in = A.take<double>((size_t)n * ns);
   D.u_in = A.take<double>((size_t)n * ns);
@@ -406,7 +425,9 @@ static void carve(DevMem& D, const HostProblem& P, int ns) {
   D.keys_out = A.take<int>(z);
   D.perm_in = A.take<int>(z);
   D.perm_out = A.take<int>(z);
-  D.sort_bytes = radix_sort_temp_bytes(z, n);
+  D.sort_bytes = std::max(radix_sort_temp_bytes(z, n),
+                          std::max(seg_sort_temp_bytes(z, (int)P.a_blk.size() - 1, n),
+                                   seg_sort_temp_bytes(z, (int)P.t_blk.size() - 1, m)));
   D.sort_temp = A.take<char>(D.sort_bytes);
   carve_vecs(A, D.f, n, m, ns);
   carve_vecs(A, D.d, n, m, ns);
@@ -537,6 +558,8 @@ static int upload(uc_lp* lp) {
   HIPOK(hipMemcpyAsync(D.t_ptr, P.t_ptr.data(), sizeof(int) * (P.ni + 1), hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(D.a_blk, P.a_blk.data(), sizeof(int) * P.a_blk.size(), hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(D.t_blk, P.t_blk.data(), sizeof(int) * P.t_blk.size(), hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(D.a_seg, P.a_seg.data(), sizeof(int) * P.a_seg.size(), hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(D.t_seg, P.t_seg.data(), sizeof(int) * P.t_seg.size(), hipMemcpyHostToDevice, s));
   HIPOK(hipStreamSynchronize(s));
   lp->uploaded = true;
   lp->setup_done = false;
@@ -577,6 +600,14 @@ static SlotDev make_slot(const uc_lp* lp) {
   S.f.tv = D.t_v32;
   S.d.av = D.a_v64;
   S.d.tv = D.t_v64;
+  S.f.avs = D.a_vs32;
+  S.f.tvs = D.t_vs32;
+  S.d.avs = D.a_vs64;
+  S.d.tvs = D.t_vs64;
+  S.a_cs = D.a_cs;
+  S.t_cs = D.t_cs;
+  S.a_dst = D.a_dst;
+  S.t_dst = D.t_dst;
   S.part_a = D.part_a;
   S.part_t = D.part_t;
   S.scal = D.scal;
@@ -630,6 +661,20 @@ static int setup_device(uc_lp* lp) {
   launch_mul_inplace(D.dc, D.fc, n, s);
   launch_scale_values(D.a_ptr, D.a_col, D.a_raw, D.dr, D.dc, m, D.a_v64, D.a_v32, s);
   launch_scale_values(D.t_ptr, D.t_col, D.t_raw, D.dc, D.dr, n, D.t_v64, D.t_v32, s);
+  // entries of each row block in column order, for the half-step gathers
+  {
+    HIPOK(hipGetLastError());
+    int se = seg_sort_pairs(D.sort_temp, D.sort_bytes, D.a_col, D.a_cs, D.perm_in, D.perm_out, z, na, D.a_seg,
+                            n, s);
+    if (se == 0) {
+      launch_gather_sorted(D.perm_out, D.a_seg, na, D.a_v64, D.a_v32, D.a_vs64, D.a_vs32, D.a_dst, s);
+      se = seg_sort_pairs(D.sort_temp, D.sort_bytes, D.t_col, D.t_cs, D.perm_in, D.perm_out, z, nt, D.t_seg, m,
+                          s);
+    }
+    if (se == 0) launch_gather_sorted(D.perm_out, D.t_seg, nt, D.t_v64, D.t_v32, D.t_vs64, D.t_vs32, D.t_dst, s);
+    if (se != 0)
+      return fail(UC_LP_EHIP, "segmented sort of the row blocks failed: %s", hipGetErrorName((hipError_t)se));
+  }
   launch_scale_vectors(D.c_in, D.l_in, D.u_in, D.b_in, D.dc, D.dr, n, m, 1, (double*)D.d.c,
                        (double*)D.d.l, (double*)D.d.u, (double*)D.d.b, (float*)D.f.c, (float*)D.f.l,
                        (float*)D.f.u, (float*)D.f.b, s);
@@ -1895,6 +1940,10 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   SD.f.tv = base->D.t_v32;
   SD.d.av = base->D.a_v64;
   SD.d.tv = base->D.t_v64;
+  SD.f.avs = base->D.a_vs32;
+  SD.f.tvs = base->D.t_vs32;
+  SD.d.avs = base->D.a_vs64;
+  SD.d.tvs = base->D.t_vs64;
   SD.part_a = A.part_a;
   SD.part_t = A.part_t;
   SD.scal = A.scal;

@@ -35,8 +35,10 @@ struct Vecs {
   const T* l;
   const T* u;
   const T* b;
-  const T* tv;  // scaled values of A^T
-  const T* av;  // scaled values of A
+  const T* tv;  // scaled values of A^T (CSR order)
+  const T* av;  // scaled values of A (CSR order)
+  const T* tvs;  // scaled values of A^T, each row block sorted by column index
+  const T* avs;  // scaled values of A, each row block sorted by column index
 };
 
 // Everything a kernel needs to know about one resident instance (a "slot").
@@ -49,6 +51,13 @@ struct SlotDev {
   const int* t_col;
   const int* a_blk;  // row-block boundaries of A   (a_nblk + 1)
   const int* t_blk;  // row-block boundaries of A^T (t_nblk + 1)
+  // Entries of each row block re-ordered by column index (so the gathers of
+  // neighbouring lanes hit neighbouring cache lines) and, per entry, its
+  // position inside the block in CSR order (where its product goes in LDS).
+  const int* a_cs;
+  const int* t_cs;
+  const unsigned short* a_dst;
+  const unsigned short* t_dst;
   int m, n, m_eq, nscen;
   int a_nblk, t_nblk;
   const double* dr;  // D_r (m)
@@ -113,6 +122,13 @@ size_t radix_sort_temp_bytes(int64_t nnz, int n);
 int radix_sort_pairs(void* temp, size_t temp_bytes, const int* keys_in, int* keys_out,
                      const int* vals_in, int* vals_out, int64_t nnz, int n, hipStream_t s);
 void launch_iota(int* v, int64_t n, hipStream_t s);
+// stable sort of (key, value) pairs inside each segment [off[b], off[b+1])
+size_t seg_sort_temp_bytes(int64_t nnz, int nseg, int ncols);
+int seg_sort_pairs(void* temp, size_t temp_bytes, const int* keys_in, int* keys_out, const int* vals_in,
+                   int* vals_out, int64_t nnz, int nseg, const int* off, int ncols, hipStream_t s);
+// vs*[k] = v*[perm[k]], dst[k] = perm[k] - off[b] for the segment b holding k
+void launch_gather_sorted(const int* perm, const int* off, int nseg, const double* v64, const float* v32,
+                          double* vs64, float* vs32, unsigned short* dst, hipStream_t s);
 // op 0: row max |a| D_r D_c ; op 1: row sum of |a| D_r D_c.  Result -> fac[r] = 1/sqrt(v) or 1.
 void launch_scale_factor(int op, const int* ptr, const int* col, const double* val, const double* drow,
                          const double* dcol, const int* blk, int nblk, int rows, double* fac,
