@@ -51,6 +51,25 @@ def dual_bytes(n, m, nnz, vb=4):
     return nnz * (vb + 4) + 4 * (m + 1) + vb * n + 4 * vb * m
 
 
+def measured_traffic(kernel="k_primal"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_primal_large_traffic.json")
+    src = os.path.join(ROOT, "paper_2607_03627_amd", "csrc", "kernels.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernels_hip_sha256") != digest:
+        return None
+    return rec.get(kernel, {}).get("traffic_bytes")
+
+
 def cpu_baseline(target_nnz):
     """The oracle (HiGHS interior point through oracle/reference.py) on a
     bounded sample of the same generator, extrapolated to the workload."""
@@ -226,7 +245,8 @@ def main():
                    "eps_rel": 1e-4, "kkt_every": 64, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_primal<float> (A^T SpMV + projection + Halpern)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": measured_traffic("k_primal") if args.workload == "large" else None,
                      "bytes_per_launch": pb, "us_per_launch": p_us},
         "extra": {
             "status": [i["status_name"] for i in infos], "iters": [i["iters"] for i in infos],
