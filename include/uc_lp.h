@@ -112,6 +112,9 @@ typedef struct {
                             (The published PDLP values are 0.8 necessary and
                             0.5 smoothing; 0.9 / 0.8 took fewer iterations to
                             1e-4 on every synthetic UC family measured.)      */
+  double halpern_gamma;  /* reflection of the Halpern step in [0, 1]:
+                            z <- w((1+g) T(z) - g z) + (1-w) z_restart;
+                            1 = reflected Halpern (default), 0 = plain         */
 } uc_lp_opts;
 
 typedef struct {

@@ -183,10 +183,12 @@ def pdhg_step(A: sp.csr_matrix, c, b, l, u, m_eq, x, y, tau, sigma):
     return x_hat, y_hat
 
 
-def halpern_update(z, z_hat, z_anchor, k):
-    """z_next = w (2 z_hat - z) + (1 - w) z_anchor with w = (k + 1)/(k + 2)."""
+def halpern_update(z, z_hat, z_anchor, k, gamma=1.0):
+    """z_next = w ((1 + gamma) z_hat - gamma z) + (1 - w) z_anchor with
+    w = (k + 1)/(k + 2): the Halpern step on the reflected operator
+    (1 + gamma) T - gamma I; gamma = 1 is the reflected form, 0 plain Halpern."""
     w = (k + 1.0) / (k + 2.0)
-    return w * (2.0 * z_hat - z) + (1.0 - w) * z_anchor
+    return w * ((1.0 + gamma) * z_hat - gamma * z) + (1.0 - w) * z_anchor
 
 
 def fixed_point_residual(A, x, y, x_hat, y_hat, tau, sigma):

@@ -195,7 +195,8 @@ __device__ inline T long_row_sum(const int* __restrict__ col, const T* __restric
 
 // Primal half-step over the rows of A^T (= columns j of A):
 //   g = c_j - (A^T y)_j ; x_hat = clamp(x - tau g, l, u) ; xbar = 2 x_hat - x
-//   non-check: x <- w xbar + (1 - w) x0,  w = (k + 1)/(k + 2), 1 - w = 1/(k + 2)
+//   non-check: x <- w ((1+gamma) x_hat - gamma x) + (1 - w) x0 (w xbar at gamma = 1),
+//              w = (k + 1)/(k + 2), 1 - w = 1/(k + 2)
 //   check:     x_hat stored, x kept for the residuals
 // Thread t handles rows r0 + t + q * kThreads, q < kRowsPerThread.
 template <typename T, bool CHECK>
@@ -249,6 +250,7 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   const double kk = (double)(S.k0[0] + jiter);
   const T w = (T)((kk + 1.0) / (kk + 2.0));
   const T wa = (T)(1.0 / (kk + 2.0));
+  const bool full = S.gamma == 1.0;  // full reflection: 2 x_hat - x is xbar itself
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
     const int j = r0 + threadIdx.x + q * kThreads;
@@ -257,13 +259,13 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
     const T xb = (T)2 * xh - x[q];
     V.xbar[j] = xb;
     if (CHECK) V.xhat[j] = xh;
-    else V.x[j] = w * xb + wa * xa[q];
+    else V.x[j] = w * (full ? xb : (T)(1.0 + S.gamma) * xh - (T)S.gamma * x[q]) + wa * xa[q];
   }
 }
 
 // Dual half-step over the rows of A:
 //   y_hat = y + sigma (b - A xbar), projected to y >= 0 on rows i >= m_eq
-//   non-check: y <- w (2 y_hat - y) + (1 - w) y0 ; check: y_hat stored
+//   non-check: y <- w ((1+gamma) y_hat - gamma y) + (1 - w) y0 ; check: y_hat stored
 template <typename T, bool CHECK>
 __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ slots,
                                                    const Tile* __restrict__ tiles, int ntiles,
@@ -312,6 +314,7 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
   const double kk = (double)(S.k0[0] + jiter);
   const T w = (T)((kk + 1.0) / (kk + 2.0));
   const T wa = (T)(1.0 / (kk + 2.0));
+  const T g1 = (T)(1.0 + S.gamma), g = (T)S.gamma;
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
     const int i = r0 + threadIdx.x + q * kThreads;
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
     T yh = y[q] + sigma * (bi[q] - s[q]);
     if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
     if (CHECK) V.yhat[i] = yh;
-    else V.y[i] = w * ((T)2 * yh - y[q]) + wa * ya[q];
+    else V.y[i] = w * (g1 * yh - g * y[q]) + wa * ya[q];
   }
 }
 
@@ -517,7 +520,8 @@ __global__ __launch_bounds__(kThreads) void k_finish_x(const SlotDev* __restrict
       V.x[j] = xh;
       V.x0[j] = xh;
     } else {
-      const T xn = w * V.xbar[j] + wa * V.x0[j];
+      const T refl = S.gamma == 1.0 ? V.xbar[j] : (T)(1.0 + S.gamma) * V.xhat[j] - (T)S.gamma * V.x[j];
+      const T xn = w * refl + wa * V.x0[j];
       V.x[j] = xn;
       if (S.restart[0] == 2) V.x0[j] = xn;
     }
@@ -542,7 +546,7 @@ __global__ __launch_bounds__(kThreads) void k_finish_y(const SlotDev* __restrict
       V.y[i] = yh;
       V.y0[i] = yh;
     } else {
-      const T yn = w * ((T)2 * V.yhat[i] - V.y[i]) + wa * V.y0[i];
+      const T yn = w * ((T)(1.0 + S.gamma) * V.yhat[i] - (T)S.gamma * V.y[i]) + wa * V.y0[i];
       V.y[i] = yn;
       if (S.restart[0] == 2) V.y0[i] = yn;
     }
@@ -637,7 +641,7 @@ __global__ __launch_bounds__(kThreads) void k_primal_ms(const SlotDev* __restric
     const T xb = (T)2 * xh - x;
     V.xbar[e] = xb;
     if (CHECK) V.xhat[e] = xh;
-    else V.x[e] = w * xb + wa * V.x0[e];
+    else V.x[e] = w * (S.gamma == 1.0 ? xb : (T)(1.0 + S.gamma) * xh - (T)S.gamma * x) + wa * V.x0[e];
   }
 }
 
@@ -679,7 +683,7 @@ __global__ __launch_bounds__(kThreads) void k_dual_ms(const SlotDev* __restrict_
     T yh = y + sigma * (V.b[e] - acc);
     if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
     if (CHECK) V.yhat[e] = yh;
-    else V.y[e] = w * ((T)2 * yh - y) + wa * V.y0[e];
+    else V.y[e] = w * ((T)(1.0 + S.gamma) * yh - (T)S.gamma * y) + wa * V.y0[e];
   }
 }
 
@@ -854,7 +858,8 @@ __global__ __launch_bounds__(kThreads) void k_finish_ms(const SlotDev* __restric
   const double k = (double)(S.k0[sc] + kk);
   const T w = (T)((k + 1.0) / (k + 2.0));
   const T wa = (T)(1.0 / (k + 2.0));
-  const T refl = which ? (T)2 * zh - z[e] : V.xbar[e];
+  const T refl = which ? (T)(1.0 + S.gamma) * zh - (T)S.gamma * z[e]
+                       : (S.gamma == 1.0 ? V.xbar[e] : (T)(1.0 + S.gamma) * zh - (T)S.gamma * z[e]);
   const T zn = w * refl + wa * z0[e];
   z[e] = zn;
   if (flag == 2) z0[e] = zn;

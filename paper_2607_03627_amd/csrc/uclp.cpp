@@ -96,6 +96,7 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->restart_necessary = 0.9;
   o->restart_artificial = 0.36;
   o->pw_smoothing = 0.8;
+  o->halpern_gamma = 1.0;
 }
 
 static int check_opts(const uc_lp_opts& o) {
@@ -111,7 +112,7 @@ static int check_opts(const uc_lp_opts& o) {
   if (o.spmv_algo != UC_LP_SPMV_ROWSPLIT) return fail(UC_LP_ENOTSUP, "spmv_algo %d for PDHG", o.spmv_algo);
   if (!(o.restart_sufficient > 0 && o.restart_sufficient <= o.restart_necessary && o.restart_necessary < 1) ||
       !(o.restart_artificial > 0 && o.restart_artificial <= 1) || !(o.pw_smoothing >= 0 && o.pw_smoothing <= 1) ||
-      (o.restart_to_current != 0 && o.restart_to_current != 1))
+      (o.restart_to_current != 0 && o.restart_to_current != 1) || !(o.halpern_gamma >= 0 && o.halpern_gamma <= 1))
     return fail(UC_LP_EINVAL, "restart / primal-weight parameters out of range");
   return UC_LP_OK;
 }
@@ -590,6 +591,7 @@ static SlotDev make_slot(const uc_lp* lp) {
   S.n = P.ni;
   S.m_eq = P.m_eq;
   S.nscen = 1;
+  S.gamma = lp->opts.halpern_gamma;
   S.a_nblk = (int)P.a_blk.size() - 1;
   S.t_nblk = (int)P.t_blk.size() - 1;
   S.dr = D.dr;

@@ -72,6 +72,7 @@ struct SlotDev {
   double sigma[kMaxScen];
   int restart[kMaxScen];        // set by the host before the finish kernel
   int active[kMaxScen];         // 0: scenario frozen (converged)
+  double gamma;                 // Halpern reflection: w((1+g) T(z) - g z) + (1-w) z0
 };
 
 // One unit of work of the batched kernels: a row block of one slot, with its

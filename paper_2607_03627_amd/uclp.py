@@ -37,7 +37,8 @@ class uc_lp_opts(C.Structure):
                 ("step_scale", C.c_double), ("spmv_algo", C.c_int32), ("verbose", C.c_int32),
                 ("timing", C.c_int32), ("restart_to_current", C.c_int32),
                 ("restart_sufficient", C.c_double), ("restart_necessary", C.c_double),
-                ("restart_artificial", C.c_double), ("pw_smoothing", C.c_double)]
+                ("restart_artificial", C.c_double), ("pw_smoothing", C.c_double),
+                ("halpern_gamma", C.c_double)]
 
 
 class uc_lp_info(C.Structure):

@@ -107,16 +107,16 @@ def step_inputs(ip, Dc, Dr, seed):
     return x, y, x0, y0
 
 
-@pytest.mark.parametrize("shape,seed", [("tiny", 1), ("medium", 2)])
+@pytest.mark.parametrize("shape,seed,gamma", [("tiny", 1, 1.0), ("medium", 2, 1.0), ("tiny", 3, 0.5)])
 @pytest.mark.parametrize("prec", [uclp.UC_LP_FP64, uclp.UC_LP_FP32_MIXED])
-def test_pdhg_step_elementwise(shape, seed, prec):
+def test_pdhg_step_elementwise(shape, seed, gamma, prec):
     lp = make_instance(shape, seed)
-    say("case", shape, seed, prec)
+    say("case", shape, seed, gamma, prec)
     ip, A, Dr, Dc, Ah = internal_oracle(lp)
     c, b, l, u = ip.c * Dc, ip.b * Dr, ip.l / Dc, ip.u / Dc
     x, y, x0, y0 = step_inputs(ip, Dc, Dr, seed)
     tau, sigma, k = 0.37, 1.9, 5
-    with Handle(lp) as H:
+    with Handle(lp, halpern_gamma=gamma) as H:
         xh, yh, xn, yn = uclp.uc_lp_debug_step(H.h, prec, x, y, x0, y0, k, tau, sigma)
         _, gdc, _ = uclp.uc_lp_get_scaling(H.h, ip.m, ip.n)
     # the kernels project onto their own scaled bounds l / D_c, u / D_c
@@ -129,8 +129,8 @@ def test_pdhg_step_elementwise(shape, seed, prec):
         x, y, x0, y0, c, b, l, u = map(f, (x, y, x0, y0, c, b, l, u))
         Ah = sp.csr_matrix((f(Ah.data), Ah.indices, Ah.indptr), shape=Ah.shape)
     rx, ry = ps.pdhg_step(Ah, c, b, l, u, ip.m_eq, x, y, tau, sigma)
-    rxn = ps.halpern_update(x, rx, x0, k)
-    ryn = ps.halpern_update(y, ry, y0, k)
+    rxn = ps.halpern_update(x, rx, x0, k, gamma)
+    ryn = ps.halpern_update(y, ry, y0, k, gamma)
     absA = abs(Ah)
     rowlen = np.diff(Ah.indptr).max()
     if prec == uclp.UC_LP_FP64:

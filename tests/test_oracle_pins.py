@@ -383,6 +383,28 @@ def test_pdhg_step_one_dimensional_hand_values():
     assert z[0] == 0.5 * (4.5 - 3.0) + 0.5 * 1.0
 
 
+@pytest.mark.parametrize("gamma", [0.0, 0.5, 1.0])
+def test_halpern_iteration_converges_to_anchor_projection(gamma):
+    # T = projection onto a box is firmly nonexpansive, so (1 + gamma) T - gamma I
+    # is nonexpansive for gamma in [0, 1] with the same fixed points (the box);
+    # Halpern's iteration anchored at z0 then tends to the point of the box
+    # nearest z0, at rate O(1/k) in the residual.
+    rng = np.random.default_rng(int(gamma * 10))
+    lo, hi = -np.ones(40), np.ones(40)
+    z0 = 3 * rng.normal(size=40)
+    z = z0.copy()
+    for k in range(4000):
+        z = ps.halpern_update(z, np.clip(z, lo, hi), z0, k, gamma)
+    assert np.max(np.abs(z - np.clip(z0, lo, hi))) < 2e-2
+    assert np.max(np.abs(z - np.clip(z, lo, hi))) < 5e-3
+    # a dropped anchor term ends at a different point
+    z = z0.copy()
+    for k in range(4000):
+        w = (k + 1.0) / (k + 2.0)
+        z = w * ((1 + gamma) * np.clip(z, lo, hi) - gamma * z)
+    assert np.max(np.abs(z - np.clip(z0, lo, hi))) > 0.1
+
+
 def test_internal_problem_maps_and_offsets():
     lp = dense_lp([[1, 2, 0], [0, 0, 0], [3, 0, 1], [1, 1, 1]], [4, 0, 2, 9], "GEEL",
                   [1, 1, 1], [0, 2, -np.inf], [5, 2, np.inf])
