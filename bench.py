@@ -40,13 +40,15 @@ def log(*a):
 
 
 def primal_bytes(n, m, nnz, vb=4):
-    # A^T values + column indices, row pointers, one read of y per row of A,
-    # per column: c, l, u, x, x0 read and x, xbar written
+    # upper bound of the library's figure (no block reads its c, l, u from
+    # the flags): A^T values + column indices, row pointers, one read of y per
+    # row of A, per column: c, l, u, x, x0 read and x, xbar written
     return nnz * (vb + 4) + 4 * (n + 1) + vb * m + 7 * vb * n
 
 
 def dual_bytes(n, m, nnz, vb=4):
-    # A values + column indices, row pointers, one read of xbar per column,
+    # upper bound, as above: A values + column indices, row pointers, one
+    # read of xbar per column,
     # per row: b, y, y0 read and y written
     return nnz * (vb + 4) + 4 * (m + 1) + vb * n + 4 * vb * m
 
@@ -222,8 +224,9 @@ def main():
     value = statistics.median(walls)
     last = infos[-1]
     n_i, m_i, z_i = last["n_presolved"], last["m_presolved"], last["nnz_presolved"]
-    pb = primal_bytes(n_i, m_i, z_i)
-    db = dual_bytes(n_i, m_i, z_i)
+    pb = last["primal_bytes"]
+    db = last["dual_bytes"]
+    assert pb <= primal_bytes(n_i, m_i, z_i) and db <= dual_bytes(n_i, m_i, z_i)
     p_us = statistics.median(i["primal_kernel_us"] for i in infos)
     d_us = statistics.median(i["dual_kernel_us"] for i in infos)
     achieved = pb / (p_us * 1e-6) / 1e9 if p_us > 0 else None

@@ -143,6 +143,13 @@ typedef struct {
   int32_t m_presolved, n_presolved;  /* sizes after the minimal presolve      */
   int64_t nnz_presolved;
   int64_t device_bytes;    /* device memory held by this instance             */
+  double primal_bytes;     /* algorithmic bytes of one primal half-step launch
+                              in the current precision: matrix values and
+                              indices, row pointers, one read of y, and the
+                              per-column streams the kernel reads or writes
+                              (c, l, u skipped where a row block holds one
+                              known value)                                     */
+  double dual_bytes;       /* the same for one dual half-step launch           */
 } uc_lp_info;
 
 /* Fill *opts with the defaults listed in uc_lp_opts. */

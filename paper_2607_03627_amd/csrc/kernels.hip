@@ -214,6 +214,7 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   const int* __restrict__ ptr = S.t_ptr;
   const int k0 = tl.k0;
   const int nz = tl.k1 - k0;
+  const int fl = tl.flags;
   // epilogue operands first, so their loads overlap the gathers
   int a[kRowsPerThread], b[kRowsPerThread];
   T c[kRowsPerThread], l[kRowsPerThread], u[kRowsPerThread], x[kRowsPerThread], xa[kRowsPerThread];
@@ -225,9 +226,9 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
     if (j < r1) {
       a[q] = ptr[j] - k0;
       b[q] = ptr[j + 1] - k0;
-      c[q] = V.c[j];
-      l[q] = V.l[j];
-      u[q] = V.u[j];
+      c[q] = (fl & kColC0) ? (T)0 : V.c[j];
+      u[q] = (fl & kColUInf) ? (T)INFINITY : V.u[j];
+      l[q] = (fl & kColL0) ? (T)0 : (fl & kColLInf) ? -(T)INFINITY : (fl & kColLNegU) ? -u[q] : V.l[j];
       x[q] = V.x[j];
       if (!CHECK) xa[q] = V.x0[j];
     }
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
     if (i < r1) {
       a[q] = ptr[i] - k0;
       b[q] = ptr[i + 1] - k0;
-      bi[q] = V.b[i];
+      bi[q] = (tl.flags & kRowB0) ? (T)0 : V.b[i];
       y[q] = V.y[i];
       if (!CHECK) ya[q] = V.y0[i];
     }

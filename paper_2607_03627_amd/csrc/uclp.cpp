@@ -188,6 +188,7 @@ struct HostProblem {
   int64_t nnzi = 0;
   std::vector<int> a_ptr, a_col, t_ptr, a_blk, t_blk;
   std::vector<int> a_seg, t_seg;  // entry offset of each row block (nblk + 1)
+  std::vector<int> a_flag, t_flag;  // TileFlag bits of each row block
   std::vector<double> a_val, c, b, l, u;
   std::vector<int> row_map;  // internal row -> original row (negative: -(row+1), negated 'L')
   std::vector<int> col_map;  // internal column -> original column
@@ -199,7 +200,8 @@ struct HostProblem {
 
 // Tiles of one matrix of one slot: rows [r0, r1) and entries [k0, k1) of each
 // row block, taken from the host copies of the partition and row pointers.
-static void push_tiles(std::vector<Tile>& v, int slot, const std::vector<int>& blk, const std::vector<int>& ptr) {
+static void push_tiles(std::vector<Tile>& v, int slot, const std::vector<int>& blk, const std::vector<int>& ptr,
+                       const std::vector<int>* flags = nullptr) {
   for (size_t b = 0; b + 1 < blk.size(); ++b) {
     Tile t;
     t.slot = slot;
@@ -208,8 +210,35 @@ static void push_tiles(std::vector<Tile>& v, int slot, const std::vector<int>& b
     t.r1 = blk[b + 1];
     t.k0 = ptr[t.r0];
     t.k1 = ptr[t.r1];
-    t.pad0 = t.pad1 = 0;
+    t.flags = flags ? (*flags)[b] : 0;
+    t.pad = 0;
     v.push_back(t);
+  }
+}
+
+static bool is_pos_zero(double v) { return v == 0.0 && !std::signbit(v); }
+
+// Per-block TileFlag bits of the internal data (exact comparisons).
+static void block_flags(HostProblem& P) {
+  const int nt = (int)P.t_blk.size() - 1, na = (int)P.a_blk.size() - 1;
+  P.t_flag.assign(std::max(nt, 0), 0);
+  P.a_flag.assign(std::max(na, 0), 0);
+  for (int bk = 0; bk < nt; ++bk) {
+    int f = kColC0 | kColL0 | kColLInf | kColLNegU | kColUInf;
+    for (int j = P.t_blk[bk]; j < P.t_blk[bk + 1]; ++j) {
+      if (!is_pos_zero(P.c[j])) f &= ~kColC0;
+      if (!is_pos_zero(P.l[j])) f &= ~kColL0;
+      if (!(std::isinf(P.l[j]) && P.l[j] < 0)) f &= ~kColLInf;
+      if (!(P.l[j] == -P.u[j] && std::signbit(P.l[j]) != std::signbit(P.u[j]))) f &= ~kColLNegU;
+      if (!(std::isinf(P.u[j]) && P.u[j] > 0)) f &= ~kColUInf;
+    }
+    P.t_flag[bk] = f;
+  }
+  for (int bk = 0; bk < na; ++bk) {
+    int f = kRowB0;
+    for (int i = P.a_blk[bk]; i < P.a_blk[bk + 1]; ++i)
+      if (!is_pos_zero(P.b[i])) f = 0;
+    P.a_flag[bk] = f;
   }
 }
 
@@ -255,6 +284,7 @@ static void presolve_data(HostProblem& P) {
   for (int32_t j = 0; j < P.n; ++j) nc += P.o_c[j] * P.o_c[j];
   P.norm_b = std::sqrt(nb);
   P.norm_c = std::sqrt(nc);
+  block_flags(P);
 }
 
 static void presolve_structure(HostProblem& P) {
@@ -508,6 +538,7 @@ struct uc_lp {
   double t_request = 0;
   double timed_primal_ms = 0, timed_dual_ms = 0;
   long long timed_n = 0;
+  int data_gen = 0;  // bumped by uc_lp_update_data (tile flags depend on the data)
 };
 
 static void set_info(uc_lp* lp, const uc_lp_info& in) {
@@ -876,6 +907,25 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
   return out;
 }
 
+// Algorithmic bytes of one non-check half-step launch with vb-byte values:
+// the matrix values and column indices, the row pointers, one read of the
+// gathered vector, and per row of the block the streams its kernel touches
+// (primal: x, x0 read, x, xbar written, and c, l, u unless the block's flags
+// supply them; dual: y, y0 read, y written, and b unless flagged).
+static void half_step_bytes(const HostProblem& P, int vb, double* pb, double* db) {
+  double p = (double)P.nnzi * (vb + 4) + 4.0 * (P.ni + 1) + (double)vb * P.mi;
+  for (size_t bk = 0; bk + 1 < P.t_blk.size(); ++bk) {
+    const int f = P.t_flag[bk];
+    const int per = 4 + !(f & kColC0) + !(f & kColUInf) + !(f & (kColL0 | kColLInf | kColLNegU));
+    p += (double)(P.t_blk[bk + 1] - P.t_blk[bk]) * per * vb;
+  }
+  double d = (double)P.nnzi * (vb + 4) + 4.0 * (P.mi + 1) + (double)vb * P.ni;
+  for (size_t bk = 0; bk + 1 < P.a_blk.size(); ++bk)
+    d += (double)(P.a_blk[bk + 1] - P.a_blk[bk]) * (3 + !(P.a_flag[bk] & kRowB0)) * vb;
+  *pb = p;
+  *db = d;
+}
+
 static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
   uc_lp_info in = get_info(lp);
   CheckOut out = check_core(lp->st, lp->opts, q, K, tnow, lp->P.obj_offset, lp->P.norm_b, lp->P.norm_c,
@@ -885,6 +935,7 @@ static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
     in.dual_kernel_us = 1e3 * lp->timed_dual_ms / lp->timed_n;
     in.timed_launches = lp->timed_n;
   }
+  half_step_bytes(lp->P, lp->st.prec ? 4 : 8, &in.primal_bytes, &in.dual_bytes);
   set_info(lp, in);
   return out;
 }
@@ -988,7 +1039,7 @@ static void run_epochs(uc_engine* E) {
     S.restart[0] = 0;
     S.active[0] = 1;
     E->h_slots[a] = S;
-    sig[a] = {lp, lp->st.prec};
+    sig[a] = {lp, lp->st.prec + 2 * lp->data_gen};
   }
   hipError_t e = hipSuccess;
   std::vector<Tile> all;
@@ -997,9 +1048,9 @@ static void run_epochs(uc_engine* E) {
     std::vector<int> ids(A);
     for (int a = 0; a < A; ++a) {
       ids[a] = a;
-      const int p = sig[a].second;
-      push_tiles(tt[p], a, E->active[a]->P.t_blk, E->active[a]->P.t_ptr);
-      push_tiles(at[p], a, E->active[a]->P.a_blk, E->active[a]->P.a_ptr);
+      const int p = E->active[a]->st.prec;
+      push_tiles(tt[p], a, E->active[a]->P.t_blk, E->active[a]->P.t_ptr, &E->active[a]->P.t_flag);
+      push_tiles(at[p], a, E->active[a]->P.a_blk, E->active[a]->P.a_ptr, &E->active[a]->P.a_flag);
     }
     E->nT1 = (int)tt[1].size();
     E->nT0 = (int)tt[0].size();
@@ -1310,6 +1361,7 @@ extern "C" int uc_lp_update_data(uc_lp* lp, const double* c, const double* b, co
   P.o_lb.swap(nl);
   P.o_ub.swap(nu);
   presolve_data(P);
+  ++lp->data_gen;
   lp->setup_done = false;
   return UC_LP_OK;
 }
@@ -1522,8 +1574,8 @@ static int debug_step_t(uc_lp* lp, const double* x, const double* y, const doubl
   S.k0[0] = k;
   S.active[0] = 1;
   std::vector<Tile> tl;
-  push_tiles(tl, 0, P.t_blk, P.t_ptr);
-  push_tiles(tl, 0, P.a_blk, P.a_ptr);
+  push_tiles(tl, 0, P.t_blk, P.t_ptr, &P.t_flag);
+  push_tiles(tl, 0, P.a_blk, P.a_ptr, &P.a_flag);
   E->layout.clear();  // the engine's tile and slot tables are overwritten below
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
@@ -1584,8 +1636,8 @@ extern "C" int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp
     if ((rc = put_vec<double>(dst, yi.data(), P.mi, s))) return rc;
   SlotDev S = make_slot(lp);
   std::vector<Tile> tl;
-  push_tiles(tl, 0, P.t_blk, P.t_ptr);
-  push_tiles(tl, 0, P.a_blk, P.a_ptr);
+  push_tiles(tl, 0, P.t_blk, P.t_ptr, &P.t_flag);
+  push_tiles(tl, 0, P.a_blk, P.a_ptr, &P.a_flag);
   E->layout.clear();  // the engine's tile and slot tables are overwritten below
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));

@@ -83,7 +83,21 @@ struct Tile {
   int blk;
   int r0, r1;
   int k0, k1;
-  int pad0, pad1;
+  int flags;  // TileFlag bits: data that are uniform over the block's rows
+  int pad;
+};
+
+// A row block of A^T (columns of A) whose c, l or u take one known value on
+// every column, or a row block of A whose b is zero on every row, does not
+// read that vector: the half-step kernels substitute the value.  The flags
+// are exact (bit patterns) and are recomputed whenever the data change.
+enum TileFlag {
+  kColC0 = 1,     // c_j == +0
+  kColL0 = 2,     // l_j == +0
+  kColLInf = 4,   // l_j == -inf
+  kColLNegU = 8,  // l_j == -u_j
+  kColUInf = 16,  // u_j == +inf
+  kRowB0 = 1      // b_i == +0
 };
 
 // ---- launchers (kernels.hip) --------------------------------------------

@@ -52,7 +52,8 @@ class uc_lp_info(C.Structure):
                 ("norm_a_est", C.c_double), ("omega", C.c_double),
                 ("primal_kernel_us", C.c_double), ("dual_kernel_us", C.c_double),
                 ("timed_launches", C.c_int64), ("m_presolved", C.c_int32), ("n_presolved", C.c_int32),
-                ("nnz_presolved", C.c_int64), ("device_bytes", C.c_int64)]
+                ("nnz_presolved", C.c_int64), ("device_bytes", C.c_int64),
+                ("primal_bytes", C.c_double), ("dual_bytes", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
