@@ -178,6 +178,28 @@ __device__ inline void stage_sorted(const int* __restrict__ cs, const T* __restr
   }
 }
 
+// The same from the packed words: one 4-byte read per entry for index and slot.
+template <typename T, typename G>
+__device__ inline void stage_packed(const unsigned* __restrict__ pk, const T* __restrict__ vs, int base,
+                                    const G* __restrict__ g, int nz, T* lds) {
+  unsigned p[kItems];
+  T v[kItems];
+#pragma unroll
+  for (int u = 0; u < kItems; ++u) {
+    const int k = threadIdx.x + u * kThreads;
+    if (k < nz) {
+      p[u] = pk[k];
+      v[u] = vs[k];
+    }
+  }
+  const G* __restrict__ gb = g + base;
+#pragma unroll
+  for (int u = 0; u < kItems; ++u) {
+    const int k = threadIdx.x + u * kThreads;
+    if (k < nz) lds[p[u] >> kPackShift] = v[u] * (T)gb[p[u] & kPackMask];
+  }
+}
+
 // Sum of one long row (above kNnzTile entries) by the whole block; valid in thread 0.
 template <typename T, typename G>
 __device__ inline T long_row_sum(const int* __restrict__ col, const T* __restrict__ val,
@@ -235,7 +257,10 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   }
   T s[kRowsPerThread];
   if (nz <= kNnzTile) {
-    stage_sorted<T, T>(S.t_cs + k0, V.tvs + k0, S.t_dst + k0, V.y, nz, lds);
+    if (tl.base >= 0)
+      stage_packed<T, T>(S.t_pk + k0, V.tvs + k0, tl.base, V.y, nz, lds);
+    else
+      stage_sorted<T, T>(S.t_cs + k0, V.tvs + k0, S.t_dst + k0, V.y, nz, lds);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kRowsPerThread; ++q) {
@@ -299,7 +324,10 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
   }
   T s[kRowsPerThread];
   if (nz <= kNnzTile) {
-    stage_sorted<T, T>(S.a_cs + k0, V.avs + k0, S.a_dst + k0, V.xbar, nz, lds);
+    if (tl.base >= 0)
+      stage_packed<T, T>(S.a_pk + k0, V.avs + k0, tl.base, V.xbar, nz, lds);
+    else
+      stage_sorted<T, T>(S.a_cs + k0, V.avs + k0, S.a_dst + k0, V.xbar, nz, lds);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kRowsPerThread; ++q) {
@@ -906,16 +934,21 @@ __global__ __launch_bounds__(kThreads) void k_gather_sorted(const int* __restric
                                                             const float* __restrict__ v32,
                                                             double* __restrict__ vs64,
                                                             float* __restrict__ vs32,
-                                                            unsigned short* __restrict__ dst) {
+                                                            unsigned short* __restrict__ dst,
+                                                            const int* __restrict__ cs,
+                                                            const int* __restrict__ base,
+                                                            unsigned* __restrict__ pk) {
   const int b = blockIdx.x;
   if (b >= nseg) return;
   const int s0 = off[b], s1 = off[b + 1];
   const bool fits = s1 - s0 <= kNnzTile;  // long-row blocks keep CSR order and never read dst
+  const int bs = base[b];
   for (int k = s0 + threadIdx.x; k < s1; k += kThreads) {
     const int p = perm[k];
     vs64[k] = v64[p];
     vs32[k] = v32[p];
     dst[k] = fits ? (unsigned short)(p - s0) : (unsigned short)0;
+    pk[k] = bs >= 0 ? ((unsigned)(p - s0) << kPackShift) | (unsigned)(cs[k] - bs) : 0u;
   }
 }
 
@@ -1365,8 +1398,10 @@ int seg_sort_pairs(void* temp, size_t temp_bytes, const int* keys_in, int* keys_
 }
 
 void launch_gather_sorted(const int* perm, const int* off, int nseg, const double* v64, const float* v32,
-                          double* vs64, float* vs32, unsigned short* dst, hipStream_t s) {
-  if (nseg > 0) k_gather_sorted<<<nseg, kThreads, 0, s>>>(perm, off, nseg, v64, v32, vs64, vs32, dst);
+                          double* vs64, float* vs32, unsigned short* dst, const int* cs,
+                          const int* base, unsigned* pk, hipStream_t s) {
+  if (nseg > 0)
+    k_gather_sorted<<<nseg, kThreads, 0, s>>>(perm, off, nseg, v64, v32, vs64, vs32, dst, cs, base, pk);
 }
 
 void launch_scale_factor(int op, const int* ptr, const int* col, const double* val, const double* drow,

@@ -189,6 +189,7 @@ struct HostProblem {
   std::vector<int> a_ptr, a_col, t_ptr, a_blk, t_blk;
   std::vector<int> a_seg, t_seg;  // entry offset of each row block (nblk + 1)
   std::vector<int> a_flag, t_flag;  // TileFlag bits of each row block
+  std::vector<int> a_base, t_base;  // Tile::base of each row block
   std::vector<double> a_val, c, b, l, u;
   std::vector<int> row_map;  // internal row -> original row (negative: -(row+1), negated 'L')
   std::vector<int> col_map;  // internal column -> original column
@@ -201,7 +202,7 @@ struct HostProblem {
 // Tiles of one matrix of one slot: rows [r0, r1) and entries [k0, k1) of each
 // row block, taken from the host copies of the partition and row pointers.
 static void push_tiles(std::vector<Tile>& v, int slot, const std::vector<int>& blk, const std::vector<int>& ptr,
-                       const std::vector<int>* flags = nullptr) {
+                       const std::vector<int>* flags = nullptr, const std::vector<int>* base = nullptr) {
   for (size_t b = 0; b + 1 < blk.size(); ++b) {
     Tile t;
     t.slot = slot;
@@ -211,8 +212,42 @@ static void push_tiles(std::vector<Tile>& v, int slot, const std::vector<int>& b
     t.k0 = ptr[t.r0];
     t.k1 = ptr[t.r1];
     t.flags = flags ? (*flags)[b] : 0;
-    t.pad = 0;
+    t.base = base ? (*base)[b] : -1;
     v.push_back(t);
+  }
+}
+
+// Tile::base of every row block of A and of A^T: the smallest gathered index
+// when the block fits the LDS tile and its gathered indices span less than
+// 2^kPackShift, else -1.
+static void block_bases(HostProblem& P) {
+  const int na = (int)P.a_blk.size() - 1, nt = (int)P.t_blk.size() - 1;
+  std::vector<int> lo(std::max(nt, 0), INT32_MAX), hi(std::max(nt, 0), -1);
+  std::vector<int> tblk_of(P.ni);
+  for (int bk = 0; bk < nt; ++bk)
+    for (int j = P.t_blk[bk]; j < P.t_blk[bk + 1]; ++j) tblk_of[j] = bk;
+  P.a_base.assign(std::max(na, 0), -1);
+  for (int bk = 0; bk < na; ++bk) {
+    const int k0 = P.a_ptr[P.a_blk[bk]], k1 = P.a_ptr[P.a_blk[bk + 1]];
+    if (k1 == k0 || k1 - k0 > kNnzTile) continue;
+    int mn = INT32_MAX, mx = -1;
+    for (int k = k0; k < k1; ++k) {
+      mn = std::min(mn, P.a_col[k]);
+      mx = std::max(mx, P.a_col[k]);
+    }
+    if (mx - mn < (1 << kPackShift)) P.a_base[bk] = mn;
+  }
+  for (int i = 0; i < P.mi; ++i)
+    for (int k = P.a_ptr[i]; k < P.a_ptr[i + 1]; ++k) {
+      const int tb = tblk_of[P.a_col[k]];
+      lo[tb] = std::min(lo[tb], i);
+      hi[tb] = std::max(hi[tb], i);
+    }
+  P.t_base.assign(std::max(nt, 0), -1);
+  for (int bk = 0; bk < nt; ++bk) {
+    const int z = P.t_ptr[P.t_blk[bk + 1]] - P.t_ptr[P.t_blk[bk]];
+    if (z == 0 || z > kNnzTile) continue;
+    if (hi[bk] - lo[bk] < (1 << kPackShift)) P.t_base[bk] = lo[bk];
   }
 }
 
@@ -345,6 +380,7 @@ static void presolve_structure(HostProblem& P) {
   P.t_seg.resize(P.t_blk.size());
   for (size_t b = 0; b < P.a_blk.size(); ++b) P.a_seg[b] = P.a_ptr[P.a_blk[b]];
   for (size_t b = 0; b < P.t_blk.size(); ++b) P.t_seg[b] = P.t_ptr[P.t_blk[b]];
+  block_bases(P);
   P.b.assign(P.mi, 0.0);
   P.c.assign(P.ni, 0.0);
   P.l.assign(P.ni, 0.0);
@@ -389,6 +425,8 @@ struct DevMem {
   float *a_v32, *t_v32;
   int *a_seg, *t_seg, *a_cs, *t_cs;
   unsigned short *a_dst, *t_dst;
+  unsigned *a_pk, *t_pk;
+  int *a_base, *t_base;
   double *a_vs64, *t_vs64;
   float *a_vs32, *t_vs32;
   double *c_in, *b_in, *l_in, *u_in;  // unscaled internal data (scenario-major)
@@ -426,6 +464,10 @@ static void carve(DevMem& D, const HostProblem& P, int ns) {
   D.t_cs = A.take<int>(z);
   D.a_dst = A.take<unsigned short>(z);
   D.t_dst = A.take<unsigned short>(z);
+  D.a_pk = A.take<unsigned>(z);
+  D.t_pk = A.take<unsigned>(z);
+  D.a_base = A.take<int>(P.a_base.size());
+  D.t_base = A.take<int>(P.t_base.size());
   D.a_vs64 = A.take<double>(z);
   D.t_vs64 = A.take<double>(z);
   D.a_vs32 = A.take<float>(z);
@@ -592,6 +634,8 @@ static int upload(uc_lp* lp) {
   HIPOK(hipMemcpyAsync(D.t_blk, P.t_blk.data(), sizeof(int) * P.t_blk.size(), hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(D.a_seg, P.a_seg.data(), sizeof(int) * P.a_seg.size(), hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(D.t_seg, P.t_seg.data(), sizeof(int) * P.t_seg.size(), hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(D.a_base, P.a_base.data(), sizeof(int) * P.a_base.size(), hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(D.t_base, P.t_base.data(), sizeof(int) * P.t_base.size(), hipMemcpyHostToDevice, s));
   HIPOK(hipStreamSynchronize(s));
   lp->uploaded = true;
   lp->setup_done = false;
@@ -641,6 +685,8 @@ static SlotDev make_slot(const uc_lp* lp) {
   S.t_cs = D.t_cs;
   S.a_dst = D.a_dst;
   S.t_dst = D.t_dst;
+  S.a_pk = D.a_pk;
+  S.t_pk = D.t_pk;
   S.part_a = D.part_a;
   S.part_t = D.part_t;
   S.scal = D.scal;
@@ -700,11 +746,14 @@ static int setup_device(uc_lp* lp) {
     int se = seg_sort_pairs(D.sort_temp, D.sort_bytes, D.a_col, D.a_cs, D.perm_in, D.perm_out, z, na, D.a_seg,
                             n, s);
     if (se == 0) {
-      launch_gather_sorted(D.perm_out, D.a_seg, na, D.a_v64, D.a_v32, D.a_vs64, D.a_vs32, D.a_dst, s);
+      launch_gather_sorted(D.perm_out, D.a_seg, na, D.a_v64, D.a_v32, D.a_vs64, D.a_vs32, D.a_dst, D.a_cs,
+                           D.a_base, D.a_pk, s);
       se = seg_sort_pairs(D.sort_temp, D.sort_bytes, D.t_col, D.t_cs, D.perm_in, D.perm_out, z, nt, D.t_seg, m,
                           s);
     }
-    if (se == 0) launch_gather_sorted(D.perm_out, D.t_seg, nt, D.t_v64, D.t_v32, D.t_vs64, D.t_vs32, D.t_dst, s);
+    if (se == 0)
+      launch_gather_sorted(D.perm_out, D.t_seg, nt, D.t_v64, D.t_v32, D.t_vs64, D.t_vs32, D.t_dst, D.t_cs,
+                           D.t_base, D.t_pk, s);
     if (se != 0)
       return fail(UC_LP_EHIP, "segmented sort of the row blocks failed: %s", hipGetErrorName((hipError_t)se));
   }
@@ -1049,8 +1098,9 @@ static void run_epochs(uc_engine* E) {
     for (int a = 0; a < A; ++a) {
       ids[a] = a;
       const int p = E->active[a]->st.prec;
-      push_tiles(tt[p], a, E->active[a]->P.t_blk, E->active[a]->P.t_ptr, &E->active[a]->P.t_flag);
-      push_tiles(at[p], a, E->active[a]->P.a_blk, E->active[a]->P.a_ptr, &E->active[a]->P.a_flag);
+      const HostProblem& Q = E->active[a]->P;
+      push_tiles(tt[p], a, Q.t_blk, Q.t_ptr, &Q.t_flag, &Q.t_base);
+      push_tiles(at[p], a, Q.a_blk, Q.a_ptr, &Q.a_flag, &Q.a_base);
     }
     E->nT1 = (int)tt[1].size();
     E->nT0 = (int)tt[0].size();
@@ -1574,8 +1624,8 @@ static int debug_step_t(uc_lp* lp, const double* x, const double* y, const doubl
   S.k0[0] = k;
   S.active[0] = 1;
   std::vector<Tile> tl;
-  push_tiles(tl, 0, P.t_blk, P.t_ptr, &P.t_flag);
-  push_tiles(tl, 0, P.a_blk, P.a_ptr, &P.a_flag);
+  push_tiles(tl, 0, P.t_blk, P.t_ptr, &P.t_flag, &P.t_base);
+  push_tiles(tl, 0, P.a_blk, P.a_ptr, &P.a_flag, &P.a_base);
   E->layout.clear();  // the engine's tile and slot tables are overwritten below
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
@@ -1636,8 +1686,8 @@ extern "C" int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp
     if ((rc = put_vec<double>(dst, yi.data(), P.mi, s))) return rc;
   SlotDev S = make_slot(lp);
   std::vector<Tile> tl;
-  push_tiles(tl, 0, P.t_blk, P.t_ptr, &P.t_flag);
-  push_tiles(tl, 0, P.a_blk, P.a_ptr, &P.a_flag);
+  push_tiles(tl, 0, P.t_blk, P.t_ptr, &P.t_flag, &P.t_base);
+  push_tiles(tl, 0, P.a_blk, P.a_ptr, &P.a_flag, &P.a_base);
   E->layout.clear();  // the engine's tile and slot tables are overwritten below
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));

@@ -58,6 +58,8 @@ struct SlotDev {
   const int* t_cs;
   const unsigned short* a_dst;
   const unsigned short* t_dst;
+  const unsigned* a_pk;  // packed entries (Tile::base >= 0)
+  const unsigned* t_pk;
   int m, n, m_eq, nscen;
   int a_nblk, t_nblk;
   const double* dr;  // D_r (m)
@@ -84,8 +86,17 @@ struct Tile {
   int r0, r1;
   int k0, k1;
   int flags;  // TileFlag bits: data that are uniform over the block's rows
-  int pad;
+  int base;   // smallest gathered index of the block, or -1: the block's
+              // entries are read from the packed words (see kPackShift)
 };
+
+// Packed entry of a row block in column order: (LDS slot << kPackShift) |
+// (gathered index - block base).  Blocks whose gathered indices span
+// 2^kPackShift or more, and long-row blocks, keep the separate index and
+// slot arrays (Tile::base = -1).
+constexpr int kPackShift = 21;
+constexpr unsigned kPackMask = (1u << kPackShift) - 1;
+static_assert(kNnzTile <= (1 << (32 - kPackShift)), "LDS slot must fit the packed word");
 
 // A row block of A^T (columns of A) whose c, l or u take one known value on
 // every column, or a row block of A whose b is zero on every row, does not
@@ -143,7 +154,8 @@ int seg_sort_pairs(void* temp, size_t temp_bytes, const int* keys_in, int* keys_
                    int* vals_out, int64_t nnz, int nseg, const int* off, int ncols, hipStream_t s);
 // vs*[k] = v*[perm[k]], dst[k] = perm[k] - off[b] for the segment b holding k
 void launch_gather_sorted(const int* perm, const int* off, int nseg, const double* v64, const float* v32,
-                          double* vs64, float* vs32, unsigned short* dst, hipStream_t s);
+                          double* vs64, float* vs32, unsigned short* dst, const int* cs,
+                          const int* base, unsigned* pk, hipStream_t s);
 // op 0: row max |a| D_r D_c ; op 1: row sum of |a| D_r D_c.  Result -> fac[r] = 1/sqrt(v) or 1.
 void launch_scale_factor(int op, const int* ptr, const int* col, const double* val, const double* drow,
                          const double* dcol, const int* blk, int nblk, int rows, double* fac,
