@@ -220,6 +220,12 @@ __device__ inline T long_row_sum(const int* __restrict__ col, const T* __restric
 //   non-check: x <- w ((1+gamma) x_hat - gamma x) + (1 - w) x0 (w xbar at gamma = 1),
 //              w = (k + 1)/(k + 2), 1 - w = 1/(k + 2)
 //   check:     x_hat stored, x kept for the residuals
+// At gamma = 1 the Halpern iterate is not stored between checks: x is read
+// only by this kernel (the dual half-step gathers xbar), so the launch after
+// another rebuilds it as w' xbar + (1 - w') x0 from the stored xbar and the
+// anchor, with the previous launch's w'.  The first launch after a check
+// reads x itself, and a check launch stores the rebuilt x for the KKT and
+// finish kernels.
 // Thread t handles rows r0 + t + q * kThreads, q < kRowsPerThread.
 template <typename T, bool CHECK>
 __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__ slots,
@@ -237,6 +243,14 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   const int k0 = tl.k0;
   const int nz = tl.k1 - k0;
   const int fl = tl.flags;
+  const bool full = S.gamma == 1.0;  // full reflection: 2 x_hat - x is xbar itself
+  const bool rebuild = full && jiter > 0;
+  T wp = 0, wap = 0;
+  if (rebuild) {
+    const double kp = (double)(S.k0[0] + jiter - 1);
+    wp = (T)((kp + 1.0) / (kp + 2.0));
+    wap = (T)(1.0 / (kp + 2.0));
+  }
   // epilogue operands first, so their loads overlap the gathers
   int a[kRowsPerThread], b[kRowsPerThread];
   T c[kRowsPerThread], l[kRowsPerThread], u[kRowsPerThread], x[kRowsPerThread], xa[kRowsPerThread];
@@ -251,8 +265,13 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
       c[q] = (fl & kColC0) ? (T)0 : V.c[j];
       u[q] = (fl & kColUInf) ? (T)INFINITY : V.u[j];
       l[q] = (fl & kColL0) ? (T)0 : (fl & kColLInf) ? -(T)INFINITY : (fl & kColLNegU) ? -u[q] : V.l[j];
-      x[q] = V.x[j];
-      if (!CHECK) xa[q] = V.x0[j];
+      if (rebuild) {
+        xa[q] = V.x0[j];
+        x[q] = wp * V.xbar[j] + wap * xa[q];
+      } else {
+        x[q] = V.x[j];
+        if (!CHECK) xa[q] = V.x0[j];
+      }
     }
   }
   T s[kRowsPerThread];
@@ -276,7 +295,6 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   const double kk = (double)(S.k0[0] + jiter);
   const T w = (T)((kk + 1.0) / (kk + 2.0));
   const T wa = (T)(1.0 / (kk + 2.0));
-  const bool full = S.gamma == 1.0;  // full reflection: 2 x_hat - x is xbar itself
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
     const int j = r0 + threadIdx.x + q * kThreads;
@@ -284,8 +302,12 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
     const T xh = clampv<T>(x[q] - tau * (c[q] - s[q]), l[q], u[q]);
     const T xb = (T)2 * xh - x[q];
     V.xbar[j] = xb;
-    if (CHECK) V.xhat[j] = xh;
-    else V.x[j] = w * (full ? xb : (T)(1.0 + S.gamma) * xh - (T)S.gamma * x[q]) + wa * xa[q];
+    if (CHECK) {
+      V.xhat[j] = xh;
+      if (rebuild) V.x[j] = x[q];
+    } else if (!full) {
+      V.x[j] = w * ((T)(1.0 + S.gamma) * xh - (T)S.gamma * x[q]) + wa * xa[q];
+    }
   }
 }
 

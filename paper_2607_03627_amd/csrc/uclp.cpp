@@ -959,13 +959,14 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
 // Algorithmic bytes of one non-check half-step launch with vb-byte values:
 // the matrix values and column indices, the row pointers, one read of the
 // gathered vector, and per row of the block the streams its kernel touches
-// (primal: x, x0 read, x, xbar written, and c, l, u unless the block's flags
-// supply them; dual: y, y0 read, y written, and b unless flagged).
-static void half_step_bytes(const HostProblem& P, int vb, double* pb, double* db) {
+// (primal: xbar, x0 read and xbar written with full reflection, else x, x0
+// read and x, xbar written, and c, l, u unless the block's flags supply them;
+// dual: y, y0 read, y written, and b unless flagged).
+static void half_step_bytes(const HostProblem& P, int vb, bool full, double* pb, double* db) {
   double p = (double)P.nnzi * (vb + 4) + 4.0 * (P.ni + 1) + (double)vb * P.mi;
   for (size_t bk = 0; bk + 1 < P.t_blk.size(); ++bk) {
     const int f = P.t_flag[bk];
-    const int per = 4 + !(f & kColC0) + !(f & kColUInf) + !(f & (kColL0 | kColLInf | kColLNegU));
+    const int per = (full ? 3 : 4) + !(f & kColC0) + !(f & kColUInf) + !(f & (kColL0 | kColLInf | kColLNegU));
     p += (double)(P.t_blk[bk + 1] - P.t_blk[bk]) * per * vb;
   }
   double d = (double)P.nnzi * (vb + 4) + 4.0 * (P.mi + 1) + (double)vb * P.ni;
@@ -984,7 +985,7 @@ static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
     in.dual_kernel_us = 1e3 * lp->timed_dual_ms / lp->timed_n;
     in.timed_launches = lp->timed_n;
   }
-  half_step_bytes(lp->P, lp->st.prec ? 4 : 8, &in.primal_bytes, &in.dual_bytes);
+  half_step_bytes(lp->P, lp->st.prec ? 4 : 8, lp->opts.halpern_gamma == 1.0, &in.primal_bytes, &in.dual_bytes);
   set_info(lp, in);
   return out;
 }

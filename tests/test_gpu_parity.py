@@ -253,6 +253,20 @@ def test_tiny_fp64_matches_simplex_oracle(seed):
     assert np.all(x >= lp.lb) and np.all(x <= lp.ub)
 
 
+@pytest.mark.parametrize("gamma", [0.0, 0.5])
+def test_tiny_partial_reflection_matches_simplex_oracle(gamma):
+    # gamma < 1 stores the Halpern iterate every iteration instead of
+    # rebuilding it from xbar; both paths reach the oracle's optimum
+    lp = make_instance("tiny", 4)
+    say("case tiny fp64 gamma", gamma)
+    z = GOLDEN["tiny/4"]["obj"]
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP64, eps_rel=1e-8, halpern_gamma=gamma)
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    k = kkt(lp, x, y)
+    assert k.rel_kkt <= 1e-8 * 1.001
+    assert abs(k.pobj - z) <= 1e-6 * abs(z)
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_tiny_fp32_modes(seed):
     lp = make_instance("tiny", seed)
