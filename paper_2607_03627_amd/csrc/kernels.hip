@@ -200,6 +200,58 @@ __device__ inline void stage_packed(const unsigned* __restrict__ pk, const T* __
   }
 }
 
+// Visit the entries of a row block that fits the LDS tile in column order:
+// visit(k, g, slot) gets the entry's position k in the column-ordered arrays,
+// its gathered index g and its CSR position slot within the block.
+template <typename Visit>
+__device__ inline void for_sorted(const Tile& tl, const unsigned* __restrict__ pk, const int* __restrict__ cs,
+                                  const unsigned short* __restrict__ dst, Visit visit) {
+  const int k0 = tl.k0, nz = tl.k1 - tl.k0;
+  if (tl.base >= 0) {
+    for (int k = threadIdx.x; k < nz; k += kThreads) {
+      const unsigned p = pk[k0 + k];
+      visit(k0 + k, tl.base + (int)(p & kPackMask), (int)(p >> kPackShift));
+    }
+  } else {
+    for (int k = threadIdx.x; k < nz; k += kThreads) visit(k0 + k, cs[k0 + k], (int)dst[k0 + k]);
+  }
+}
+
+// block_rows over a tile whose entries are also stored in column order: a
+// block that fits the LDS tile stages psorted(k, g) (position k of the
+// column-ordered arrays, gathered index g) at each entry's CSR position; a
+// long row takes pcsr(k) in CSR order.  f(row, sum) runs for every row, with
+// the row's products summed in CSR order either way.
+template <typename ACC, typename PS, typename PC, typename F>
+__device__ inline void block_rows_sorted(const Tile& tl, const int* __restrict__ ptr, const unsigned* pk,
+                                         const int* cs, const unsigned short* dst, ACC* lds, ACC* red,
+                                         PS psorted, PC pcsr, F f) {
+  const int r0 = tl.r0, r1 = tl.r1, k0 = tl.k0, k1 = tl.k1;
+  if (k1 - k0 <= kNnzTile) {
+    for_sorted(tl, pk, cs, dst, [&](int k, int g, int slot) { lds[slot] = psorted(k, g); });
+    __syncthreads();
+    for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
+      const int a = ptr[r] - k0;
+      const int b = ptr[r + 1] - k0;
+      ACC s = 0;
+      for (int k = a; k < b; ++k) s += lds[k];
+      f(r, s);
+    }
+    return;
+  }
+  ACC s = 0;
+  for (int k = k0 + threadIdx.x; k < k1; k += kThreads) s += pcsr(k);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ACC t = red[0];
+    for (int w = 1; w < kThreads / 64; ++w) t += red[w];
+    f(r0, t);
+  }
+}
+
 // Sum of one long row (above kNnzTile entries) by the whole block; valid in thread 0.
 template <typename T, typename G>
 __device__ inline T long_row_sum(const int* __restrict__ col, const T* __restrict__ val,
@@ -239,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
   const int r0 = tl.r0, r1 = tl.r1;
-  const int* __restrict__ ptr = S.t_ptr;
+  const unsigned short* __restrict__ rend = S.t_end;
   const int k0 = tl.k0;
   const int nz = tl.k1 - k0;
   const int fl = tl.flags;
@@ -260,8 +312,8 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
     a[q] = b[q] = 0;
     c[q] = l[q] = u[q] = x[q] = xa[q] = 0;
     if (j < r1) {
-      a[q] = ptr[j] - k0;
-      b[q] = ptr[j + 1] - k0;
+      a[q] = j == r0 ? 0 : rend[j - 1];
+      b[q] = rend[j];
       c[q] = (fl & kColC0) ? (T)0 : V.c[j];
       u[q] = (fl & kColUInf) ? (T)INFINITY : V.u[j];
       l[q] = (fl & kColL0) ? (T)0 : (fl & kColLInf) ? -(T)INFINITY : (fl & kColLNegU) ? -u[q] : V.l[j];
@@ -326,7 +378,7 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
   const int r0 = tl.r0, r1 = tl.r1;
-  const int* __restrict__ ptr = S.a_ptr;
+  const unsigned short* __restrict__ rend = S.a_end;
   const int k0 = tl.k0;
   const int nz = tl.k1 - k0;
   int a[kRowsPerThread], b[kRowsPerThread];
@@ -337,8 +389,8 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
     a[q] = b[q] = 0;
     bi[q] = y[q] = ya[q] = 0;
     if (i < r1) {
-      a[q] = ptr[i] - k0;
-      b[q] = ptr[i + 1] - k0;
+      a[q] = i == r0 ? 0 : rend[i - 1];
+      b[q] = rend[i];
       bi[q] = (tl.flags & kRowB0) ? (T)0 : V.b[i];
       y[q] = V.y[i];
       if (!CHECK) ya[q] = V.y0[i];
@@ -420,13 +472,13 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict
     q[RQ_RESMAX] = fmax(q[RQ_RESMAX], fabs(ru));
   };
   if (nz <= kNnzTile) {
-    for (int k = threadIdx.x; k < nz; k += kThreads) {
-      const int c = col[k0 + k];
-      const double v = val[k0 + k];
+    const double* __restrict__ vs = S.d.avs;
+    for_sorted(tl, S.a_pk, S.a_cs, S.a_dst, [&](int k, int c, int slot) {
+      const double v = vs[k];
       const double a = (double)xh[c];
-      lds1[k] = v * a;
-      lds2[k] = v * (a - (double)x[c]);
-    }
+      lds1[slot] = v * a;
+      lds2[slot] = v * (a - (double)x[c]);
+    });
     __syncthreads();
     for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
       double s1 = 0, s2 = 0;
@@ -491,7 +543,10 @@ __global__ __launch_bounds__(kThreads) void k_kkt_cols(const SlotDev* __restrict
   const T* __restrict__ yh = V.yhat;
   double q[CQ_N] = {0, 0, 0, 0, 0};
   const bool is_max[CQ_N] = {false, false, false, false, false};
-  block_rows<double>(S.t_ptr, r0, r1, lds, red, [&](int k) { return val[k] * (double)yh[col[k]]; },
+  const double* __restrict__ vs = S.d.tvs;
+  block_rows_sorted<double>(tl, S.t_ptr, S.t_pk, S.t_cs, S.t_dst, lds, red,
+                     [&](int k, int c) { return vs[k] * (double)yh[c]; },
+                     [&](int k) { return val[k] * (double)yh[col[k]]; },
                      [&](int j, double s) {
                        const double c = S.d.c[j];
                        const double l = S.d.l[j];

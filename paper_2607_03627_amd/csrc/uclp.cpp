@@ -190,6 +190,7 @@ struct HostProblem {
   std::vector<int> a_seg, t_seg;  // entry offset of each row block (nblk + 1)
   std::vector<int> a_flag, t_flag;  // TileFlag bits of each row block
   std::vector<int> a_base, t_base;  // Tile::base of each row block
+  std::vector<uint16_t> a_end, t_end;  // row ends relative to the row block's first entry
   std::vector<double> a_val, c, b, l, u;
   std::vector<int> row_map;  // internal row -> original row (negative: -(row+1), negated 'L')
   std::vector<int> col_map;  // internal column -> original column
@@ -248,6 +249,18 @@ static void block_bases(HostProblem& P) {
     const int z = P.t_ptr[P.t_blk[bk + 1]] - P.t_ptr[P.t_blk[bk]];
     if (z == 0 || z > kNnzTile) continue;
     if (hi[bk] - lo[bk] < (1 << kPackShift)) P.t_base[bk] = lo[bk];
+  }
+}
+
+// End of every row's entries relative to its block's first entry (a block
+// holds at most kNnzTile entries, so the offsets fit 16 bits); long-row blocks
+// never read them and get 0.
+static void block_row_ends(const std::vector<int>& ptr, const std::vector<int>& blk, std::vector<uint16_t>& end) {
+  end.assign(ptr.size() - 1, 0);
+  for (size_t bk = 0; bk + 1 < blk.size(); ++bk) {
+    const int z0 = ptr[blk[bk]];
+    if (ptr[blk[bk + 1]] - z0 > kNnzTile) continue;
+    for (int r = blk[bk]; r < blk[bk + 1]; ++r) end[r] = (uint16_t)(ptr[r + 1] - z0);
   }
 }
 
@@ -381,6 +394,8 @@ static void presolve_structure(HostProblem& P) {
   for (size_t b = 0; b < P.a_blk.size(); ++b) P.a_seg[b] = P.a_ptr[P.a_blk[b]];
   for (size_t b = 0; b < P.t_blk.size(); ++b) P.t_seg[b] = P.t_ptr[P.t_blk[b]];
   block_bases(P);
+  block_row_ends(P.a_ptr, P.a_blk, P.a_end);
+  block_row_ends(P.t_ptr, P.t_blk, P.t_end);
   P.b.assign(P.mi, 0.0);
   P.c.assign(P.ni, 0.0);
   P.l.assign(P.ni, 0.0);
@@ -427,6 +442,7 @@ struct DevMem {
   unsigned short *a_dst, *t_dst;
   unsigned *a_pk, *t_pk;
   int *a_base, *t_base;
+  unsigned short *a_end, *t_end;
   double *a_vs64, *t_vs64;
   float *a_vs32, *t_vs32;
   double *c_in, *b_in, *l_in, *u_in;  // unscaled internal data (scenario-major)
@@ -468,6 +484,8 @@ static void carve(DevMem& D, const HostProblem& P, int ns) {
   D.t_pk = A.take<unsigned>(z);
   D.a_base = A.take<int>(P.a_base.size());
   D.t_base = A.take<int>(P.t_base.size());
+  D.a_end = A.take<unsigned short>(P.a_end.size());
+  D.t_end = A.take<unsigned short>(P.t_end.size());
   D.a_vs64 = A.take<double>(z);
   D.t_vs64 = A.take<double>(z);
   D.a_vs32 = A.take<float>(z);
@@ -634,8 +652,14 @@ static int upload(uc_lp* lp) {
   HIPOK(hipMemcpyAsync(D.t_blk, P.t_blk.data(), sizeof(int) * P.t_blk.size(), hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(D.a_seg, P.a_seg.data(), sizeof(int) * P.a_seg.size(), hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(D.t_seg, P.t_seg.data(), sizeof(int) * P.t_seg.size(), hipMemcpyHostToDevice, s));
-  HIPOK(hipMemcpyAsync(D.a_base, P.a_base.data(), sizeof(int) * P.a_base.size(), hipMemcpyHostToDevice, s));
-  HIPOK(hipMemcpyAsync(D.t_base, P.t_base.data(), sizeof(int) * P.t_base.size(), hipMemcpyHostToDevice, s));
+  if (!P.a_base.empty())
+    HIPOK(hipMemcpyAsync(D.a_base, P.a_base.data(), sizeof(int) * P.a_base.size(), hipMemcpyHostToDevice, s));
+  if (!P.t_base.empty())
+    HIPOK(hipMemcpyAsync(D.t_base, P.t_base.data(), sizeof(int) * P.t_base.size(), hipMemcpyHostToDevice, s));
+  if (!P.a_end.empty())
+    HIPOK(hipMemcpyAsync(D.a_end, P.a_end.data(), sizeof(uint16_t) * P.a_end.size(), hipMemcpyHostToDevice, s));
+  if (!P.t_end.empty())
+    HIPOK(hipMemcpyAsync(D.t_end, P.t_end.data(), sizeof(uint16_t) * P.t_end.size(), hipMemcpyHostToDevice, s));
   HIPOK(hipStreamSynchronize(s));
   lp->uploaded = true;
   lp->setup_done = false;
@@ -687,6 +711,8 @@ static SlotDev make_slot(const uc_lp* lp) {
   S.t_dst = D.t_dst;
   S.a_pk = D.a_pk;
   S.t_pk = D.t_pk;
+  S.a_end = D.a_end;
+  S.t_end = D.t_end;
   S.part_a = D.part_a;
   S.part_t = D.part_t;
   S.scal = D.scal;
@@ -957,19 +983,19 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
 }
 
 // Algorithmic bytes of one non-check half-step launch with vb-byte values:
-// the matrix values and column indices, the row pointers, one read of the
+// the matrix values and column indices, the 16-bit row ends, one read of the
 // gathered vector, and per row of the block the streams its kernel touches
 // (primal: xbar, x0 read and xbar written with full reflection, else x, x0
 // read and x, xbar written, and c, l, u unless the block's flags supply them;
 // dual: y, y0 read, y written, and b unless flagged).
 static void half_step_bytes(const HostProblem& P, int vb, bool full, double* pb, double* db) {
-  double p = (double)P.nnzi * (vb + 4) + 4.0 * (P.ni + 1) + (double)vb * P.mi;
+  double p = (double)P.nnzi * (vb + 4) + 2.0 * P.ni + (double)vb * P.mi;
   for (size_t bk = 0; bk + 1 < P.t_blk.size(); ++bk) {
     const int f = P.t_flag[bk];
     const int per = (full ? 3 : 4) + !(f & kColC0) + !(f & kColUInf) + !(f & (kColL0 | kColLInf | kColLNegU));
     p += (double)(P.t_blk[bk + 1] - P.t_blk[bk]) * per * vb;
   }
-  double d = (double)P.nnzi * (vb + 4) + 4.0 * (P.mi + 1) + (double)vb * P.ni;
+  double d = (double)P.nnzi * (vb + 4) + 2.0 * P.mi + (double)vb * P.ni;
   for (size_t bk = 0; bk + 1 < P.a_blk.size(); ++bk)
     d += (double)(P.a_blk[bk + 1] - P.a_blk[bk]) * (3 + !(P.a_flag[bk] & kRowB0)) * vb;
   *pb = p;

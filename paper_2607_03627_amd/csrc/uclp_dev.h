@@ -60,6 +60,11 @@ struct SlotDev {
   const unsigned short* t_dst;
   const unsigned* a_pk;  // packed entries (Tile::base >= 0)
   const unsigned* t_pk;
+  // end of each row's entries relative to its row block's first entry
+  // (0 in long-row blocks); a row starts where the previous row of the
+  // block ends
+  const unsigned short* a_end;
+  const unsigned short* t_end;
   int m, n, m_eq, nscen;
   int a_nblk, t_nblk;
   const double* dr;  // D_r (m)
