@@ -578,31 +578,62 @@ __global__ __launch_bounds__(kThreads) void k_kkt_cols(const SlotDev* __restrict
 }
 
 // Final reduction of the block partials of one slot, in block order.
-__global__ __launch_bounds__(kThreads) void k_reduce(const SlotDev* __restrict__ slots,
-                                                     const int* __restrict__ ids) {
-  __shared__ double red[(kThreads / 64) * (RQ_N + CQ_N)];
-  const SlotDev& S = slots[ids[blockIdx.x]];
-  double q[RQ_N + CQ_N];
-  bool is_max[RQ_N + CQ_N];
+__global__ __launch_bounds__(kThreads) void k_reduce_part(const SlotDev* __restrict__ slots,
+                                                          const int* __restrict__ ids,
+                                                          double* __restrict__ red2) {
+  constexpr int NQ = RQ_N + CQ_N;
+  __shared__ double red[(kThreads / 64) * NQ];
+  const SlotDev& S = slots[ids[blockIdx.y]];
+  const int g = blockIdx.x;
+  double q[NQ];
+  bool is_max[NQ];
 #pragma unroll
-  for (int k = 0; k < RQ_N + CQ_N; ++k) {
+  for (int k = 0; k < NQ; ++k) {
     q[k] = 0.0;
     is_max[k] = (k == RQ_RESMAX);
   }
-  for (int b = threadIdx.x; b < S.a_nblk; b += kThreads) {
+  const int a0 = (int)((int64_t)S.a_nblk * g / kRedChunks), a1 = (int)((int64_t)S.a_nblk * (g + 1) / kRedChunks);
+  for (int b = a0 + (int)threadIdx.x; b < a1; b += kThreads) {
     const double* p = S.part_a + (size_t)b * RQ_N;
 #pragma unroll
     for (int k = 0; k < RQ_N; ++k) q[k] = is_max[k] ? fmax(q[k], p[k]) : q[k] + p[k];
   }
-  for (int b = threadIdx.x; b < S.t_nblk; b += kThreads) {
+  const int t0 = (int)((int64_t)S.t_nblk * g / kRedChunks), t1 = (int)((int64_t)S.t_nblk * (g + 1) / kRedChunks);
+  for (int b = t0 + (int)threadIdx.x; b < t1; b += kThreads) {
     const double* p = S.part_t + (size_t)b * CQ_N;
 #pragma unroll
     for (int k = 0; k < CQ_N; ++k) q[RQ_N + k] += p[k];
   }
-  block_reduce<RQ_N + CQ_N>(q, is_max, red);
+  block_reduce<NQ>(q, is_max, red);
+  if (threadIdx.x == 0) {
+    double* out = red2 + ((size_t)blockIdx.y * kRedChunks + g) * NQ;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) out[k] = q[k];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce(const SlotDev* __restrict__ slots,
+                                                     const int* __restrict__ ids,
+                                                     const double* __restrict__ red2) {
+  constexpr int NQ = RQ_N + CQ_N;
+  __shared__ double red[(kThreads / 64) * NQ];
+  const SlotDev& S = slots[ids[blockIdx.x]];
+  double q[NQ];
+  bool is_max[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    q[k] = 0.0;
+    is_max[k] = (k == RQ_RESMAX);
+  }
+  for (int g = threadIdx.x; g < kRedChunks; g += kThreads) {
+    const double* p = red2 + ((size_t)blockIdx.x * kRedChunks + g) * NQ;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) q[k] = is_max[k] ? fmax(q[k], p[k]) : q[k] + p[k];
+  }
+  block_reduce<NQ>(q, is_max, red);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < RQ_N + CQ_N; ++k) S.scal[k] = q[k];
+    for (int k = 0; k < NQ; ++k) S.scal[k] = q[k];
   }
 }
 
@@ -1394,9 +1425,12 @@ void launch_kkt(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles,
   }
 }
 
-void launch_reduce(const SlotDev* slots, const int* slot_ids, int nslots, int nscen, hipStream_t s) {
+void launch_reduce(const SlotDev* slots, const int* slot_ids, int nslots, int nscen, double* red2,
+                   hipStream_t s) {
   (void)nscen;
-  if (nslots > 0) k_reduce<<<nslots, kThreads, 0, s>>>(slots, slot_ids);
+  if (nslots <= 0) return;
+  k_reduce_part<<<dim3(kRedChunks, nslots), kThreads, 0, s>>>(slots, slot_ids, red2);
+  k_reduce<<<nslots, kThreads, 0, s>>>(slots, slot_ids, red2);
 }
 
 void launch_finish(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,

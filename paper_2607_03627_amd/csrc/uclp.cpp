@@ -566,6 +566,7 @@ struct uc_engine {
   int* d_ids = nullptr;
   double* h_scal = nullptr;  // pinned, max_slots * kScal
   double* d_scal = nullptr;  // device, max_slots * kScal (one copy per check)
+  double* d_red2 = nullptr;  // device, max_slots * kRedChunks * (RQ_N + CQ_N)
   // tile layout of the current active set, rebuilt when the set or a
   // precision changes
   std::vector<std::pair<const uc_lp*, int>> layout;
@@ -1176,7 +1177,7 @@ static void run_epochs(uc_engine* E) {
   }
   launch_kkt(1, E->d_slots, T1, nT1, A1, nA1, 1, s);
   launch_kkt(0, E->d_slots, T0, nT0, A0, nA0, 1, s);
-  launch_reduce(E->d_slots, E->d_ids, A, 1, s);
+  launch_reduce(E->d_slots, E->d_ids, A, 1, E->d_red2, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(E->h_scal, E->d_scal, (size_t)A * kScal * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1290,6 +1291,7 @@ static int engine_init(uc_engine* E) {
   HIPOK(hipMalloc(&E->d_ids, sizeof(int) * E->max_slots));
   HIPOK(hipHostMalloc((void**)&E->h_scal, sizeof(double) * kScal * E->max_slots, hipHostMallocDefault));
   HIPOK(hipMalloc(&E->d_scal, sizeof(double) * kScal * E->max_slots));
+  HIPOK(hipMalloc(&E->d_red2, sizeof(double) * kRedChunks * (RQ_N + CQ_N) * E->max_slots));
   for (auto& ev : E->ev) HIPOK(hipEventCreate(&ev));
   E->worker = std::thread(worker_main, E);
   return UC_LP_OK;
@@ -1308,6 +1310,7 @@ static void engine_free(uc_engine* E) {
   if (E->d_ids) (void)hipFree(E->d_ids);
   if (E->d_tiles) (void)hipFree(E->d_tiles);
   if (E->d_scal) (void)hipFree(E->d_scal);
+  if (E->d_red2) (void)hipFree(E->d_red2);
   if (E->h_scal) (void)hipHostFree(E->h_scal);
   for (auto& ev : E->ev)
     if (ev) (void)hipEventDestroy(ev);
@@ -1722,7 +1725,7 @@ extern "C" int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp
   int zero = 0;
   HIPOK(hipMemcpyAsync(E->d_ids, &zero, sizeof zero, hipMemcpyHostToDevice, s));
   launch_kkt(0, E->d_slots, E->d_tiles, S.t_nblk, E->d_tiles + S.t_nblk, S.a_nblk, 1, s);
-  launch_reduce(E->d_slots, E->d_ids, 1, 1, s);
+  launch_reduce(E->d_slots, E->d_ids, 1, 1, E->d_red2, s);
   double q[kScal];
   HIPOK(hipMemcpyAsync(q, D.scal, sizeof q, hipMemcpyDeviceToHost, s));
   HIPOK(hipStreamSynchronize(s));

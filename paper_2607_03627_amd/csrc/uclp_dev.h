@@ -127,7 +127,13 @@ void launch_dual(int prec, bool check, const SlotDev* slots, const Tile* tiles, 
                  hipEvent_t e1 = nullptr);
 void launch_kkt(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles,
                 const Tile* atiles, int natiles, int nscen, hipStream_t s);
-void launch_reduce(const SlotDev* slots, const int* slot_ids, int nslots, int nscen, hipStream_t s);
+// Two-level deterministic reduction of the KKT partials of each listed slot
+// into its scal: kRedChunks workgroups per slot each reduce a fixed range of
+// row blocks into red2 (nslots * kRedChunks * (RQ_N + CQ_N) doubles), then one
+// workgroup per slot reduces those in a fixed order.
+constexpr int kRedChunks = 64;
+void launch_reduce(const SlotDev* slots, const int* slot_ids, int nslots, int nscen, double* red2,
+                   hipStream_t s);
 void launch_finish(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles,
                    const Tile* atiles, int natiles, int kk, int nscen, hipStream_t s);
 void launch_promote(const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
