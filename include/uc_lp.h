@@ -115,6 +115,16 @@ typedef struct {
   double halpern_gamma;  /* reflection of the Halpern step in [0, 1]:
                             z <- w((1+g) T(z) - g z) + (1-w) z_restart;
                             1 = reflected Halpern (default), 0 = plain         */
+  double pw_max_change;  /* bound on one primal-weight update: the new weight
+                            stays within [w / this, w * this]; default 4,
+                            0 = unbounded                                     */
+  int32_t fp32_stall_checks; /* FP32 phase: continue in FP64 when the relative
+                            KKT error has not fallen below 0.9 of its best
+                            value for this many checks; default 24, 0 = never.
+                            (Near its rounding floor the FP32 iteration can
+                            take restarts on residual noise whose primal-weight
+                            updates then stall it; both guards bound that.)  */
+  int32_t reserved;      /* must be 0                                         */
 } uc_lp_opts;
 
 typedef struct {

@@ -729,6 +729,40 @@ __global__ __launch_bounds__(kThreads) void k_promote_y(const SlotDev* __restric
 // access, and one read of the matrix serves every scenario.
 constexpr int kLanes = 16;                       // lanes per row (>= nscen)
 constexpr int kRowsPerPass = kThreads / kLanes;  // rows per pass of the block
+constexpr int kMsUnroll = 4;                     // rows per thread in flight
+
+// One row's dot product for scenario sc from the staged entries [a, b): the
+// first kMsDot entries are unrolled (predicated) so their gathers issue
+// together, in entry order; longer rows continue in a loop.
+constexpr int kMsDot = 4;
+
+template <typename T>
+__device__ inline T row_dot_ms(int a, int b, const int* lc, const T* lv, const T* __restrict__ g, int ns, int sc) {
+  T v[kMsDot], p[kMsDot];
+#pragma unroll
+  for (int t = 0; t < kMsDot; ++t) {
+    v[t] = 0;
+    p[t] = 0;
+    if (a + t < b) {
+      v[t] = lv[a + t];
+      p[t] = g[(size_t)lc[a + t] * ns + sc];
+    }
+  }
+  T s = 0;
+#pragma unroll
+  for (int t = 0; t < kMsDot; ++t)
+    if (a + t < b) s += v[t] * p[t];
+  for (int k = a + kMsDot; k < b; ++k) s += lv[k] * g[(size_t)lc[k] * ns + sc];
+  return s;
+}
+
+template <typename T>
+__device__ inline T row_dot_ms_global(int a, int b, const int* __restrict__ col, const T* __restrict__ val,
+                                      const T* __restrict__ g, int ns, int sc) {
+  T s = 0;
+  for (int k = a; k < b; ++k) s += val[k] * g[(size_t)col[k] * ns + sc];
+  return s;
+}
 
 template <typename T>
 __device__ inline void stage_entries(const int* __restrict__ col, const T* __restrict__ val, int nz,
@@ -760,25 +794,60 @@ __global__ __launch_bounds__(kThreads) void k_primal_ms(const SlotDev* __restric
   const int ns = S.nscen;
   const int sc = threadIdx.x % kLanes;
   if (sc >= ns || !S.active[sc]) return;
+  const int fl = tl.flags;
   const T tau = (T)S.tau[sc];
   const double kk = (double)(S.k0[sc] + jiter);
   const T w = (T)((kk + 1.0) / (kk + 2.0));
   const T wa = (T)(1.0 / (kk + 2.0));
+  // full reflection: x is rebuilt from xbar and x0 as in k_primal
+  const bool full = S.gamma == 1.0;
+  const bool rebuild = full && jiter > 0;
+  T wp = 0, wap = 0;
+  if (rebuild) {
+    const double kp = (double)(S.k0[sc] + jiter - 1);
+    wp = (T)((kp + 1.0) / (kp + 2.0));
+    wap = (T)(1.0 / (kp + 2.0));
+  }
   const T* __restrict__ y = V.y;
-  for (int j = r0 + threadIdx.x / kLanes; j < r1; j += kRowsPerPass) {
-    const int a = ptr[j], b = ptr[j + 1];
-    T acc = 0;
-    if (staged)
-      for (int k = a - k0; k < b - k0; ++k) acc += lv[k] * y[(size_t)lc[k] * ns + sc];
-    else
-      for (int k = a; k < b; ++k) acc += V.tv[k] * y[(size_t)S.t_col[k] * ns + sc];
-    const size_t e = (size_t)j * ns + sc;
-    const T x = V.x[e];
-    const T xh = clampv<T>(x - tau * (V.c[e] - acc), V.l[e], V.u[e]);
-    const T xb = (T)2 * xh - x;
-    V.xbar[e] = xb;
-    if (CHECK) V.xhat[e] = xh;
-    else V.x[e] = w * (S.gamma == 1.0 ? xb : (T)(1.0 + S.gamma) * xh - (T)S.gamma * x) + wa * V.x0[e];
+  // kMsUnroll rows per thread at a time: their vector loads and gathers are
+  // all issued before the first epilogue
+  for (int jb = r0 + threadIdx.x / kLanes; jb < r1; jb += kMsUnroll * kRowsPerPass) {
+    T acc[kMsUnroll], x[kMsUnroll], c[kMsUnroll], l[kMsUnroll], u[kMsUnroll], xa[kMsUnroll];
+#pragma unroll
+    for (int q = 0; q < kMsUnroll; ++q) {
+      const int j = jb + q * kRowsPerPass;
+      acc[q] = x[q] = c[q] = l[q] = u[q] = xa[q] = 0;
+      if (j < r1) {
+        const size_t e = (size_t)j * ns + sc;
+        c[q] = (fl & kColC0) ? (T)0 : V.c[e];
+        u[q] = (fl & kColUInf) ? (T)INFINITY : V.u[e];
+        l[q] = (fl & kColL0) ? (T)0 : (fl & kColLInf) ? -(T)INFINITY : (fl & kColLNegU) ? -u[q] : V.l[e];
+        if (rebuild) {
+          xa[q] = V.x0[e];
+          x[q] = wp * V.xbar[e] + wap * xa[q];
+        } else {
+          x[q] = V.x[e];
+          if (!CHECK) xa[q] = V.x0[e];
+        }
+        acc[q] = staged ? row_dot_ms<T>(ptr[j] - k0, ptr[j + 1] - k0, lc, lv, y, ns, sc)
+                        : row_dot_ms_global<T>(ptr[j], ptr[j + 1], S.t_col, V.tv, y, ns, sc);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kMsUnroll; ++q) {
+      const int j = jb + q * kRowsPerPass;
+      if (j >= r1) break;
+      const size_t e = (size_t)j * ns + sc;
+      const T xh = clampv<T>(x[q] - tau * (c[q] - acc[q]), l[q], u[q]);
+      const T xb = (T)2 * xh - x[q];
+      V.xbar[e] = xb;
+      if (CHECK) {
+        V.xhat[e] = xh;
+        if (rebuild) V.x[e] = x[q];
+      } else if (!full) {
+        V.x[e] = w * ((T)(1.0 + S.gamma) * xh - (T)S.gamma * x[q]) + wa * xa[q];
+      }
+    }
   }
 }
 
@@ -803,24 +872,38 @@ __global__ __launch_bounds__(kThreads) void k_dual_ms(const SlotDev* __restrict_
   const int ns = S.nscen;
   const int sc = threadIdx.x % kLanes;
   if (sc >= ns || !S.active[sc]) return;
+  const bool b0 = (tl.flags & kRowB0) != 0;
   const T sigma = (T)S.sigma[sc];
   const double kk = (double)(S.k0[sc] + jiter);
   const T w = (T)((kk + 1.0) / (kk + 2.0));
   const T wa = (T)(1.0 / (kk + 2.0));
-  const T* __restrict__ xb = V.xbar;
-  for (int i = r0 + threadIdx.x / kLanes; i < r1; i += kRowsPerPass) {
-    const int a = ptr[i], b = ptr[i + 1];
-    T acc = 0;
-    if (staged)
-      for (int k = a - k0; k < b - k0; ++k) acc += lv[k] * xb[(size_t)lc[k] * ns + sc];
-    else
-      for (int k = a; k < b; ++k) acc += V.av[k] * xb[(size_t)S.a_col[k] * ns + sc];
-    const size_t e = (size_t)i * ns + sc;
-    const T y = V.y[e];
-    T yh = y + sigma * (V.b[e] - acc);
-    if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
-    if (CHECK) V.yhat[e] = yh;
-    else V.y[e] = w * ((T)(1.0 + S.gamma) * yh - (T)S.gamma * y) + wa * V.y0[e];
+  const T g1 = (T)(1.0 + S.gamma), g = (T)S.gamma;
+  const T* __restrict__ xbv = V.xbar;
+  for (int ib = r0 + threadIdx.x / kLanes; ib < r1; ib += kMsUnroll * kRowsPerPass) {
+    T acc[kMsUnroll], y[kMsUnroll], bi[kMsUnroll], ya[kMsUnroll];
+#pragma unroll
+    for (int q = 0; q < kMsUnroll; ++q) {
+      const int i = ib + q * kRowsPerPass;
+      acc[q] = y[q] = bi[q] = ya[q] = 0;
+      if (i < r1) {
+        const size_t e = (size_t)i * ns + sc;
+        bi[q] = b0 ? (T)0 : V.b[e];
+        y[q] = V.y[e];
+        if (!CHECK) ya[q] = V.y0[e];
+        acc[q] = staged ? row_dot_ms<T>(ptr[i] - k0, ptr[i + 1] - k0, lc, lv, xbv, ns, sc)
+                        : row_dot_ms_global<T>(ptr[i], ptr[i + 1], S.a_col, V.av, xbv, ns, sc);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kMsUnroll; ++q) {
+      const int i = ib + q * kRowsPerPass;
+      if (i >= r1) break;
+      const size_t e = (size_t)i * ns + sc;
+      T yh = y[q] + sigma * (bi[q] - acc[q]);
+      if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
+      if (CHECK) V.yhat[e] = yh;
+      else V.y[e] = w * (g1 * yh - g * y[q]) + wa * ya[q];
+    }
   }
 }
 
@@ -952,22 +1035,48 @@ __global__ __launch_bounds__(kThreads) void k_kkt_cols_ms(const SlotDev* __restr
 }
 
 // scal[s * kScal + q]: thread (q, s) sums its partial over all blocks in order
-__global__ __launch_bounds__(kThreads) void k_reduce_ms(const SlotDev* __restrict__ slots) {
+// Two-level reduction of the scenario partials: kRedChunksMs workgroups each
+// reduce a fixed range of row blocks for every (quantity, scenario), then one
+// workgroup reduces the chunks in order.  Deterministic.
+constexpr int kRedChunksMs = 256;
+
+__global__ __launch_bounds__(kThreads) void k_reduce_ms_part(const SlotDev* __restrict__ slots,
+                                                             double* __restrict__ red2) {
+  const SlotDev& S = slots[0];
+  const int g = blockIdx.x;
+  const int idx = threadIdx.x;
+  if (idx >= (RQ_N + CQ_N) * kLanes) return;
+  const int tq = idx / kLanes;
+  const int sc = idx % kLanes;
+  if (sc >= S.nscen) return;
+  double acc = 0.0;
+  if (tq < RQ_N) {
+    const bool mx = tq == RQ_RESMAX;
+    const int b0 = (int)((int64_t)S.a_nblk * g / kRedChunksMs), b1 = (int)((int64_t)S.a_nblk * (g + 1) / kRedChunksMs);
+    for (int b = b0; b < b1; ++b) {
+      const double v = S.part_a[((size_t)b * RQ_N + tq) * kMaxScen + sc];
+      acc = mx ? fmax(acc, v) : acc + v;
+    }
+  } else {
+    const int k = tq - RQ_N;
+    const int b0 = (int)((int64_t)S.t_nblk * g / kRedChunksMs), b1 = (int)((int64_t)S.t_nblk * (g + 1) / kRedChunksMs);
+    for (int b = b0; b < b1; ++b) acc += S.part_t[((size_t)b * CQ_N + k) * kMaxScen + sc];
+  }
+  red2[((size_t)g * (RQ_N + CQ_N) + tq) * kMaxScen + sc] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_ms(const SlotDev* __restrict__ slots,
+                                                        const double* __restrict__ red2) {
   const SlotDev& S = slots[0];
   for (int idx = threadIdx.x; idx < (RQ_N + CQ_N) * kLanes; idx += kThreads) {
     const int tq = idx / kLanes;
     const int sc = idx % kLanes;
     if (sc >= S.nscen) continue;
+    const bool mx = tq == RQ_RESMAX;
     double acc = 0.0;
-    if (tq < RQ_N) {
-      const bool mx = tq == RQ_RESMAX;
-      for (int b = 0; b < S.a_nblk; ++b) {
-        const double v = S.part_a[((size_t)b * RQ_N + tq) * kMaxScen + sc];
-        acc = mx ? fmax(acc, v) : acc + v;
-      }
-    } else {
-      const int k = tq - RQ_N;
-      for (int b = 0; b < S.t_nblk; ++b) acc += S.part_t[((size_t)b * CQ_N + k) * kMaxScen + sc];
+    for (int g = 0; g < kRedChunksMs; ++g) {
+      const double v = red2[((size_t)g * (RQ_N + CQ_N) + tq) * kMaxScen + sc];
+      acc = mx ? fmax(acc, v) : acc + v;
     }
     S.scal[sc * kScal + tq] = acc;
   }
@@ -1646,7 +1755,7 @@ void launch_dual_ms(int prec, bool check, const SlotDev* slots, const Tile* tile
 }
 
 void launch_kkt_ms(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
-                   int natiles, hipStream_t s) {
+                   int natiles, double* red2, hipStream_t s) {
   if (prec == 1) {
     if (natiles > 0) k_kkt_rows_ms<float><<<xcd_grid(natiles), kThreads, 0, s>>>(slots, atiles, natiles);
     if (nttiles > 0) k_kkt_cols_ms<float><<<xcd_grid(nttiles), kThreads, 0, s>>>(slots, ttiles, nttiles);
@@ -1654,8 +1763,11 @@ void launch_kkt_ms(int prec, const SlotDev* slots, const Tile* ttiles, int nttil
     if (natiles > 0) k_kkt_rows_ms<double><<<xcd_grid(natiles), kThreads, 0, s>>>(slots, atiles, natiles);
     if (nttiles > 0) k_kkt_cols_ms<double><<<xcd_grid(nttiles), kThreads, 0, s>>>(slots, ttiles, nttiles);
   }
-  k_reduce_ms<<<1, kThreads, 0, s>>>(slots);
+  k_reduce_ms_part<<<kRedChunksMs, kThreads, 0, s>>>(slots, red2);
+  k_reduce_ms<<<1, kThreads, 0, s>>>(slots, red2);
 }
+
+size_t red2_ms_doubles() { return (size_t)kRedChunksMs * (RQ_N + CQ_N) * kMaxScen; }
 
 void launch_finish_ms(int prec, const SlotDev* slots, int64_t nx, int64_t ny, int kk, hipStream_t s) {
   if (prec == 1) {

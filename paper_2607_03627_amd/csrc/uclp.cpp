@@ -97,6 +97,9 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->restart_artificial = 0.36;
   o->pw_smoothing = 0.8;
   o->halpern_gamma = 1.0;
+  o->pw_max_change = 4.0;
+  o->fp32_stall_checks = 24;
+  o->reserved = 0;
 }
 
 static int check_opts(const uc_lp_opts& o) {
@@ -112,7 +115,8 @@ static int check_opts(const uc_lp_opts& o) {
   if (o.spmv_algo != UC_LP_SPMV_ROWSPLIT) return fail(UC_LP_ENOTSUP, "spmv_algo %d for PDHG", o.spmv_algo);
   if (!(o.restart_sufficient > 0 && o.restart_sufficient <= o.restart_necessary && o.restart_necessary < 1) ||
       !(o.restart_artificial > 0 && o.restart_artificial <= 1) || !(o.pw_smoothing >= 0 && o.pw_smoothing <= 1) ||
-      (o.restart_to_current != 0 && o.restart_to_current != 1) || !(o.halpern_gamma >= 0 && o.halpern_gamma <= 1))
+      (o.restart_to_current != 0 && o.restart_to_current != 1) || !(o.halpern_gamma >= 0 && o.halpern_gamma <= 1) ||
+      !(o.pw_max_change == 0 || o.pw_max_change >= 1) || o.fp32_stall_checks < 0 || o.reserved != 0)
     return fail(UC_LP_EINVAL, "restart / primal-weight parameters out of range");
   return UC_LP_OK;
 }
@@ -545,6 +549,9 @@ struct PdhgState {
   bool r_start_set = false, r_prev_set = false;
   double r_start = 0, r_prev = 0;
   double t_start = 0;
+  double best_kkt = 0;       // FP32 phase: best relative KKT error so far
+  long long best_check = 0;  // check index at which it was reached
+  long long checks = 0;
 };
 
 struct uc_engine {
@@ -928,6 +935,16 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
         out.status = UC_LP_OPTIMAL;
       }
     }
+    // an FP32 phase that stopped improving continues in FP64
+    ++st.checks;
+    if (st.prec == 1 && !out.terminate) {
+      if (st.best_check == 0 || in.rel_kkt < 0.9 * st.best_kkt) {
+        st.best_kkt = in.rel_kkt;
+        st.best_check = st.checks;
+      } else if (o.fp32_stall_checks > 0 && st.checks - st.best_check >= o.fp32_stall_checks) {
+        out.promote = true;
+      }
+    }
     if (!out.terminate && st.iters >= o.iter_limit) {
       out.terminate = true;
       out.status = UC_LP_ITER_LIMIT;
@@ -956,7 +973,11 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
       const double dX = std::sqrt(std::max(q[RQ_N + CQ_DX0], 0.0));
       const double dY = std::sqrt(std::max(q[RQ_DY0], 0.0));
       const double th = o.pw_smoothing;
-      if (dX > 1e-10 && dY > 1e-10) st.omega = std::exp(th * std::log(dY / dX) + (1.0 - th) * std::log(st.omega));
+      if (dX > 1e-10 && dY > 1e-10) {
+        double w = std::exp(th * std::log(dY / dX) + (1.0 - th) * std::log(st.omega));
+        if (o.pw_max_change >= 1) w = std::min(std::max(w, st.omega / o.pw_max_change), st.omega * o.pw_max_change);
+        st.omega = w;
+      }
       st.k_inner = 0;
       st.r_start_set = false;
       st.r_prev_set = false;
@@ -1927,7 +1948,7 @@ extern "C" int uc_copy_bench(int device, size_t bytes, int32_t reps, double* gbp
 struct ScenArena {
   Arena ar;
   double *c_in, *l_in, *u_in, *b_in, *x_out, *y_out, *x_warm, *y_warm;
-  double *part_a, *part_t, *scal;
+  double *part_a, *part_t, *scal, *red2;
   Vecs<float> f;
   Vecs<double> d;
   SlotDev* slot_dev;
@@ -1948,6 +1969,7 @@ static void carve_scen(ScenArena& A, const HostProblem& P, int S) {
   A.part_a = a.take<double>(P.a_blk.size() * RQ_N * kMaxScen);
   A.part_t = a.take<double>(P.t_blk.size() * CQ_N * kMaxScen);
   A.scal = a.take<double>((size_t)kScal * kMaxScen);
+  A.red2 = a.take<double>(red2_ms_doubles());
   carve_vecs(a, A.f, n, m, S);
   carve_vecs(a, A.d, n, m, S);
   A.slot_dev = a.take<SlotDev>(1);
@@ -1992,8 +2014,16 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
     Q.c.assign(ni, 0.0);
     Q.l.assign(ni, 0.0);
     Q.u.assign(ni, 0.0);
+    Q.t_blk = P.t_blk;  // for the block flags
+    Q.a_blk = P.a_blk;
     presolve_data(Q);
     if (Q.infeasible) return fail(UC_LP_EINVAL, "scenario %d is infeasible by its empty rows", s);
+  }
+  // a block flag holds for the batch when it holds for every scenario
+  std::vector<int> tflag = SP[0].t_flag, aflag = SP[0].a_flag;
+  for (int s = 1; s < S; ++s) {
+    for (size_t k = 0; k < tflag.size(); ++k) tflag[k] &= SP[s].t_flag[k];
+    for (size_t k = 0; k < aflag.size(); ++k) aflag[k] &= SP[s].a_flag[k];
   }
   int rc = debug_ready(base);
   if (rc) return rc;
@@ -2104,8 +2134,8 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   launch_init_iterates(A.slot_dev, phase, xin, yin, ni, mi, P.m_eq, S, st);
   std::vector<Tile> tl;
   const int nt = (int)P.t_blk.size() - 1, na = (int)P.a_blk.size() - 1;
-  push_tiles(tl, 0, P.t_blk, P.t_ptr);
-  push_tiles(tl, 0, P.a_blk, P.a_ptr);
+  push_tiles(tl, 0, P.t_blk, P.t_ptr, &tflag);
+  push_tiles(tl, 0, P.a_blk, P.a_ptr, &aflag);
   SCEN_HIP(hipMemcpyAsync(A.tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
   SCEN_HIP(hipStreamSynchronize(st));
   const Tile* TT = A.tiles;
@@ -2127,7 +2157,7 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
       launch_primal_ms(phase, check, A.slot_dev, TT, nt, j, st);
       launch_dual_ms(phase, check, A.slot_dev, TA, na, j, st);
     }
-    launch_kkt_ms(phase, A.slot_dev, TT, nt, TA, na, st);
+    launch_kkt_ms(phase, A.slot_dev, TT, nt, TA, na, A.red2, st);
     SCEN_HIP(hipMemcpyAsync(q.data(), A.scal, q.size() * 8, hipMemcpyDeviceToHost, st));
     SCEN_HIP(hipStreamSynchronize(st));
     SCEN_HIP(hipGetLastError());

@@ -146,7 +146,9 @@ void launch_dual_ms(int prec, bool check, const SlotDev* slots, const Tile* tile
                     hipStream_t s);
 // KKT partials and their reduction into slots[0].scal[s * kScal + q]
 void launch_kkt_ms(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
-                   int natiles, hipStream_t s);
+                   int natiles, double* red2, hipStream_t s);
+// doubles of the red2 buffer that launch_kkt_ms needs
+size_t red2_ms_doubles();
 void launch_finish_ms(int prec, const SlotDev* slots, int64_t nx, int64_t ny, int kk, hipStream_t s);
 void launch_promote_ms(const SlotDev* slots, int64_t nx, int64_t ny, hipStream_t s);
 

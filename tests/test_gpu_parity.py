@@ -267,6 +267,34 @@ def test_tiny_partial_reflection_matches_simplex_oracle(gamma):
     assert abs(k.pobj - z) <= 1e-6 * abs(z)
 
 
+def test_fp32_stall_continues_in_fp64():
+    # a stall window of one check hands the solve to FP64 at the first check
+    # without a 10% improvement; the FP64 phase still reaches the target
+    lp = make_instance("medium", 1)
+    say("case medium fp32 stall")
+    z = GOLDEN["medium/1"]["obj"]
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP32_MIXED, fp32_stall_checks=1)
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    assert 0 < info["iters_fp64"] < info["iters"]
+    assert info["precision_now"] == uclp.UC_LP_FP64
+    k = kkt(lp, x, y)
+    assert k.rel_kkt <= 1e-4 * 1.001
+    assert abs(k.pobj - z) <= 1e-3 * abs(z)
+
+
+def test_weight_bound_of_one_fixes_the_primal_weight():
+    # a change bound of 1 keeps the initial weight whatever the smoothing, so
+    # two smoothings take the same iterates; unbounded, they do not
+    lp = make_instance("tiny", 2)
+    say("case tiny weight bound")
+    _, _, a = solve(lp, precision=uclp.UC_LP_FP64, eps_rel=1e-6, pw_max_change=1.0, pw_smoothing=0.8)
+    _, _, b = solve(lp, precision=uclp.UC_LP_FP64, eps_rel=1e-6, pw_max_change=1.0, pw_smoothing=0.5)
+    _, _, c = solve(lp, precision=uclp.UC_LP_FP64, eps_rel=1e-6, pw_max_change=0.0, pw_smoothing=0.5)
+    assert a["restarts"] > 0 and c["restarts"] > 0
+    assert (a["iters"], a["pobj"], a["omega"]) == (b["iters"], b["pobj"], b["omega"])
+    assert c["omega"] != a["omega"]
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_tiny_fp32_modes(seed):
     lp = make_instance("tiny", seed)
