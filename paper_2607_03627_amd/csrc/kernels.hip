@@ -126,6 +126,20 @@ __device__ inline void block_rows(const int* __restrict__ ptr, int r0, int r1, A
 // PDHG half-steps (one scenario per slot)
 // ---------------------------------------------------------------------------
 
+// Pointers that the half-steps read through are cast to the global address
+// space: loaded from the slot descriptor they are generic, and generic loads
+// may alias LDS, which makes the compiler wait for each gather before the
+// next product is written to LDS.
+#define UCLP_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const UCLP_GLOBAL T* gld(const T* p) {
+  return (const UCLP_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ UCLP_GLOBAL T* gst(T* p) {
+  return (UCLP_GLOBAL T*)p;
+}
+
 // Staging of one row block's products val[k] * g[col[k]] into LDS.  Every
 // thread first issues all of its (at most kItems) column-index and value
 // loads, then all gathers, so each wave keeps many independent loads in
@@ -156,48 +170,51 @@ __device__ inline void stage_products(const int* __restrict__ col, const T* __re
 // neighbouring lanes fall on neighbouring cache lines, and each product is
 // written to its CSR position dst[k] so the per-row sums keep CSR order.
 template <typename T, typename G>
-__device__ inline void stage_sorted(const int* __restrict__ cs, const T* __restrict__ vs,
-                                    const unsigned short* __restrict__ dst, const G* __restrict__ g,
-                                    int nz, T* lds) {
-  int c[kItems];
-  int d[kItems];
-  T v[kItems];
+__device__ inline void stage_sorted(const int* cs_, const T* vs_, const unsigned short* dst_, const G* g_, int nz,
+                                    T* lds) {
+  // straight-line loads: items past the block's end re-read its last entry
+  // and are not written, so all gathers of a thread are in flight together
+  if (nz <= 0) return;
+  const UCLP_GLOBAL int* cs = gld(cs_);
+  const UCLP_GLOBAL T* vs = gld(vs_);
+  const UCLP_GLOBAL unsigned short* dst = gld(dst_);
+  const UCLP_GLOBAL G* g = gld(g_);
+  int c[kItems], d[kItems];
+  T v[kItems], gv[kItems];
 #pragma unroll
   for (int u = 0; u < kItems; ++u) {
-    const int k = threadIdx.x + u * kThreads;
-    if (k < nz) {
-      c[u] = cs[k];
-      v[u] = vs[k];
-      d[u] = dst[k];
-    }
+    const int k = min((int)threadIdx.x + u * kThreads, nz - 1);
+    c[u] = cs[k];
+    v[u] = vs[k];
+    d[u] = dst[k];
   }
 #pragma unroll
-  for (int u = 0; u < kItems; ++u) {
-    const int k = threadIdx.x + u * kThreads;
-    if (k < nz) lds[d[u]] = v[u] * (T)g[c[u]];
-  }
+  for (int u = 0; u < kItems; ++u) gv[u] = (T)g[c[u]];
+#pragma unroll
+  for (int u = 0; u < kItems; ++u)
+    if ((int)threadIdx.x + u * kThreads < nz) lds[d[u]] = v[u] * gv[u];
 }
 
 // The same from the packed words: one 4-byte read per entry for index and slot.
 template <typename T, typename G>
-__device__ inline void stage_packed(const unsigned* __restrict__ pk, const T* __restrict__ vs, int base,
-                                    const G* __restrict__ g, int nz, T* lds) {
+__device__ inline void stage_packed(const unsigned* pk_, const T* vs_, int base, const G* g_, int nz, T* lds) {
+  if (nz <= 0) return;
+  const UCLP_GLOBAL unsigned* pk = gld(pk_);
+  const UCLP_GLOBAL T* vs = gld(vs_);
+  const UCLP_GLOBAL G* gb = gld(g_) + base;
   unsigned p[kItems];
-  T v[kItems];
+  T v[kItems], gv[kItems];
 #pragma unroll
   for (int u = 0; u < kItems; ++u) {
-    const int k = threadIdx.x + u * kThreads;
-    if (k < nz) {
-      p[u] = pk[k];
-      v[u] = vs[k];
-    }
+    const int k = min((int)threadIdx.x + u * kThreads, nz - 1);
+    p[u] = pk[k];
+    v[u] = vs[k];
   }
-  const G* __restrict__ gb = g + base;
 #pragma unroll
-  for (int u = 0; u < kItems; ++u) {
-    const int k = threadIdx.x + u * kThreads;
-    if (k < nz) lds[p[u] >> kPackShift] = v[u] * (T)gb[p[u] & kPackMask];
-  }
+  for (int u = 0; u < kItems; ++u) gv[u] = (T)gb[p[u] & kPackMask];
+#pragma unroll
+  for (int u = 0; u < kItems; ++u)
+    if ((int)threadIdx.x + u * kThreads < nz) lds[p[u] >> kPackShift] = v[u] * gv[u];
 }
 
 // Visit the entries of a row block that fits the LDS tile in column order:
@@ -291,7 +308,7 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
   const int r0 = tl.r0, r1 = tl.r1;
-  const unsigned short* __restrict__ rend = S.t_end;
+  const UCLP_GLOBAL unsigned short* rend = gld(S.t_end);
   const int k0 = tl.k0;
   const int nz = tl.k1 - k0;
   const int fl = tl.flags;
@@ -303,27 +320,28 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
     wp = (T)((kp + 1.0) / (kp + 2.0));
     wap = (T)(1.0 / (kp + 2.0));
   }
-  // epilogue operands first, so their loads overlap the gathers
+  // epilogue operands first, so their loads overlap the gathers.  The loads
+  // are straight-line: a thread past the block's last row loads that row
+  // and skips the epilogue; values that depend on loads (x rebuilt, l = -u)
+  // are formed after the barrier.
   int a[kRowsPerThread], b[kRowsPerThread];
-  T c[kRowsPerThread], l[kRowsPerThread], u[kRowsPerThread], x[kRowsPerThread], xa[kRowsPerThread];
+  T c[kRowsPerThread], lr[kRowsPerThread], u[kRowsPerThread], xv[kRowsPerThread], xa[kRowsPerThread];
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
-    const int j = r0 + threadIdx.x + q * kThreads;
-    a[q] = b[q] = 0;
-    c[q] = l[q] = u[q] = x[q] = xa[q] = 0;
-    if (j < r1) {
-      a[q] = j == r0 ? 0 : rend[j - 1];
-      b[q] = rend[j];
-      c[q] = (fl & kColC0) ? (T)0 : V.c[j];
-      u[q] = (fl & kColUInf) ? (T)INFINITY : V.u[j];
-      l[q] = (fl & kColL0) ? (T)0 : (fl & kColLInf) ? -(T)INFINITY : (fl & kColLNegU) ? -u[q] : V.l[j];
-      if (rebuild) {
-        xa[q] = V.x0[j];
-        x[q] = wp * V.xbar[j] + wap * xa[q];
-      } else {
-        x[q] = V.x[j];
-        if (!CHECK) xa[q] = V.x0[j];
-      }
+    const int j = min(r0 + (int)threadIdx.x + q * kThreads, r1 - 1);
+    const int ap = rend[max(j - 1, r0)];
+    a[q] = j == r0 ? 0 : ap;
+    b[q] = rend[j];
+    c[q] = (fl & kColC0) ? (T)0 : gld(V.c)[j];
+    u[q] = (fl & kColUInf) ? (T)INFINITY : gld(V.u)[j];
+    lr[q] = (fl & (kColL0 | kColLInf | kColLNegU)) ? (T)0 : gld(V.l)[j];
+    xa[q] = 0;
+    if (rebuild) {
+      xa[q] = gld(V.x0)[j];
+      xv[q] = gld(V.xbar)[j];
+    } else {
+      xv[q] = gld(V.x)[j];
+      if (!CHECK) xa[q] = gld(V.x0)[j];
     }
   }
   T s[kRowsPerThread];
@@ -351,14 +369,16 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   for (int q = 0; q < kRowsPerThread; ++q) {
     const int j = r0 + threadIdx.x + q * kThreads;
     if (j >= r1) break;
-    const T xh = clampv<T>(x[q] - tau * (c[q] - s[q]), l[q], u[q]);
-    const T xb = (T)2 * xh - x[q];
-    V.xbar[j] = xb;
+    const T x = rebuild ? wp * xv[q] + wap * xa[q] : xv[q];
+    const T l = (fl & kColL0) ? (T)0 : (fl & kColLInf) ? -(T)INFINITY : (fl & kColLNegU) ? -u[q] : lr[q];
+    const T xh = clampv<T>(x - tau * (c[q] - s[q]), l, u[q]);
+    const T xb = (T)2 * xh - x;
+    gst(V.xbar)[j] = xb;
     if (CHECK) {
-      V.xhat[j] = xh;
-      if (rebuild) V.x[j] = x[q];
+      gst(V.xhat)[j] = xh;
+      if (rebuild) gst(V.x)[j] = x;
     } else if (!full) {
-      V.x[j] = w * ((T)(1.0 + S.gamma) * xh - (T)S.gamma * x[q]) + wa * xa[q];
+      gst(V.x)[j] = w * ((T)(1.0 + S.gamma) * xh - (T)S.gamma * x) + wa * xa[q];
     }
   }
 }
@@ -378,23 +398,21 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
   const int r0 = tl.r0, r1 = tl.r1;
-  const unsigned short* __restrict__ rend = S.a_end;
+  const UCLP_GLOBAL unsigned short* rend = gld(S.a_end);
   const int k0 = tl.k0;
   const int nz = tl.k1 - k0;
+  // straight-line epilogue loads, as in k_primal
   int a[kRowsPerThread], b[kRowsPerThread];
   T bi[kRowsPerThread], y[kRowsPerThread], ya[kRowsPerThread];
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
-    const int i = r0 + threadIdx.x + q * kThreads;
-    a[q] = b[q] = 0;
-    bi[q] = y[q] = ya[q] = 0;
-    if (i < r1) {
-      a[q] = i == r0 ? 0 : rend[i - 1];
-      b[q] = rend[i];
-      bi[q] = (tl.flags & kRowB0) ? (T)0 : V.b[i];
-      y[q] = V.y[i];
-      if (!CHECK) ya[q] = V.y0[i];
-    }
+    const int i = min(r0 + (int)threadIdx.x + q * kThreads, r1 - 1);
+    const int ap = rend[max(i - 1, r0)];
+    a[q] = i == r0 ? 0 : ap;
+    b[q] = rend[i];
+    bi[q] = (tl.flags & kRowB0) ? (T)0 : gld(V.b)[i];
+    y[q] = gld(V.y)[i];
+    ya[q] = CHECK ? (T)0 : gld(V.y0)[i];
   }
   T s[kRowsPerThread];
   if (nz <= kNnzTile) {
@@ -424,8 +442,8 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
     if (i >= r1) break;
     T yh = y[q] + sigma * (bi[q] - s[q]);
     if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
-    if (CHECK) V.yhat[i] = yh;
-    else V.y[i] = w * (g1 * yh - g * y[q]) + wa * ya[q];
+    if (CHECK) gst(V.yhat)[i] = yh;
+    else gst(V.y)[i] = w * (g1 * yh - g * y[q]) + wa * ya[q];
   }
 }
 
