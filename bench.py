@@ -125,8 +125,9 @@ def serving_leg(seed=0, n_requests=64, eps=1e-8, iter_limit=400000):
 
 def scenario_leg(base_lp, n_scen=16):
     """Scenario batch over the shared matrix (load x U[0.85,1.15] per bus, cost
-    x U[0.95,1.05] per unit), warm-started from the nominal solution, against
-    sequential plain FP64 solves of the same scenarios, all to 1e-4."""
+    x U[0.95,1.05] per unit), warm-started from the nominal solution and cold,
+    against sequential plain FP64 solves and sequential single-LP FP32 solves
+    of the same scenarios, all to 1e-4."""
     import numpy as np
 
     from paper_2607_03627_amd import uclp
@@ -148,6 +149,12 @@ def scenario_leg(base_lp, n_scen=16):
         out["batch_iters"] = [i.iters for i in infos]
         out["batch_status"] = [uclp.STATUS_NAMES[i.status] for i in infos]
         out["batch_rel_kkt_max"] = max(i.rel_kkt for i in infos)
+        out["batch_iters_fp64"] = [i.iters_fp64 for i in infos]
+        t = time.perf_counter()
+        _, _, infos = uclp.uc_lp_solve_scenarios(h, base_lp.n, base_lp.m, c, b, lb, ub)
+        out["batch_cold_s"] = time.perf_counter() - t
+        out["batch_cold_iters"] = [i.iters for i in infos]
+        out["batch_cold_status"] = [uclp.STATUS_NAMES[i.status] for i in infos]
     finally:
         uclp.uc_lp_destroy(h)
     log(f"[bench] scenarios batch: {out}")
@@ -164,6 +171,20 @@ def scenario_leg(base_lp, n_scen=16):
     out["sequential_iters"] = its
     out["speedup_vs_sequential"] = seq / out["batch_warm_s"]
     log(f"[bench] scenarios sequential: {seq:.2f}s")
+    # the same scenarios one at a time on the single-LP FP32 path
+    seq32 = 0.0
+    its32 = []
+    for k in range(n_scen):
+        lp_k = base_lp.with_data(c=c[k], b=b[k], lb=lb[k], ub=ub[k])
+        _, _, info = uclp.solve(lp_k, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-4),
+                                timeout_s=600)
+        seq32 += info["t_total_s"]
+        its32.append(info["iters"])
+    out["sequential_fp32_cold_s"] = seq32
+    out["sequential_fp32_iters"] = its32
+    out["speedup_vs_sequential_fp32"] = seq32 / out["batch_warm_s"]
+    out["cold_batch_speedup_vs_sequential_fp32"] = seq32 / out["batch_cold_s"]
+    log(f"[bench] scenarios sequential fp32: {seq32:.2f}s")
     return out
 
 

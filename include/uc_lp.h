@@ -120,7 +120,8 @@ typedef struct {
                             0 = unbounded                                     */
   int32_t fp32_stall_checks; /* FP32 phase: continue in FP64 when the relative
                             KKT error has not fallen below 0.9 of its best
-                            value for this many checks; default 24, 0 = never.
+                            value for this many checks and that best is within
+                            10x of the target; default 24, 0 = never.
                             (Near its rounding floor the FP32 iteration can
                             take restarts on residual noise whose primal-weight
                             updates then stall it; both guards bound that.)  */

@@ -217,21 +217,43 @@ __device__ inline void stage_packed(const unsigned* pk_, const T* vs_, int base,
     if ((int)threadIdx.x + u * kThreads < nz) lds[p[u] >> kPackShift] = v[u] * gv[u];
 }
 
-// Visit the entries of a row block that fits the LDS tile in column order:
-// visit(k, g, slot) gets the entry's position k in the column-ordered arrays,
-// its gathered index g and its CSR position slot within the block.
-template <typename Visit>
-__device__ inline void for_sorted(const Tile& tl, const unsigned* __restrict__ pk, const int* __restrict__ cs,
-                                  const unsigned short* __restrict__ dst, Visit visit) {
+// The entries of a row block that fits the LDS tile, in column order, kItems
+// per thread: load(k, g) gets an entry's position k in the column-ordered
+// arrays and its gathered index g and returns its value(s); store(slot, v)
+// then writes them at the entry's CSR position.  All loads of a thread are
+// issued before its first store (items past the block's end repeat its last
+// entry and are not stored).
+template <typename V, typename Load, typename Store>
+__device__ inline void for_sorted(const Tile& tl, const unsigned* pk_, const int* cs_, const unsigned short* dst_,
+                                  Load load, Store store) {
   const int k0 = tl.k0, nz = tl.k1 - tl.k0;
+  if (nz <= 0) return;
+  int kk[kItems], g[kItems], sl[kItems];
   if (tl.base >= 0) {
-    for (int k = threadIdx.x; k < nz; k += kThreads) {
-      const unsigned p = pk[k0 + k];
-      visit(k0 + k, tl.base + (int)(p & kPackMask), (int)(p >> kPackShift));
+    const UCLP_GLOBAL unsigned* pk = gld(pk_);
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+      kk[u] = k0 + min((int)threadIdx.x + u * kThreads, nz - 1);
+      const unsigned p = pk[kk[u]];
+      g[u] = tl.base + (int)(p & kPackMask);
+      sl[u] = (int)(p >> kPackShift);
     }
   } else {
-    for (int k = threadIdx.x; k < nz; k += kThreads) visit(k0 + k, cs[k0 + k], (int)dst[k0 + k]);
+    const UCLP_GLOBAL int* cs = gld(cs_);
+    const UCLP_GLOBAL unsigned short* dst = gld(dst_);
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+      kk[u] = k0 + min((int)threadIdx.x + u * kThreads, nz - 1);
+      g[u] = cs[kk[u]];
+      sl[u] = (int)dst[kk[u]];
+    }
   }
+  V v[kItems];
+#pragma unroll
+  for (int u = 0; u < kItems; ++u) v[u] = load(kk[u], g[u]);
+#pragma unroll
+  for (int u = 0; u < kItems; ++u)
+    if ((int)threadIdx.x + u * kThreads < nz) store(sl[u], v[u]);
 }
 
 // block_rows over a tile whose entries are also stored in column order: a
@@ -245,7 +267,7 @@ __device__ inline void block_rows_sorted(const Tile& tl, const int* __restrict__
                                          PS psorted, PC pcsr, F f) {
   const int r0 = tl.r0, r1 = tl.r1, k0 = tl.k0, k1 = tl.k1;
   if (k1 - k0 <= kNnzTile) {
-    for_sorted(tl, pk, cs, dst, [&](int k, int g, int slot) { lds[slot] = psorted(k, g); });
+    for_sorted<ACC>(tl, pk, cs, dst, psorted, [&](int slot, ACC v) { lds[slot] = v; });
     __syncthreads();
     for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
       const int a = ptr[r] - k0;
@@ -490,13 +512,23 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict
     q[RQ_RESMAX] = fmax(q[RQ_RESMAX], fabs(ru));
   };
   if (nz <= kNnzTile) {
-    const double* __restrict__ vs = S.d.avs;
-    for_sorted(tl, S.a_pk, S.a_cs, S.a_dst, [&](int k, int c, int slot) {
-      const double v = vs[k];
-      const double a = (double)xh[c];
-      lds1[slot] = v * a;
-      lds2[slot] = v * (a - (double)x[c]);
-    });
+    const UCLP_GLOBAL double* vs = gld(S.d.avs);
+    const UCLP_GLOBAL T* gxh = gld(xh);
+    const UCLP_GLOBAL T* gx = gld(x);
+    struct P2 {
+      double p1, p2;
+    };
+    for_sorted<P2>(
+        tl, S.a_pk, S.a_cs, S.a_dst,
+        [&](int k, int c) {
+          const double v = vs[k];
+          const double a = (double)gxh[c];
+          return P2{v * a, v * (a - (double)gx[c])};
+        },
+        [&](int slot, P2 p) {
+          lds1[slot] = p.p1;
+          lds2[slot] = p.p2;
+        });
     __syncthreads();
     for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
       double s1 = 0, s2 = 0;
@@ -562,8 +594,10 @@ __global__ __launch_bounds__(kThreads) void k_kkt_cols(const SlotDev* __restrict
   double q[CQ_N] = {0, 0, 0, 0, 0};
   const bool is_max[CQ_N] = {false, false, false, false, false};
   const double* __restrict__ vs = S.d.tvs;
+  const UCLP_GLOBAL double* gvs = gld(vs);
+  const UCLP_GLOBAL T* gyh = gld(yh);
   block_rows_sorted<double>(tl, S.t_ptr, S.t_pk, S.t_cs, S.t_dst, lds, red,
-                     [&](int k, int c) { return vs[k] * (double)yh[c]; },
+                     [&](int k, int c) { return gvs[k] * (double)gyh[c]; },
                      [&](int k) { return val[k] * (double)yh[col[k]]; },
                      [&](int j, double s) {
                        const double c = S.d.c[j];
@@ -755,18 +789,16 @@ constexpr int kMsUnroll = 4;                     // rows per thread in flight
 constexpr int kMsDot = 4;
 
 template <typename T>
-__device__ inline T row_dot_ms(int a, int b, const int* lc, const T* lv, const T* __restrict__ g, int ns, int sc) {
+__device__ inline T row_dot_ms(int a, int b, const int* lc, const T* lv, const UCLP_GLOBAL T* g, int ns, int sc) {
+  T s = 0;
+  if (b <= a) return s;
   T v[kMsDot], p[kMsDot];
 #pragma unroll
   for (int t = 0; t < kMsDot; ++t) {
-    v[t] = 0;
-    p[t] = 0;
-    if (a + t < b) {
-      v[t] = lv[a + t];
-      p[t] = g[(size_t)lc[a + t] * ns + sc];
-    }
+    const int k = min(a + t, b - 1);
+    v[t] = lv[k];
+    p[t] = g[(size_t)lc[k] * ns + sc];
   }
-  T s = 0;
 #pragma unroll
   for (int t = 0; t < kMsDot; ++t)
     if (a + t < b) s += v[t] * p[t];
@@ -776,7 +808,7 @@ __device__ inline T row_dot_ms(int a, int b, const int* lc, const T* lv, const T
 
 template <typename T>
 __device__ inline T row_dot_ms_global(int a, int b, const int* __restrict__ col, const T* __restrict__ val,
-                                      const T* __restrict__ g, int ns, int sc) {
+                                      const UCLP_GLOBAL T* g, int ns, int sc) {
   T s = 0;
   for (int k = a; k < b; ++k) s += val[k] * g[(size_t)col[k] * ns + sc];
   return s;
@@ -826,44 +858,45 @@ __global__ __launch_bounds__(kThreads) void k_primal_ms(const SlotDev* __restric
     wp = (T)((kp + 1.0) / (kp + 2.0));
     wap = (T)(1.0 / (kp + 2.0));
   }
-  const T* __restrict__ y = V.y;
+  const UCLP_GLOBAL T* y = gld(V.y);
   // kMsUnroll rows per thread at a time: their vector loads and gathers are
   // all issued before the first epilogue
   for (int jb = r0 + threadIdx.x / kLanes; jb < r1; jb += kMsUnroll * kRowsPerPass) {
     T acc[kMsUnroll], x[kMsUnroll], c[kMsUnroll], l[kMsUnroll], u[kMsUnroll], xa[kMsUnroll];
 #pragma unroll
     for (int q = 0; q < kMsUnroll; ++q) {
-      const int j = jb + q * kRowsPerPass;
-      acc[q] = x[q] = c[q] = l[q] = u[q] = xa[q] = 0;
-      if (j < r1) {
-        const size_t e = (size_t)j * ns + sc;
-        c[q] = (fl & kColC0) ? (T)0 : V.c[e];
-        u[q] = (fl & kColUInf) ? (T)INFINITY : V.u[e];
-        l[q] = (fl & kColL0) ? (T)0 : (fl & kColLInf) ? -(T)INFINITY : (fl & kColLNegU) ? -u[q] : V.l[e];
-        if (rebuild) {
-          xa[q] = V.x0[e];
-          x[q] = wp * V.xbar[e] + wap * xa[q];
-        } else {
-          x[q] = V.x[e];
-          if (!CHECK) xa[q] = V.x0[e];
-        }
-        acc[q] = staged ? row_dot_ms<T>(ptr[j] - k0, ptr[j + 1] - k0, lc, lv, y, ns, sc)
-                        : row_dot_ms_global<T>(ptr[j], ptr[j + 1], S.t_col, V.tv, y, ns, sc);
+      // straight-line loads: rows past the block's end load its last row
+      const int j = min(jb + q * kRowsPerPass, r1 - 1);
+      const size_t e = (size_t)j * ns + sc;
+      c[q] = (fl & kColC0) ? (T)0 : gld(V.c)[e];
+      u[q] = (fl & kColUInf) ? (T)INFINITY : gld(V.u)[e];
+      l[q] = (fl & (kColL0 | kColLInf | kColLNegU)) ? (T)0 : gld(V.l)[e];
+      xa[q] = 0;
+      if (rebuild) {
+        xa[q] = gld(V.x0)[e];
+        x[q] = gld(V.xbar)[e];
+      } else {
+        x[q] = gld(V.x)[e];
+        if (!CHECK) xa[q] = gld(V.x0)[e];
       }
+      acc[q] = staged ? row_dot_ms<T>(ptr[j] - k0, ptr[j + 1] - k0, lc, lv, y, ns, sc)
+                      : row_dot_ms_global<T>(ptr[j], ptr[j + 1], S.t_col, V.tv, y, ns, sc);
     }
 #pragma unroll
     for (int q = 0; q < kMsUnroll; ++q) {
       const int j = jb + q * kRowsPerPass;
       if (j >= r1) break;
       const size_t e = (size_t)j * ns + sc;
-      const T xh = clampv<T>(x[q] - tau * (c[q] - acc[q]), l[q], u[q]);
-      const T xb = (T)2 * xh - x[q];
-      V.xbar[e] = xb;
+      const T xq = rebuild ? wp * x[q] + wap * xa[q] : x[q];
+      const T lq = (fl & kColL0) ? (T)0 : (fl & kColLInf) ? -(T)INFINITY : (fl & kColLNegU) ? -u[q] : l[q];
+      const T xh = clampv<T>(xq - tau * (c[q] - acc[q]), lq, u[q]);
+      const T xb = (T)2 * xh - xq;
+      gst(V.xbar)[e] = xb;
       if (CHECK) {
-        V.xhat[e] = xh;
-        if (rebuild) V.x[e] = x[q];
+        gst(V.xhat)[e] = xh;
+        if (rebuild) gst(V.x)[e] = xq;
       } else if (!full) {
-        V.x[e] = w * ((T)(1.0 + S.gamma) * xh - (T)S.gamma * x[q]) + wa * xa[q];
+        gst(V.x)[e] = w * ((T)(1.0 + S.gamma) * xh - (T)S.gamma * xq) + wa * xa[q];
       }
     }
   }
@@ -896,21 +929,18 @@ __global__ __launch_bounds__(kThreads) void k_dual_ms(const SlotDev* __restrict_
   const T w = (T)((kk + 1.0) / (kk + 2.0));
   const T wa = (T)(1.0 / (kk + 2.0));
   const T g1 = (T)(1.0 + S.gamma), g = (T)S.gamma;
-  const T* __restrict__ xbv = V.xbar;
+  const UCLP_GLOBAL T* xbv = gld(V.xbar);
   for (int ib = r0 + threadIdx.x / kLanes; ib < r1; ib += kMsUnroll * kRowsPerPass) {
     T acc[kMsUnroll], y[kMsUnroll], bi[kMsUnroll], ya[kMsUnroll];
 #pragma unroll
     for (int q = 0; q < kMsUnroll; ++q) {
-      const int i = ib + q * kRowsPerPass;
-      acc[q] = y[q] = bi[q] = ya[q] = 0;
-      if (i < r1) {
-        const size_t e = (size_t)i * ns + sc;
-        bi[q] = b0 ? (T)0 : V.b[e];
-        y[q] = V.y[e];
-        if (!CHECK) ya[q] = V.y0[e];
-        acc[q] = staged ? row_dot_ms<T>(ptr[i] - k0, ptr[i + 1] - k0, lc, lv, xbv, ns, sc)
-                        : row_dot_ms_global<T>(ptr[i], ptr[i + 1], S.a_col, V.av, xbv, ns, sc);
-      }
+      const int i = min(ib + q * kRowsPerPass, r1 - 1);
+      const size_t e = (size_t)i * ns + sc;
+      bi[q] = b0 ? (T)0 : gld(V.b)[e];
+      y[q] = gld(V.y)[e];
+      ya[q] = CHECK ? (T)0 : gld(V.y0)[e];
+      acc[q] = staged ? row_dot_ms<T>(ptr[i] - k0, ptr[i + 1] - k0, lc, lv, xbv, ns, sc)
+                      : row_dot_ms_global<T>(ptr[i], ptr[i + 1], S.a_col, V.av, xbv, ns, sc);
     }
 #pragma unroll
     for (int q = 0; q < kMsUnroll; ++q) {
@@ -919,8 +949,8 @@ __global__ __launch_bounds__(kThreads) void k_dual_ms(const SlotDev* __restrict_
       const size_t e = (size_t)i * ns + sc;
       T yh = y[q] + sigma * (bi[q] - acc[q]);
       if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
-      if (CHECK) V.yhat[e] = yh;
-      else V.y[e] = w * (g1 * yh - g * y[q]) + wa * ya[q];
+      if (CHECK) gst(V.yhat)[e] = yh;
+      else gst(V.y)[e] = w * (g1 * yh - g * y[q]) + wa * ya[q];
     }
   }
 }

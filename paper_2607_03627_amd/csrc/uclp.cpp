@@ -193,6 +193,8 @@ struct HostProblem {
   std::vector<int> a_ptr, a_col, t_ptr, a_blk, t_blk;
   std::vector<int> a_seg, t_seg;  // entry offset of each row block (nblk + 1)
   std::vector<int> a_flag, t_flag;  // TileFlag bits of each row block
+  std::vector<int> fx_row, fx_col;  // entries of A in fixed columns
+  std::vector<double> fx_val;
   std::vector<int> a_base, t_base;  // Tile::base of each row block
   std::vector<uint16_t> a_end, t_end;  // row ends relative to the row block's first entry
   std::vector<double> a_val, c, b, l, u;
@@ -270,14 +272,15 @@ static void block_row_ends(const std::vector<int>& ptr, const std::vector<int>& 
 
 static bool is_pos_zero(double v) { return v == 0.0 && !std::signbit(v); }
 
-// Per-block TileFlag bits of the internal data (exact comparisons).
-static void block_flags(HostProblem& P) {
-  const int nt = (int)P.t_blk.size() - 1, na = (int)P.a_blk.size() - 1;
+// Per-block TileFlag bits of P's internal data over S's row blocks (exact
+// comparisons).
+static void block_flags(HostProblem& P, const HostProblem& S) {
+  const int nt = (int)S.t_blk.size() - 1, na = (int)S.a_blk.size() - 1;
   P.t_flag.assign(std::max(nt, 0), 0);
   P.a_flag.assign(std::max(na, 0), 0);
   for (int bk = 0; bk < nt; ++bk) {
     int f = kColC0 | kColL0 | kColLInf | kColLNegU | kColUInf;
-    for (int j = P.t_blk[bk]; j < P.t_blk[bk + 1]; ++j) {
+    for (int j = S.t_blk[bk]; j < S.t_blk[bk + 1]; ++j) {
       if (!is_pos_zero(P.c[j])) f &= ~kColC0;
       if (!is_pos_zero(P.l[j])) f &= ~kColL0;
       if (!(std::isinf(P.l[j]) && P.l[j] < 0)) f &= ~kColLInf;
@@ -288,7 +291,7 @@ static void block_flags(HostProblem& P) {
   }
   for (int bk = 0; bk < na; ++bk) {
     int f = kRowB0;
-    for (int i = P.a_blk[bk]; i < P.a_blk[bk + 1]; ++i)
+    for (int i = S.a_blk[bk]; i < S.a_blk[bk + 1]; ++i)
       if (!is_pos_zero(P.b[i])) f = 0;
     P.a_flag[bk] = f;
   }
@@ -297,21 +300,20 @@ static void block_flags(HostProblem& P) {
 // Data-dependent part of the presolve (right-hand side shift, objective
 // offset, norms, feasibility of removed rows).  The structure (which columns
 // are fixed and which rows are empty) is fixed at create time.
-static void presolve_data(HostProblem& P) {
+// P holds the data (o_c, o_b, o_lb, o_ub in, c, b, l, u and the block flags
+// out); S holds the structure (maps, fixed entries, blocks).  S is P itself
+// except for the scenarios of a batch, which share their base's structure.
+static void presolve_data(HostProblem& P, const HostProblem& S) {
   const int32_t m = P.m;
   std::vector<double> shift(m, 0.0);
   P.obj_offset = 0.0;
-  for (int32_t r = 0; r < m; ++r)
-    for (int32_t k = P.o_ptr[r]; k < P.o_ptr[r + 1]; ++k) {
-      const int j = P.o_col[k];
-      if (P.int_col[j] < 0) shift[r] += P.o_val[k] * P.o_lb[j];
-    }
+  for (size_t e = 0; e < S.fx_row.size(); ++e) shift[S.fx_row[e]] += S.fx_val[e] * P.o_lb[S.fx_col[e]];
   for (int32_t j = 0; j < P.n; ++j)
-    if (P.int_col[j] < 0) P.obj_offset += P.o_c[j] * P.o_lb[j];
+    if (S.int_col[j] < 0) P.obj_offset += P.o_c[j] * P.o_lb[j];
   P.infeasible = false;
   std::vector<char> kept(m, 0);
   for (int i = 0; i < P.mi; ++i) {
-    const int enc = P.row_map[i];
+    const int enc = S.row_map[i];
     const int r = enc >= 0 ? enc : -enc - 1;
     kept[r] = 1;
     const double sgn = enc >= 0 ? 1.0 : -1.0;
@@ -321,12 +323,12 @@ static void presolve_data(HostProblem& P) {
     if (kept[r]) continue;
     const double rhs = P.o_b[r] - shift[r];  // removed row reads 0 (=,>=,<=) rhs
     const double tol = 1e-9 * (1.0 + std::fabs(P.o_b[r]));
-    if ((P.o_sense[r] == 'E' && std::fabs(rhs) > tol) || (P.o_sense[r] == 'G' && rhs > tol) ||
-        (P.o_sense[r] == 'L' && rhs < -tol))
+    if ((S.o_sense[r] == 'E' && std::fabs(rhs) > tol) || (S.o_sense[r] == 'G' && rhs > tol) ||
+        (S.o_sense[r] == 'L' && rhs < -tol))
       P.infeasible = true;
   }
   for (int j = 0; j < P.ni; ++j) {
-    const int o = P.col_map[j];
+    const int o = S.col_map[j];
     P.c[j] = P.o_c[o];
     P.l[j] = P.o_lb[o];
     P.u[j] = P.o_ub[o];
@@ -336,7 +338,7 @@ static void presolve_data(HostProblem& P) {
   for (int32_t j = 0; j < P.n; ++j) nc += P.o_c[j] * P.o_c[j];
   P.norm_b = std::sqrt(nb);
   P.norm_c = std::sqrt(nc);
-  block_flags(P);
+  block_flags(P, S);
 }
 
 static void presolve_structure(HostProblem& P) {
@@ -349,6 +351,17 @@ static void presolve_structure(HostProblem& P) {
       P.col_map.push_back(j);
     }
   P.ni = (int)P.col_map.size();
+  // entries in fixed columns, for the right-hand-side shift of presolve_data
+  P.fx_row.clear();
+  P.fx_col.clear();
+  P.fx_val.clear();
+  for (int32_t r = 0; r < m; ++r)
+    for (int32_t k = P.o_ptr[r]; k < P.o_ptr[r + 1]; ++k)
+      if (P.int_col[P.o_col[k]] < 0) {
+        P.fx_row.push_back(r);
+        P.fx_col.push_back(P.o_col[k]);
+        P.fx_val.push_back(P.o_val[k]);
+      }
   // rows with at least one entry in a kept column; E rows first
   std::vector<int> cnt(m, 0);
   for (int32_t r = 0; r < m; ++r)
@@ -941,7 +954,9 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
       if (st.best_check == 0 || in.rel_kkt < 0.9 * st.best_kkt) {
         st.best_kkt = in.rel_kkt;
         st.best_check = st.checks;
-      } else if (o.fp32_stall_checks > 0 && st.checks - st.best_check >= o.fp32_stall_checks) {
+      } else if (o.fp32_stall_checks > 0 && st.checks - st.best_check >= o.fp32_stall_checks &&
+                 st.best_kkt <= 10.0 * target) {
+        // a stall within a decade of the target is taken for the FP32 floor
         out.promote = true;
       }
     }
@@ -1411,7 +1426,7 @@ extern "C" int uc_lp_create(uc_engine* eng, int32_t m, int32_t n, int64_t nnz, c
   P.o_lb.assign(lb, lb + n);
   P.o_ub.assign(ub, ub + n);
   presolve_structure(P);
-  presolve_data(P);
+  presolve_data(P, P);
   if (P.ni == 0) return fail(UC_LP_ENOTSUP, "every column is fixed; nothing to solve");
   lp->need_bytes = arena_bytes(P, 1);
   std::memset(&lp->info, 0, sizeof lp->info);
@@ -1461,7 +1476,7 @@ extern "C" int uc_lp_update_data(uc_lp* lp, const double* c, const double* b, co
   P.o_b.swap(nb);
   P.o_lb.swap(nl);
   P.o_ub.swap(nu);
-  presolve_data(P);
+  presolve_data(P, P);
   ++lp->data_gen;
   lp->setup_done = false;
   return UC_LP_OK;
@@ -1994,29 +2009,20 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
     for (int32_t j = 0; j < n; ++j)
       if ((ls[j] == us[j]) != (P.int_col[j] < 0))
         return fail(UC_LP_ENOTSUP, "scenario %d: column %d differs from the base in being fixed", s, j);
-    HostProblem& Q = SP[s];
+    HostProblem& Q = SP[s];  // data only; the structure is the base's
     Q.m = m;
     Q.n = n;
-    Q.o_ptr = P.o_ptr;
-    Q.o_col = P.o_col;
-    Q.o_val = P.o_val;
-    Q.o_sense = P.o_sense;
     Q.o_c.assign(cs, cs + n);
     Q.o_b.assign(bs, bs + m);
     Q.o_lb.assign(ls, ls + n);
     Q.o_ub.assign(us, us + n);
-    Q.int_col = P.int_col;
-    Q.col_map = P.col_map;
-    Q.row_map = P.row_map;
     Q.ni = ni;
     Q.mi = mi;
     Q.b.assign(mi, 0.0);
     Q.c.assign(ni, 0.0);
     Q.l.assign(ni, 0.0);
     Q.u.assign(ni, 0.0);
-    Q.t_blk = P.t_blk;  // for the block flags
-    Q.a_blk = P.a_blk;
-    presolve_data(Q);
+    presolve_data(Q, P);
     if (Q.infeasible) return fail(UC_LP_EINVAL, "scenario %d is infeasible by its empty rows", s);
   }
   // a block flag holds for the batch when it holds for every scenario
@@ -2055,17 +2061,13 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   } while (0)
   // scenario-major internal data -> interleaved scaled data on the device
   {
-    std::vector<double> hc((size_t)ni * S), hl((size_t)ni * S), hu((size_t)ni * S), hb((size_t)mi * S);
-    for (int s = 0; s < S; ++s) {
-      std::copy(SP[s].c.begin(), SP[s].c.end(), hc.begin() + (size_t)s * ni);
-      std::copy(SP[s].l.begin(), SP[s].l.end(), hl.begin() + (size_t)s * ni);
-      std::copy(SP[s].u.begin(), SP[s].u.end(), hu.begin() + (size_t)s * ni);
-      std::copy(SP[s].b.begin(), SP[s].b.end(), hb.begin() + (size_t)s * mi);
+    for (int s = 0; s < S; ++s) {  // scenario-major, straight from each scenario's arrays
+      SCEN_HIP(hipMemcpyAsync(A.c_in + (size_t)s * ni, SP[s].c.data(), (size_t)ni * 8, hipMemcpyHostToDevice, st));
+      SCEN_HIP(hipMemcpyAsync(A.l_in + (size_t)s * ni, SP[s].l.data(), (size_t)ni * 8, hipMemcpyHostToDevice, st));
+      SCEN_HIP(hipMemcpyAsync(A.u_in + (size_t)s * ni, SP[s].u.data(), (size_t)ni * 8, hipMemcpyHostToDevice, st));
+      if (mi)
+        SCEN_HIP(hipMemcpyAsync(A.b_in + (size_t)s * mi, SP[s].b.data(), (size_t)mi * 8, hipMemcpyHostToDevice, st));
     }
-    SCEN_HIP(hipMemcpyAsync(A.c_in, hc.data(), hc.size() * 8, hipMemcpyHostToDevice, st));
-    SCEN_HIP(hipMemcpyAsync(A.l_in, hl.data(), hl.size() * 8, hipMemcpyHostToDevice, st));
-    SCEN_HIP(hipMemcpyAsync(A.u_in, hu.data(), hu.size() * 8, hipMemcpyHostToDevice, st));
-    if (mi) SCEN_HIP(hipMemcpyAsync(A.b_in, hb.data(), hb.size() * 8, hipMemcpyHostToDevice, st));
     launch_scale_vectors(A.c_in, A.l_in, A.u_in, A.b_in, base->D.dc, base->D.dr, ni, mi, S, (double*)A.d.c,
                          (double*)A.d.l, (double*)A.d.u, (double*)A.d.b, (float*)A.f.c, (float*)A.f.l,
                          (float*)A.f.u, (float*)A.f.b, st);
