@@ -97,7 +97,15 @@ __device__ inline void block_rows(const int* __restrict__ ptr, int r0, int r1, A
   const int k1 = ptr[r1];
   const int nz = k1 - k0;
   if (nz <= kNnzTile) {
-    for (int k = threadIdx.x; k < nz; k += kThreads) lds[k] = prod(k0 + k);
+    if (nz > 0) {
+      // all products' loads are issued before the first LDS store
+      ACC v[kNnzTile / kThreads];
+#pragma unroll
+      for (int u = 0; u < kNnzTile / kThreads; ++u) v[u] = prod(k0 + min((int)threadIdx.x + u * kThreads, nz - 1));
+#pragma unroll
+      for (int u = 0; u < kNnzTile / kThreads; ++u)
+        if ((int)threadIdx.x + u * kThreads < nz) lds[threadIdx.x + u * kThreads] = v[u];
+    }
     __syncthreads();
     for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
       const int a = ptr[r] - k0;
