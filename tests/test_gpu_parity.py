@@ -56,15 +56,35 @@ def internal_oracle(lp):
     return ip, A, Dr, Dc, Ah
 
 
+_FULL = {}
+
+
+def full_size_case():
+    """The 6,049-bus-shaped LP the benchmark times, with the oracle's internal
+    problem and scaling, built once per test session."""
+    if not _FULL:
+        lp = make_instance("large", 0)
+        _FULL["lp"] = lp
+        _FULL["oracle"] = internal_oracle(lp)
+    return _FULL["lp"], _FULL["oracle"]
+
+
+def instance_and_oracle(shape, seed):
+    if shape == "large":
+        assert seed == 0
+        return full_size_case()
+    lp = make_instance(shape, seed)
+    return lp, internal_oracle(lp)
+
+
 # ---------------------------------------------------------------------------
 # a1 presolve + transpose, a2 scaling, a3 operator norm
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape,seed", [("tiny", 0), ("medium", 1)])
+@pytest.mark.parametrize("shape,seed", [("tiny", 0), ("medium", 1), ("large", 0)])
 def test_presolve_and_transpose_bit_exact(shape, seed):
-    lp = make_instance(shape, seed)
     say("case", shape, seed)
-    ip = ps.internal_problem(lp)
+    lp, (ip, _, _, _, _) = instance_and_oracle(shape, seed)
     with Handle(lp) as H:
         d = uclp.uc_lp_internal_dims(H.h)
         assert (d["m"], d["n"], d["nnz"], d["m_eq"]) == (ip.m, ip.n, len(ip.col_idx), ip.m_eq)
@@ -107,12 +127,13 @@ def step_inputs(ip, Dc, Dr, seed):
     return x, y, x0, y0
 
 
-@pytest.mark.parametrize("shape,seed,gamma", [("tiny", 1, 1.0), ("medium", 2, 1.0), ("tiny", 3, 0.5)])
+@pytest.mark.parametrize("shape,seed,gamma", [("tiny", 1, 1.0), ("medium", 2, 1.0), ("tiny", 3, 0.5), ("large", 0, 1.0)])
 @pytest.mark.parametrize("prec", [uclp.UC_LP_FP64, uclp.UC_LP_FP32_MIXED])
 def test_pdhg_step_elementwise(shape, seed, gamma, prec):
-    lp = make_instance(shape, seed)
+    # ("large", 0) is the benchmark's full-size LP: every one of its 3.2M + 3.0M
+    # step outputs is compared with the oracle's
     say("case", shape, seed, gamma, prec)
-    ip, A, Dr, Dc, Ah = internal_oracle(lp)
+    lp, (ip, A, Dr, Dc, Ah) = instance_and_oracle(shape, seed)
     c, b, l, u = ip.c * Dc, ip.b * Dr, ip.l / Dc, ip.u / Dc
     x, y, x0, y0 = step_inputs(ip, Dc, Dr, seed)
     tau, sigma, k = 0.37, 1.9, 5
@@ -155,6 +176,33 @@ def test_pdhg_step_elementwise(shape, seed, gamma, prec):
 # ---------------------------------------------------------------------------
 # a7: the FP64 KKT check kernels
 # ---------------------------------------------------------------------------
+
+def test_full_size_scaling():
+    # D_r, D_c of the benchmark's LP against the oracle's; the power-iteration
+    # estimate stays below the Pock-Chambolle bound of the scaled matrix
+    lp, (ip, A, Dr, Dc, Ah) = full_size_case()
+    say("case large 0 scaling")
+    with Handle(lp) as H:
+        dr, dc, nrm = uclp.uc_lp_get_scaling(H.h, ip.m, ip.n)
+    assert np.max(np.abs(dr / Dr - 1)) <= 1e-12
+    assert np.max(np.abs(dc / Dc - 1)) <= 1e-12
+    assert 0.5 < nrm <= 1 + 1e-12
+
+
+def test_full_size_solve_in_the_benchmark_configuration():
+    # the benchmark's solve (FP32 iterates, FP64 checks, 1e-4, event timing
+    # on); the oracle recomputes the KKT error of the returned point
+    lp, _ = full_size_case()
+    say("case large 0 solve")
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-4, timing=1)
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    k = kkt(lp, x, y)
+    say("large rel_kkt", k.rel_kkt, info["rel_kkt"], k.pobj)
+    assert k.rel_kkt <= 1e-4 * 1.001
+    assert abs(k.rel_kkt - info["rel_kkt"]) <= 1e-6
+    assert np.all(x >= lp.lb) and np.all(x <= lp.ub)
+    assert info["primal_kernel_us"] > 0 and info["dual_kernel_us"] > 0
+
 
 def test_kkt_kernels_match_oracle():
     lp = make_instance("tiny", 0)
