@@ -126,6 +126,9 @@ typedef struct {
                             take restarts on residual noise whose primal-weight
                             updates then stall it; both guards bound that.)  */
   int32_t reserved;      /* must be 0                                         */
+  double pw_integral;    /* integral gain of the primal-weight update: log w
+                            also moves by -this * (sum of past errors
+                            log w - log(dy/dx)); default 0                    */
 } uc_lp_opts;
 
 typedef struct {

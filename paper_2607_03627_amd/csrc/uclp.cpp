@@ -98,6 +98,7 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->pw_smoothing = 0.8;
   o->halpern_gamma = 1.0;
   o->pw_max_change = 4.0;
+  o->pw_integral = 0.0;
   o->fp32_stall_checks = 24;
   o->reserved = 0;
 }
@@ -116,7 +117,8 @@ static int check_opts(const uc_lp_opts& o) {
   if (!(o.restart_sufficient > 0 && o.restart_sufficient <= o.restart_necessary && o.restart_necessary < 1) ||
       !(o.restart_artificial > 0 && o.restart_artificial <= 1) || !(o.pw_smoothing >= 0 && o.pw_smoothing <= 1) ||
       (o.restart_to_current != 0 && o.restart_to_current != 1) || !(o.halpern_gamma >= 0 && o.halpern_gamma <= 1) ||
-      !(o.pw_max_change == 0 || o.pw_max_change >= 1) || o.fp32_stall_checks < 0 || o.reserved != 0)
+      !(o.pw_max_change == 0 || o.pw_max_change >= 1) || o.fp32_stall_checks < 0 || o.reserved != 0 ||
+      !(o.pw_integral >= 0 && o.pw_integral <= 1))
     return fail(UC_LP_EINVAL, "restart / primal-weight parameters out of range");
   return UC_LP_OK;
 }
@@ -562,6 +564,7 @@ struct PdhgState {
   bool r_start_set = false, r_prev_set = false;
   double r_start = 0, r_prev = 0;
   double t_start = 0;
+  double pw_int = 0;         // running sum of primal-weight errors
   double best_kkt = 0;       // FP32 phase: best relative KKT error so far
   long long best_check = 0;  // check index at which it was reached
   long long checks = 0;
@@ -989,7 +992,10 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
       const double dY = std::sqrt(std::max(q[RQ_DY0], 0.0));
       const double th = o.pw_smoothing;
       if (dX > 1e-10 && dY > 1e-10) {
-        double w = std::exp(th * std::log(dY / dX) + (1.0 - th) * std::log(st.omega));
+        // log w <- log w - th e - ki sum(e), e = log w - log(dY / dX)
+        const double e = std::log(st.omega) - std::log(dY / dX);
+        st.pw_int += e;
+        double w = std::exp(std::log(st.omega) - th * e - o.pw_integral * st.pw_int);
         if (o.pw_max_change >= 1) w = std::min(std::max(w, st.omega / o.pw_max_change), st.omega * o.pw_max_change);
         st.omega = w;
       }

@@ -69,11 +69,29 @@ def full_size_case():
     return _FULL["lp"], _FULL["oracle"]
 
 
+def ragged_instance(seed):
+    """The 30-bus LP with one dense row (sum of all columns <= 1e6) and one
+    dense column (0.01 in every row, cost 50, bounds [0, 1]): a row of A and a
+    row of A^T longer than one LDS tile, next to the short UC rows."""
+    base = make_instance("tiny", seed)
+    m, n = base.m, base.n
+    rows = [base.col_idx[base.row_ptr[i]:base.row_ptr[i + 1]] for i in range(m)]
+    vals = [base.val[base.row_ptr[i]:base.row_ptr[i + 1]] for i in range(m)]
+    cols = [np.append(r, n) for r in rows] + [np.arange(n + 1)]
+    vs = [np.append(v, 0.01) for v in vals] + [np.append(np.ones(n), 0.01)]
+    rp = np.zeros(m + 2, np.int32)
+    rp[1:] = np.cumsum([len(r) for r in cols])
+    return LP(m=m + 1, n=n + 1, row_ptr=rp, col_idx=np.concatenate(cols).astype(np.int32),
+              val=np.concatenate(vs), c=np.append(base.c, 50.0), b=np.append(base.b, 1e6),
+              sense=np.append(base.sense, np.uint8(ord("L"))), lb=np.append(base.lb, 0.0),
+              ub=np.append(base.ub, 1.0))
+
+
 def instance_and_oracle(shape, seed):
     if shape == "large":
         assert seed == 0
         return full_size_case()
-    lp = make_instance(shape, seed)
+    lp = ragged_instance(seed) if shape == "ragged" else make_instance(shape, seed)
     return lp, internal_oracle(lp)
 
 
@@ -127,7 +145,8 @@ def step_inputs(ip, Dc, Dr, seed):
     return x, y, x0, y0
 
 
-@pytest.mark.parametrize("shape,seed,gamma", [("tiny", 1, 1.0), ("medium", 2, 1.0), ("tiny", 3, 0.5), ("large", 0, 1.0)])
+@pytest.mark.parametrize("shape,seed,gamma", [("tiny", 1, 1.0), ("medium", 2, 1.0), ("tiny", 3, 0.5), ("ragged", 0, 1.0),
+                                              ("large", 0, 1.0)])
 @pytest.mark.parametrize("prec", [uclp.UC_LP_FP64, uclp.UC_LP_FP32_MIXED])
 def test_pdhg_step_elementwise(shape, seed, gamma, prec):
     # ("large", 0) is the benchmark's full-size LP: every one of its 3.2M + 3.0M
@@ -341,6 +360,19 @@ def test_weight_bound_of_one_fixes_the_primal_weight():
     assert a["restarts"] > 0 and c["restarts"] > 0
     assert (a["iters"], a["pobj"], a["omega"]) == (b["iters"], b["pobj"], b["omega"])
     assert c["omega"] != a["omega"]
+
+
+def test_long_rows_solve_matches_simplex_oracle():
+    # long rows of A and of A^T take the block-wide path in every kernel
+    lp = ragged_instance(1)
+    say("case ragged fp64")
+    assert np.diff(lp.row_ptr).max() > 2048
+    res = simplex_solve(lp)
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP64, eps_rel=1e-8)
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    k = kkt(lp, x, y)
+    assert k.rel_kkt <= 1e-8 * 1.001
+    assert abs(k.pobj - res.obj) <= 1e-6 * abs(res.obj)
 
 
 @pytest.mark.parametrize("seed", range(3))
