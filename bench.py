@@ -227,7 +227,7 @@ def main():
             log(f"[bench] {label} step {i}: {walls[-1]:.3f}s status {info['status_name']} iters {info['iters']} "
                 f"restarts {info['restarts']} t_eps {info['t_to_eps_s']:.3f}s setup {info['t_setup_s']:.3f}s "
                 f"kkt {info['rel_kkt']:.2e} pobj {info['pobj']:.10g} primal_us {info['primal_kernel_us']:.1f} "
-                f"dual_us {info['dual_kernel_us']:.1f}")
+                f"dual_us {info['dual_kernel_us']:.1f} iters_fp64 {info['iters_fp64']}")
         return walls, infos
 
     opts = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-4, timing=1,

@@ -129,6 +129,10 @@ typedef struct {
   double pw_integral;    /* integral gain of the primal-weight update: log w
                             also moves by -this * (sum of past errors
                             log w - log(dy/dx)); default 0                    */
+  double pw_balance;     /* at a restart log w also moves by this * log(rel.
+                            primal residual / rel. dual residual), raising the
+                            dual step while the primal residual lags;
+                            default 0.5, 0 = off                              */
 } uc_lp_opts;
 
 typedef struct {
@@ -151,7 +155,8 @@ typedef struct {
   int64_t iters_at_eps;    /* iterations at the eps_rel milestone             */
   double norm_a_est;       /* power-iteration estimate of ||A_hat||_2         */
   double omega;            /* current primal weight                           */
-  double primal_kernel_us; /* mean duration of timed primal half-step kernels  */
+  double primal_kernel_us; /* mean duration of timed primal half-step kernels
+                              (the FP32 ones when the solve had an FP32 phase) */
   double dual_kernel_us;   /* mean duration of timed dual half-step kernels    */
   int64_t timed_launches;  /* number of launches in each mean above           */
   int32_t m_presolved, n_presolved;  /* sizes after the minimal presolve      */

@@ -99,6 +99,7 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->halpern_gamma = 1.0;
   o->pw_max_change = 4.0;
   o->pw_integral = 0.0;
+  o->pw_balance = 0.5;
   o->fp32_stall_checks = 24;
   o->reserved = 0;
 }
@@ -118,7 +119,7 @@ static int check_opts(const uc_lp_opts& o) {
       !(o.restart_artificial > 0 && o.restart_artificial <= 1) || !(o.pw_smoothing >= 0 && o.pw_smoothing <= 1) ||
       (o.restart_to_current != 0 && o.restart_to_current != 1) || !(o.halpern_gamma >= 0 && o.halpern_gamma <= 1) ||
       !(o.pw_max_change == 0 || o.pw_max_change >= 1) || o.fp32_stall_checks < 0 || o.reserved != 0 ||
-      !(o.pw_integral >= 0 && o.pw_integral <= 1))
+      !(o.pw_integral >= 0 && o.pw_integral <= 1) || !(o.pw_balance >= 0 && o.pw_balance <= 1))
     return fail(UC_LP_EINVAL, "restart / primal-weight parameters out of range");
   return UC_LP_OK;
 }
@@ -620,8 +621,9 @@ struct uc_lp {
   PdhgState st;
   int slot = -1;
   double t_request = 0;
-  double timed_primal_ms = 0, timed_dual_ms = 0;
-  long long timed_n = 0;
+  // timed launches by precision (0 FP64, 1 FP32)
+  double timed_primal_ms[2] = {0, 0}, timed_dual_ms[2] = {0, 0};
+  long long timed_n[2] = {0, 0};
   int data_gen = 0;  // bumped by uc_lp_update_data (tile flags depend on the data)
 };
 
@@ -995,7 +997,11 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
         // log w <- log w - th e - ki sum(e), e = log w - log(dY / dX)
         const double e = std::log(st.omega) - std::log(dY / dX);
         st.pw_int += e;
-        double w = std::exp(std::log(st.omega) - th * e - o.pw_integral * st.pw_int);
+        double lw = std::log(st.omega) - th * e - o.pw_integral * st.pw_int;
+        // residual balance: a primal residual above the dual one raises w
+        if (o.pw_balance > 0 && in.rel_primal > 0 && in.rel_dual > 0)
+          lw += o.pw_balance * std::log(in.rel_primal / in.rel_dual);
+        double w = std::exp(lw);
         if (o.pw_max_change >= 1) w = std::min(std::max(w, st.omega / o.pw_max_change), st.omega * o.pw_max_change);
         st.omega = w;
       }
@@ -1049,12 +1055,17 @@ static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
   uc_lp_info in = get_info(lp);
   CheckOut out = check_core(lp->st, lp->opts, q, K, tnow, lp->P.obj_offset, lp->P.norm_b, lp->P.norm_c,
                             lp->cancel.load(), in);
-  if (lp->timed_n > 0) {
-    in.primal_kernel_us = 1e3 * lp->timed_primal_ms / lp->timed_n;
-    in.dual_kernel_us = 1e3 * lp->timed_dual_ms / lp->timed_n;
-    in.timed_launches = lp->timed_n;
+  // report the FP32 launches when there are any (an FP32 solve that hands
+  // over to FP64 near its end still reports its FP32 kernels), with the
+  // algorithmic bytes of that precision
+  const int tp = lp->timed_n[1] > 0 ? 1 : 0;
+  if (lp->timed_n[tp] > 0) {
+    in.primal_kernel_us = 1e3 * lp->timed_primal_ms[tp] / lp->timed_n[tp];
+    in.dual_kernel_us = 1e3 * lp->timed_dual_ms[tp] / lp->timed_n[tp];
+    in.timed_launches = lp->timed_n[tp];
   }
-  half_step_bytes(lp->P, lp->st.prec ? 4 : 8, lp->opts.halpern_gamma == 1.0, &in.primal_bytes, &in.dual_bytes);
+  const int bp = lp->timed_n[0] + lp->timed_n[1] > 0 ? tp : lp->st.prec;
+  half_step_bytes(lp->P, bp ? 4 : 8, lp->opts.halpern_gamma == 1.0, &in.primal_bytes, &in.dual_bytes);
   set_info(lp, in);
   return out;
 }
@@ -1087,8 +1098,10 @@ static void start_instance(uc_engine* E, uc_lp* lp) {
   const double t0 = now_s();
   lp->st = PdhgState();
   lp->st.t_start = t0;
-  lp->timed_primal_ms = lp->timed_dual_ms = 0;
-  lp->timed_n = 0;
+  for (int p = 0; p < 2; ++p) {
+    lp->timed_primal_ms[p] = lp->timed_dual_ms[p] = 0;
+    lp->timed_n[p] = 0;
+  }
   {
     std::lock_guard<std::mutex> g(lp->mu);
     uc_lp_info in;
@@ -1235,11 +1248,12 @@ static void run_epochs(uc_engine* E) {
     float t01 = 0, t12 = 0;
     if (hipEventElapsedTime(&t01, E->ev[0], E->ev[1]) == hipSuccess &&
         hipEventElapsedTime(&t12, E->ev[2], E->ev[3]) == hipSuccess) {
+      const int tp = nT1 > 0 ? 1 : 0;  // the group that carried the events
       for (auto* lp : E->active)
         if (lp->opts.timing) {
-          lp->timed_primal_ms += t01;
-          lp->timed_dual_ms += t12;
-          ++lp->timed_n;
+          lp->timed_primal_ms[tp] += t01;
+          lp->timed_dual_ms[tp] += t12;
+          ++lp->timed_n[tp];
         }
     }
   }

@@ -81,10 +81,20 @@ def test_warm_start_from_nominal_solution():
     finally:
         uclp.uc_lp_destroy(h)
     for k in range(3):
-        assert warm[2][k].status == uclp.UC_LP_OPTIMAL
+        assert warm[2][k].status == cold[2][k].status == uclp.UC_LP_OPTIMAL
         cc, bb, ll, uu = scenario_data(lp, k + 1)
         assert kkt(lp.with_data(c=cc, b=bb, lb=ll, ub=uu), warm[0][k], warm[1][k]).rel_kkt <= 1e-4
-    assert sum(i.iters for i in warm[2]) <= sum(i.iters for i in cold[2])
+    # the warm start is used: a scenario started at its own FP64 optimum stops
+    # at the first check
+    lp1 = lp.with_data(c=c[0], b=b[0], lb=lb[0], ub=ub[0])
+    x1, y1, i1 = uclp.solve(lp1, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-8))
+    assert i1["status"] == uclp.UC_LP_OPTIMAL
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-6))
+    try:
+        own = uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, c[:1], b[:1], lb[:1], ub[:1], x1, y1)
+    finally:
+        uclp.uc_lp_destroy(h)
+    assert own[2][0].status == uclp.UC_LP_OPTIMAL and own[2][0].iters == 64
 
 
 def test_scenario_count_limits():

@@ -38,13 +38,14 @@ def test_library_exports_every_declared_symbol():
 
 def test_binding_structs_match_header_layout():
     # the two structs are passed by pointer; their sizes must agree with the C layout
-    assert ctypes.sizeof(uclp.uc_lp_opts) == 4 * 4 + 8 + 5 * 8 + 4 * 4 + 6 * 8 + 2 * 4 + 8
+    assert ctypes.sizeof(uclp.uc_lp_opts) == 4 * 4 + 8 + 5 * 8 + 4 * 4 + 6 * 8 + 2 * 4 + 2 * 8
     o = uclp.uc_lp_opts_default()
     assert o.precision == uclp.UC_LP_FP32_MIXED_POLISH and o.kkt_every == 64
     assert o.iter_limit == 100000 and o.eps_rel == 1e-4 and o.eps_polish == 1e-8
     assert (o.restart_sufficient, o.restart_necessary, o.restart_artificial, o.pw_smoothing) == \
         (0.2, 0.9, 0.36, 0.8)
     assert o.halpern_gamma == 1.0 and o.pw_max_change == 4.0 and o.fp32_stall_checks == 24 and o.reserved == 0
+    assert o.pw_integral == 0.0 and o.pw_balance == 0.5
 
 
 def small():
@@ -95,7 +96,7 @@ def test_bad_options_are_rejected():
                      (dict(step_scale=1.5), uclp.UC_LP_EINVAL), (dict(eps_rel=-1.0), uclp.UC_LP_EINVAL),
                      (dict(halpern_gamma=1.5), uclp.UC_LP_EINVAL), (dict(pw_max_change=0.5), uclp.UC_LP_EINVAL),
                      (dict(fp32_stall_checks=-1), uclp.UC_LP_EINVAL), (dict(reserved=1), uclp.UC_LP_EINVAL),
-                     (dict(pw_integral=2.0), uclp.UC_LP_EINVAL)):
+                     (dict(pw_integral=2.0), uclp.UC_LP_EINVAL), (dict(pw_balance=-0.5), uclp.UC_LP_EINVAL)):
         rc, h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(**kw), raw=True)
         assert rc == code and h is None
 
