@@ -188,6 +188,33 @@ def scenario_leg(base_lp, n_scen=16):
     return out
 
 
+def race_leg(large_lp):
+    """Algorithm 1 on synthetic UC LPs of several sizes: this library's GPU
+    PDHG (FP32, 1e-4) against HiGHS interior point on the host cores, checked
+    every 0.5 s; the first to finish wins and the other is stopped."""
+    from paper_2607_03627_amd import uclp
+    from paper_2607_03627_amd.instances import make_instance
+    from paper_2607_03627_amd.race import race
+
+    cases = [("tiny/0", make_instance("tiny", 0)), ("medium/0", make_instance("medium", 0)),
+             ("medium/1", make_instance("medium", 1)), ("large_kc0/0", make_instance("large_kc0", 0)),
+             ("large/0", large_lp)]
+    rows = []
+    for name, lp in cases:
+        r = race(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-4), poll_s=0.5,
+                 cpu_method="highs-ipm", timeout_s=600)
+        rows.append({"case": name, "rows": lp.m, "winner": r.winner, "seconds": round(r.seconds, 3),
+                     "polls": r.polls,
+                     "legs": {x.name: {"status": x.status, "seconds": round(x.seconds, 3),
+                                       "solve_s": x.info.get("t_total_s", x.info.get("highs_seconds"))}
+                              for x in r.results}})
+        log(f"[bench] race {name}: {rows[-1]}")
+    wins = {}
+    for row in rows:
+        wins[row["winner"]] = wins.get(row["winner"], 0) + 1
+    return {"poll_s": 0.5, "cases": rows, "wins": wins}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +228,7 @@ def main():
                     help="iteration limit of each solve (short runs for hardware counters)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream leg")
     ap.add_argument("--scenarios", action="store_true", help="also run the 16-scenario batch leg")
+    ap.add_argument("--race", action="store_true", help="also run the GPU-CPU race on five LPs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -331,6 +359,11 @@ def main():
             out["scenarios"] = scenario_leg(lp)
         except Exception as e:
             out["scenarios"] = {"error": repr(e)}
+    if args.race:
+        try:
+            out["race"] = race_leg(lp)
+        except Exception as e:
+            out["race"] = {"error": repr(e)}
     if not args.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(lp.nnz)
