@@ -708,7 +708,7 @@ __global__ __launch_bounds__(kThreads) void k_finish_x(const SlotDev* __restrict
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const double k = (double)(S.k0[0] + kk);
+  const double k = (double)(S.kfin + kk);
   const T w = (T)((k + 1.0) / (k + 2.0));
   const T wa = (T)(1.0 / (k + 2.0));
   for (int j = tl.r0 + threadIdx.x; j < tl.r1; j += kThreads) {
@@ -734,7 +734,7 @@ __global__ __launch_bounds__(kThreads) void k_finish_y(const SlotDev* __restrict
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
   const Vecs<T>& V = vecs<T>(S);
-  const double k = (double)(S.k0[0] + kk);
+  const double k = (double)(S.kfin + kk);
   const T w = (T)((k + 1.0) / (k + 2.0));
   const T wa = (T)(1.0 / (k + 2.0));
   for (int i = tl.r0 + threadIdx.x; i < tl.r1; i += kThreads) {

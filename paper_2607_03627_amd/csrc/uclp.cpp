@@ -583,6 +583,10 @@ struct uc_engine {
   std::deque<uc_lp*> queue;
   std::vector<uc_lp*> active;
   bool shutdown = false;
+  // d_slots already holds the next epoch's parameters of the current layout
+  // (uploaded with the last check's restart flags)
+  bool slots_current = false;
+  bool pending_upload = false;  // that upload was not followed by a sync
   // device tables
   SlotDev* d_slots = nullptr;
   Tile* d_tiles = nullptr;
@@ -597,7 +601,7 @@ struct uc_engine {
   size_t off_t0 = 0, off_a1 = 0, off_a0 = 0;
   int nT1 = 0, nT0 = 0, nA1 = 0, nA0 = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  std::vector<SlotDev> h_slots;
+  SlotDev* h_slots = nullptr;  // pinned, max_slots; rewritten only after a sync
   std::string err;
 };
 
@@ -621,6 +625,7 @@ struct uc_lp {
   PdhgState st;
   int slot = -1;
   double t_request = 0;
+  double hs_bytes[2][2] = {{0, 0}, {0, 0}};  // [precision][primal, dual] per half-step launch
   // timed launches by precision (0 FP64, 1 FP32)
   double timed_primal_ms[2] = {0, 0}, timed_dual_ms[2] = {0, 0};
   long long timed_n[2] = {0, 0};
@@ -1065,7 +1070,8 @@ static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
     in.timed_launches = lp->timed_n[tp];
   }
   const int bp = lp->timed_n[0] + lp->timed_n[1] > 0 ? tp : lp->st.prec;
-  half_step_bytes(lp->P, bp ? 4 : 8, lp->opts.halpern_gamma == 1.0, &in.primal_bytes, &in.dual_bytes);
+  in.primal_bytes = lp->hs_bytes[bp][0];
+  in.dual_bytes = lp->hs_bytes[bp][1];
   set_info(lp, in);
   return out;
 }
@@ -1124,6 +1130,8 @@ static void start_instance(uc_engine* E, uc_lp* lp) {
   if (!lp->uploaded) rc = upload(lp);
   if (rc == UC_LP_OK) rc = setup_device(lp);
   lp->st.prec = lp->opts.precision == UC_LP_FP64 ? 0 : 1;
+  for (int p = 0; p < 2; ++p)
+    half_step_bytes(lp->P, p ? 4 : 8, lp->opts.halpern_gamma == 1.0, &lp->hs_bytes[p][0], &lp->hs_bytes[p][1]);
   if (rc == UC_LP_OK) rc = init_iterates(lp, lp->st.prec);
   if (rc != UC_LP_OK) {
     worker_fail(E, lp);
@@ -1158,21 +1166,28 @@ static void run_epochs(uc_engine* E) {
   const int A = (int)E->active.size();
   int K = 1 << 30;
   for (auto* lp : E->active) K = std::min(K, lp->opts.kkt_every);
-  E->h_slots.resize(std::max<size_t>(E->h_slots.size(), (size_t)A));
   std::vector<std::pair<const uc_lp*, int>> sig(A);
-  for (int a = 0; a < A; ++a) {
-    uc_lp* lp = E->active[a];
-    lp->slot = a;
-    SlotDev S = make_slot(lp);
-    S.scal = E->d_scal + (size_t)a * kScal;
-    S.tau[0] = lp->st.eta / lp->st.omega;
-    S.sigma[0] = lp->st.eta * lp->st.omega;
-    S.k0[0] = lp->st.k_inner;
-    S.restart[0] = 0;
-    S.active[0] = 1;
-    E->h_slots[a] = S;
-    sig[a] = {lp, lp->st.prec + 2 * lp->data_gen};
+  for (int a = 0; a < A; ++a) sig[a] = {E->active[a], E->active[a]->st.prec + 2 * E->active[a]->data_gen};
+  // an unchanged batch continues on the parameters uploaded after its last
+  // check; otherwise the slot table is rebuilt from the instances' state
+  const bool same = sig == E->layout && E->slots_current;
+  if (!same) {
+    if (E->pending_upload) (void)hipStreamSynchronize(s);  // h_slots may still be read
+    E->pending_upload = false;
+    for (int a = 0; a < A; ++a) {
+      uc_lp* lp = E->active[a];
+      lp->slot = a;
+      SlotDev S = make_slot(lp);
+      S.scal = E->d_scal + (size_t)a * kScal;
+      S.tau[0] = lp->st.eta / lp->st.omega;
+      S.sigma[0] = lp->st.eta * lp->st.omega;
+      S.k0[0] = lp->st.k_inner;
+      S.restart[0] = 0;
+      S.active[0] = 1;
+      E->h_slots[a] = S;
+    }
   }
+  E->slots_current = false;
   hipError_t e = hipSuccess;
   std::vector<Tile> all;
   if (sig != E->layout) {
@@ -1209,8 +1224,8 @@ static void run_epochs(uc_engine* E) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors die at scope end
     E->layout = sig;
   }
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(E->d_slots, E->h_slots.data(), A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !same)
+    e = hipMemcpyAsync(E->d_slots, E->h_slots, A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
   const Tile* T1 = E->d_tiles;
   const Tile* T0 = E->d_tiles + E->off_t0;
   const Tile* A1 = E->d_tiles + E->off_a1;
@@ -1259,15 +1274,31 @@ static void run_epochs(uc_engine* E) {
   }
   const double tnow = now_s();
   std::vector<CheckOut> outs(A);
+  bool changed = false;
   for (int a = 0; a < A; ++a) {
     uc_lp* lp = E->active[a];
-    // the finish kernel needs the epoch-start k0 and the restart decision
     outs[a] = process_check(lp, E->h_scal + (size_t)a * kScal, K, tnow);
-    E->h_slots[a].restart[0] = outs[a].restart ? (lp->opts.restart_to_current ? 2 : 1) : 0;
+    changed |= outs[a].terminate || outs[a].promote;
+    // one upload serves the finish kernel (restart decision, the check
+    // step's index) and the next epoch (its k0, tau, sigma)
+    SlotDev& S = E->h_slots[a];
+    S.restart[0] = outs[a].restart ? (lp->opts.restart_to_current ? 2 : 1) : 0;
+    S.kfin = S.k0[0] + K - 1;
+    S.k0[0] = lp->st.k_inner;
+    S.tau[0] = lp->st.eta / lp->st.omega;
+    S.sigma[0] = lp->st.eta * lp->st.omega;
   }
-  e = hipMemcpyAsync(E->d_slots, E->h_slots.data(), A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
-  launch_finish(1, E->d_slots, T1, nT1, A1, nA1, K - 1, 1, s);
-  launch_finish(0, E->d_slots, T0, nT0, A0, nA0, K - 1, 1, s);
+  e = hipMemcpyAsync(E->d_slots, E->h_slots, A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
+  launch_finish(1, E->d_slots, T1, nT1, A1, nA1, 0, 1, s);
+  launch_finish(0, E->d_slots, T0, nT0, A0, nA0, 0, 1, s);
+  if (!changed && e == hipSuccess) {
+    // nothing leaves or switches precision: the next epoch follows on the
+    // stream without waiting for the finish kernels (the half-steps do not
+    // read the restart flag)
+    E->slots_current = true;
+    E->pending_upload = true;
+    return;
+  }
   // precision switches: FP32 x_hat, y_hat -> FP64 iterates of the same slot
   std::vector<Tile> pt, pa, both;
   for (int a = 0; a < A; ++a)
@@ -1346,6 +1377,7 @@ static int engine_init(uc_engine* E) {
   HIPOK(hipMalloc(&E->d_slots, sizeof(SlotDev) * E->max_slots));
   HIPOK(hipMalloc(&E->d_ids, sizeof(int) * E->max_slots));
   HIPOK(hipHostMalloc((void**)&E->h_scal, sizeof(double) * kScal * E->max_slots, hipHostMallocDefault));
+  HIPOK(hipHostMalloc((void**)&E->h_slots, sizeof(SlotDev) * E->max_slots, hipHostMallocDefault));
   HIPOK(hipMalloc(&E->d_scal, sizeof(double) * kScal * E->max_slots));
   HIPOK(hipMalloc(&E->d_red2, sizeof(double) * kRedChunks * (RQ_N + CQ_N) * E->max_slots));
   for (auto& ev : E->ev) HIPOK(hipEventCreate(&ev));
@@ -1368,6 +1400,7 @@ static void engine_free(uc_engine* E) {
   if (E->d_scal) (void)hipFree(E->d_scal);
   if (E->d_red2) (void)hipFree(E->d_red2);
   if (E->h_scal) (void)hipHostFree(E->h_scal);
+  if (E->h_slots) (void)hipHostFree(E->h_slots);
   for (auto& ev : E->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (E->stream) (void)hipStreamDestroy(E->stream);
@@ -1708,6 +1741,7 @@ static int debug_step_t(uc_lp* lp, const double* x, const double* y, const doubl
   S.tau[0] = tau;
   S.sigma[0] = sigma;
   S.k0[0] = k;
+  S.kfin = k;
   S.active[0] = 1;
   std::vector<Tile> tl;
   push_tiles(tl, 0, P.t_blk, P.t_ptr, &P.t_flag, &P.t_base);

@@ -80,6 +80,8 @@ struct SlotDev {
   int restart[kMaxScen];        // set by the host before the finish kernel
   int active[kMaxScen];         // 0: scenario frozen (converged)
   double gamma;                 // Halpern reflection: w((1+g) T(z) - g z) + (1-w) z0
+  long long kfin;               // single-scenario slots: iteration index of the
+                                // check step the finish kernel completes
 };
 
 // One unit of work of the batched kernels: a row block of one slot, with its
