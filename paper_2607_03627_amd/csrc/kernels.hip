@@ -148,33 +148,12 @@ __device__ __forceinline__ UCLP_GLOBAL T* gst(T* p) {
   return (UCLP_GLOBAL T*)p;
 }
 
-// Staging of one row block's products val[k] * g[col[k]] into LDS.  Every
-// thread first issues all of its (at most kItems) column-index and value
-// loads, then all gathers, so each wave keeps many independent loads in
-// flight before the block barrier.
+// Staging of one row block's products into LDS: every thread issues all of
+// its (at most kItems) entry loads, then all gathers, so each wave keeps many
+// independent loads in flight before the block barrier.
 constexpr int kItems = kNnzTile / kThreads;
 
-template <typename T, typename G>
-__device__ inline void stage_products(const int* __restrict__ col, const T* __restrict__ val,
-                                      const G* __restrict__ g, int nz, T* lds) {
-  int c[kItems];
-  T v[kItems];
-#pragma unroll
-  for (int u = 0; u < kItems; ++u) {
-    const int k = threadIdx.x + u * kThreads;
-    if (k < nz) {
-      c[u] = col[k];
-      v[u] = val[k];
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kItems; ++u) {
-    const int k = threadIdx.x + u * kThreads;
-    if (k < nz) lds[k] = v[u] * (T)g[c[u]];
-  }
-}
-
-// The same staging from the block's entries in column order: the gathers of
+// The staging reads the block's entries in column order: the gathers of
 // neighbouring lanes fall on neighbouring cache lines, and each product is
 // written to its CSR position dst[k] so the per-row sums keep CSR order.
 template <typename T, typename G>
