@@ -1481,6 +1481,7 @@ extern "C" int uc_lp_create(uc_engine* eng, int32_t m, int32_t n, int64_t nnz, c
   presolve_structure(P);
   presolve_data(P, P);
   if (P.ni == 0) return fail(UC_LP_ENOTSUP, "every column is fixed; nothing to solve");
+  if (P.mi == 0) return fail(UC_LP_ENOTSUP, "no row has an entry in a free column; nothing for PDHG to solve");
   lp->need_bytes = arena_bytes(P, 1);
   std::memset(&lp->info, 0, sizeof lp->info);
   lp->info.t_to_eps_s = -1;

@@ -362,6 +362,31 @@ def test_weight_bound_of_one_fixes_the_primal_weight():
     assert c["omega"] != a["omega"]
 
 
+def test_columns_without_entries():
+    # 600 columns that appear in no row fill whole row blocks of A^T with no
+    # entries; each goes to the bound its cost points at, so the optimum
+    # moves by the sum of the negative costs
+    lp = make_instance("tiny", 6)
+    z = GOLDEN["tiny/6"]["obj"]
+    k = 600
+    rng = np.random.default_rng(6)
+    cx = rng.uniform(-2.0, 2.0, k)
+    wide = LP(m=lp.m, n=lp.n + k, row_ptr=lp.row_ptr, col_idx=lp.col_idx, val=lp.val,
+              c=np.append(lp.c, cx), b=lp.b, sense=lp.sense, lb=np.append(lp.lb, np.zeros(k)),
+              ub=np.append(lp.ub, np.ones(k)))
+    say("case tiny 6 with empty columns")
+    x, y, info = solve(wide, precision=uclp.UC_LP_FP64, eps_rel=1e-8)
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    zz = z + cx[cx < 0].sum()
+    assert abs(info["pobj"] - zz) <= 1e-6 * abs(zz)
+    xe = x[lp.n:]
+    assert np.all((xe >= 0) & (xe <= 1))
+    # a column whose cost is small next to the objective's scale may stop
+    # short of its bound within the relative KKT tolerance; the others reach it
+    big = np.abs(cx) > 0.1
+    assert np.max(np.abs(xe[big] - (cx[big] < 0))) <= 1e-6
+
+
 def test_long_rows_solve_matches_simplex_oracle():
     # long rows of A and of A^T take the block-wide path in every kernel
     lp = ragged_instance(1)

@@ -90,6 +90,21 @@ def test_create_rejects_malformed_input_without_a_device(case):
     assert uclp.uc_lp_last_error() != ""
 
 
+def test_degenerate_problems_are_refused_before_the_device():
+    # every column fixed, or no row left after the minimal presolve: there is
+    # no PDHG problem, and the call fails before any device work
+    lp = small()
+    fixed = mutated(lb=lambda a: np.zeros_like(a), ub=lambda a: np.zeros_like(a))
+    rc, h = uclp.uc_lp_create(fixed, raw=True)
+    assert rc == uclp.UC_LP_ENOTSUP and h is None
+    empty = LP(m=2, n=3, row_ptr=np.zeros(3, np.int32), col_idx=np.zeros(0, np.int32), val=np.zeros(0),
+               c=np.array([1.0, -1.0, 0.0]), b=np.zeros(2), sense=np.array([ord("E"), ord("G")], np.uint8),
+               lb=np.zeros(3), ub=np.ones(3))
+    rc, h = uclp.uc_lp_create(empty, raw=True)
+    assert rc == uclp.UC_LP_ENOTSUP and h is None
+    assert "row" in uclp.uc_lp_last_error()
+
+
 def test_bad_options_are_rejected():
     lp = small()
     for kw, code in ((dict(precision=7), uclp.UC_LP_ENOTSUP), (dict(kkt_every=0), uclp.UC_LP_EINVAL),
