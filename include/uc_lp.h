@@ -197,6 +197,8 @@ void uc_engine_destroy(uc_engine* eng);
  *   NaN or infinite matrix value, cost or right-hand side, lb > ub,
  *   lb = +inf or ub = -inf, unknown sense code.
  * EBUDGET: the instance needs more device memory than the engine budget.
+ * ENOTSUP: every column is fixed, or no row keeps an entry in a free column
+ *   (nothing is left for PDHG).
  * The minimal presolve removes fixed columns (lb == ub) and empty rows; an
  * empty row that cannot be satisfied makes the instance INFEASIBLE (reported
  * by uc_lp_status after uc_lp_solve, not as an error here). */
@@ -224,8 +226,8 @@ int uc_lp_status(const uc_lp* lp, uc_lp_info* out);
  * (timeout_s < 0: no limit).  ETIMEOUT on timeout. */
 int uc_lp_wait(uc_lp* lp, double timeout_s);
 
-/* Request termination of a queued or running solve (the "terminate the
- * other solver" step of Algorithm 1).  Takes effect at the next check
+/* Request termination of a queued or running solve (the step of Algorithm 1
+ * that stops the slower leg).  Takes effect at the next check
  * (at most kkt_every iterations later); the status becomes CANCELLED.
  * OK if nothing is running. */
 int uc_lp_cancel(uc_lp* lp);
@@ -268,7 +270,7 @@ int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* c,
 int uc_lp_internal_dims(uc_lp* lp, int32_t* m_int, int32_t* n_int, int64_t* nnz_int,
                         int32_t* m_eq, int32_t* row_map, int32_t* col_map);
 
-/* The transpose built on the device (Sec. "a stored A^T"): t_row_ptr[n_int+1],
+/* The transpose built on the device: t_row_ptr[n_int+1],
  * t_col[nnz_int], t_val[nnz_int] of the UNSCALED internal matrix, with the
  * entries of each transposed row in increasing original row order. */
 int uc_lp_get_transpose(uc_lp* lp, int32_t* t_row_ptr, int32_t* t_col, double* t_val);
@@ -282,7 +284,8 @@ int uc_lp_get_scaling(uc_lp* lp, double* d_row, double* d_col, double* norm_est)
  * iteration index k and steps tau, sigma, computes
  *   x_hat = proj_[l,u](x - tau (c - A'y)),
  *   y_hat = proj_Y(y + sigma (b - A (2 x_hat - x))),
- *   x_next = w (2 x_hat - x) + (1 - w) x0,  y_next likewise, w = (k+1)/(k+2).
+ *   x_next = w ((1+g) x_hat - g x) + (1 - w) x0,  y_next likewise,
+ *   w = (k+1)/(k+2), g = the handle's halpern_gamma (1 by default).
  * All vectors are FP64 host arrays of internal length (x*: n_int, y*: m_int);
  * FP32 mode rounds the inputs to FP32 and widens the outputs. */
 int uc_lp_debug_step(uc_lp* lp, int32_t precision, const double* x, const double* y,
