@@ -100,6 +100,7 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->pw_max_change = 4.0;
   o->pw_integral = 0.0;
   o->pw_balance = 0.5;
+  o->pw_balance_polish = 0.0;
   o->fp32_stall_checks = 24;
   o->reserved = 0;
 }
@@ -119,7 +120,8 @@ static int check_opts(const uc_lp_opts& o) {
       !(o.restart_artificial > 0 && o.restart_artificial <= 1) || !(o.pw_smoothing >= 0 && o.pw_smoothing <= 1) ||
       (o.restart_to_current != 0 && o.restart_to_current != 1) || !(o.halpern_gamma >= 0 && o.halpern_gamma <= 1) ||
       !(o.pw_max_change == 0 || o.pw_max_change >= 1) || o.fp32_stall_checks < 0 || o.reserved != 0 ||
-      !(o.pw_integral >= 0 && o.pw_integral <= 1) || !(o.pw_balance >= 0 && o.pw_balance <= 1))
+      !(o.pw_integral >= 0 && o.pw_integral <= 1) || !(o.pw_balance >= 0 && o.pw_balance <= 1) ||
+      !(o.pw_balance_polish >= 0 && o.pw_balance_polish <= 1))
     return fail(UC_LP_EINVAL, "restart / primal-weight parameters out of range");
   return UC_LP_OK;
 }
@@ -1004,8 +1006,8 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
         st.pw_int += e;
         double lw = std::log(st.omega) - th * e - o.pw_integral * st.pw_int;
         // residual balance: a primal residual above the dual one raises w
-        if (o.pw_balance > 0 && in.rel_primal > 0 && in.rel_dual > 0)
-          lw += o.pw_balance * std::log(in.rel_primal / in.rel_dual);
+        const double gb = o.precision == UC_LP_FP32_MIXED_POLISH ? o.pw_balance_polish : o.pw_balance;
+        if (gb > 0 && in.rel_primal > 0 && in.rel_dual > 0) lw += gb * std::log(in.rel_primal / in.rel_dual);
         double w = std::exp(lw);
         if (o.pw_max_change >= 1) w = std::min(std::max(w, st.omega / o.pw_max_change), st.omega * o.pw_max_change);
         st.omega = w;

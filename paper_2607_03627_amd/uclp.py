@@ -40,7 +40,7 @@ class uc_lp_opts(C.Structure):
                 ("restart_artificial", C.c_double), ("pw_smoothing", C.c_double),
                 ("halpern_gamma", C.c_double), ("pw_max_change", C.c_double),
                 ("fp32_stall_checks", C.c_int32), ("reserved", C.c_int32), ("pw_integral", C.c_double),
-                ("pw_balance", C.c_double)]
+                ("pw_balance", C.c_double), ("pw_balance_polish", C.c_double)]
 
 
 class uc_lp_info(C.Structure):

@@ -38,14 +38,14 @@ def test_library_exports_every_declared_symbol():
 
 def test_binding_structs_match_header_layout():
     # the two structs are passed by pointer; their sizes must agree with the C layout
-    assert ctypes.sizeof(uclp.uc_lp_opts) == 4 * 4 + 8 + 5 * 8 + 4 * 4 + 6 * 8 + 2 * 4 + 2 * 8
+    assert ctypes.sizeof(uclp.uc_lp_opts) == 4 * 4 + 8 + 5 * 8 + 4 * 4 + 6 * 8 + 2 * 4 + 3 * 8
     o = uclp.uc_lp_opts_default()
     assert o.precision == uclp.UC_LP_FP32_MIXED_POLISH and o.kkt_every == 64
     assert o.iter_limit == 100000 and o.eps_rel == 1e-4 and o.eps_polish == 1e-8
     assert (o.restart_sufficient, o.restart_necessary, o.restart_artificial, o.pw_smoothing) == \
         (0.2, 0.9, 0.36, 0.8)
     assert o.halpern_gamma == 1.0 and o.pw_max_change == 4.0 and o.fp32_stall_checks == 24 and o.reserved == 0
-    assert o.pw_integral == 0.0 and o.pw_balance == 0.5
+    assert o.pw_integral == 0.0 and o.pw_balance == 0.5 and o.pw_balance_polish == 0.0
 
 
 def small():
