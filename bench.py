@@ -53,21 +53,28 @@ def dual_bytes(n, m, nnz, vb=4):
     return nnz * (vb + 4) + 4 * (m + 1) + vb * n + 4 * vb * m
 
 
+# the device code and the launch shape it is compiled for
+KERNEL_SOURCES = ("kernels.hip", "uclp_dev.h")
+
+
 def measured_traffic(kernel="k_primal"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source changed since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "k_primal_large_traffic.json")
-    src = os.path.join(ROOT, "paper_2607_03627_amd", "csrc", "kernels.hip")
+    csrc = os.path.join(ROOT, "paper_2607_03627_amd", "csrc")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for name in KERNEL_SOURCES:
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+        digest = h.hexdigest()
     except OSError:
         return None
-    if rec.get("kernels_hip_sha256") != digest:
+    if rec.get("kernel_sources_sha256") != digest:
         return None
     return rec.get(kernel, {}).get("traffic_bytes")
 

@@ -10,10 +10,10 @@ namespace uclp {
 // Row blocks: at most kRowsPerBlock rows and kNnzTile entries, except a
 // block holding one row longer than kNnzTile (handled by a block-wide loop).
 // Thread t of a workgroup owns rows r0 + t + q * kThreads, q < kRowsPerThread.
-constexpr int kThreads = 512;
-constexpr int kRowsPerThread = 1;
+constexpr int kThreads = 256;
+constexpr int kRowsPerThread = 2;
 constexpr int kRowsPerBlock = kThreads * kRowsPerThread;
-constexpr int kNnzTile = 4 * kThreads;
+constexpr int kNnzTile = 2048;
 constexpr int kMaxScen = 16;
 
 // Per-block partial sums written by the KKT check kernels.
