@@ -149,59 +149,61 @@ __device__ __forceinline__ UCLP_GLOBAL T* gst(T* p) {
 }
 
 // Staging of one row block's products into LDS: every thread issues all of
-// its (at most kItems) entry loads, then all gathers, so each wave keeps many
-// independent loads in flight before the block barrier.
+// its (at most kNnzTile / NT) entry loads, then all gathers, so each wave
+// keeps many independent loads in flight before the block barrier.
 constexpr int kItems = kNnzTile / kThreads;
 
 // The staging reads the block's entries in column order: the gathers of
 // neighbouring lanes fall on neighbouring cache lines, and each product is
 // written to its CSR position dst[k] so the per-row sums keep CSR order.
-template <typename T, typename G>
+template <typename T, typename G, int NT = kThreads>
 __device__ inline void stage_sorted(const int* cs_, const T* vs_, const unsigned short* dst_, const G* g_, int nz,
                                     T* lds) {
   // straight-line loads: items past the block's end re-read its last entry
   // and are not written, so all gathers of a thread are in flight together
+  constexpr int kIt = kNnzTile / NT;
   if (nz <= 0) return;
   const UCLP_GLOBAL int* cs = gld(cs_);
   const UCLP_GLOBAL T* vs = gld(vs_);
   const UCLP_GLOBAL unsigned short* dst = gld(dst_);
   const UCLP_GLOBAL G* g = gld(g_);
-  int c[kItems], d[kItems];
-  T v[kItems], gv[kItems];
+  int c[kIt], d[kIt];
+  T v[kIt], gv[kIt];
 #pragma unroll
-  for (int u = 0; u < kItems; ++u) {
-    const int k = min((int)threadIdx.x + u * kThreads, nz - 1);
+  for (int u = 0; u < kIt; ++u) {
+    const int k = min((int)threadIdx.x + u * NT, nz - 1);
     c[u] = cs[k];
     v[u] = vs[k];
     d[u] = dst[k];
   }
 #pragma unroll
-  for (int u = 0; u < kItems; ++u) gv[u] = (T)g[c[u]];
+  for (int u = 0; u < kIt; ++u) gv[u] = (T)g[c[u]];
 #pragma unroll
-  for (int u = 0; u < kItems; ++u)
-    if ((int)threadIdx.x + u * kThreads < nz) lds[d[u]] = v[u] * gv[u];
+  for (int u = 0; u < kIt; ++u)
+    if ((int)threadIdx.x + u * NT < nz) lds[d[u]] = v[u] * gv[u];
 }
 
 // The same from the packed words: one 4-byte read per entry for index and slot.
-template <typename T, typename G>
+template <typename T, typename G, int NT = kThreads>
 __device__ inline void stage_packed(const unsigned* pk_, const T* vs_, int base, const G* g_, int nz, T* lds) {
+  constexpr int kIt = kNnzTile / NT;
   if (nz <= 0) return;
   const UCLP_GLOBAL unsigned* pk = gld(pk_);
   const UCLP_GLOBAL T* vs = gld(vs_);
   const UCLP_GLOBAL G* gb = gld(g_) + base;
-  unsigned p[kItems];
-  T v[kItems], gv[kItems];
+  unsigned p[kIt];
+  T v[kIt], gv[kIt];
 #pragma unroll
-  for (int u = 0; u < kItems; ++u) {
-    const int k = min((int)threadIdx.x + u * kThreads, nz - 1);
+  for (int u = 0; u < kIt; ++u) {
+    const int k = min((int)threadIdx.x + u * NT, nz - 1);
     p[u] = pk[k];
     v[u] = vs[k];
   }
 #pragma unroll
-  for (int u = 0; u < kItems; ++u) gv[u] = (T)gb[p[u] & kPackMask];
+  for (int u = 0; u < kIt; ++u) gv[u] = (T)gb[p[u] & kPackMask];
 #pragma unroll
-  for (int u = 0; u < kItems; ++u)
-    if ((int)threadIdx.x + u * kThreads < nz) lds[p[u] >> kPackShift] = v[u] * gv[u];
+  for (int u = 0; u < kIt; ++u)
+    if ((int)threadIdx.x + u * NT < nz) lds[p[u] >> kPackShift] = v[u] * gv[u];
 }
 
 // The entries of a row block that fits the LDS tile, in column order, kItems
@@ -279,17 +281,17 @@ __device__ inline void block_rows_sorted(const Tile& tl, const int* __restrict__
 }
 
 // Sum of one long row (above kNnzTile entries) by the whole block; valid in thread 0.
-template <typename T, typename G>
+template <typename T, typename G, int NT = kThreads>
 __device__ inline T long_row_sum(const int* __restrict__ col, const T* __restrict__ val,
                                  const G* __restrict__ g, int nz, T* red) {
   T s = 0;
-  for (int k = threadIdx.x; k < nz; k += kThreads) s += val[k] * (T)g[col[k]];
+  for (int k = threadIdx.x; k < nz; k += NT) s += val[k] * (T)g[col[k]];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   T t = red[0];
-  for (int w = 1; w < kThreads / 64; ++w) t += red[w];
+  for (int w = 1; w < NT / 64; ++w) t += red[w];
   return t;
 }
 
@@ -304,13 +306,14 @@ __device__ inline T long_row_sum(const int* __restrict__ col, const T* __restric
 // anchor, with the previous launch's w'.  The first launch after a check
 // reads x itself, and a check launch stores the rebuilt x for the KKT and
 // finish kernels.
-// Thread t handles rows r0 + t + q * kThreads, q < kRowsPerThread.
-template <typename T, bool CHECK>
-__global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__ slots,
+// NT threads per workgroup; thread t handles rows r0 + t + q * NT, q < kRowsPerBlock / NT.
+template <typename T, bool CHECK, int NT>
+__global__ __launch_bounds__(NT) void k_primal(const SlotDev* __restrict__ slots,
                                                      const Tile* __restrict__ tiles, int ntiles,
                                                      int jiter) {
   __shared__ T lds[kNnzTile];
-  __shared__ T red[kThreads / 64];
+  __shared__ T red[NT / 64];
+  constexpr int kRpt = kRowsPerBlock / NT;
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
   const Tile tl = tiles[t];
@@ -333,11 +336,11 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   // are straight-line: a thread past the block's last row loads that row
   // and skips the epilogue; values that depend on loads (x rebuilt, l = -u)
   // are formed after the barrier.
-  int a[kRowsPerThread], b[kRowsPerThread];
-  T c[kRowsPerThread], lr[kRowsPerThread], u[kRowsPerThread], xv[kRowsPerThread], xa[kRowsPerThread];
+  int a[kRpt], b[kRpt];
+  T c[kRpt], lr[kRpt], u[kRpt], xv[kRpt], xa[kRpt];
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int j = min(r0 + (int)threadIdx.x + q * kThreads, r1 - 1);
+  for (int q = 0; q < kRpt; ++q) {
+    const int j = min(r0 + (int)threadIdx.x + q * NT, r1 - 1);
     const int ap = rend[max(j - 1, r0)];
     a[q] = j == r0 ? 0 : ap;
     b[q] = rend[j];
@@ -353,21 +356,21 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
       if (!CHECK) xa[q] = gld(V.x0)[j];
     }
   }
-  T s[kRowsPerThread];
+  T s[kRpt];
   if (nz <= kNnzTile) {
     if (tl.base >= 0)
-      stage_packed<T, T>(S.t_pk + k0, V.tvs + k0, tl.base, V.y, nz, lds);
+      stage_packed<T, T, NT>(S.t_pk + k0, V.tvs + k0, tl.base, V.y, nz, lds);
     else
-      stage_sorted<T, T>(S.t_cs + k0, V.tvs + k0, S.t_dst + k0, V.y, nz, lds);
+      stage_sorted<T, T, NT>(S.t_cs + k0, V.tvs + k0, S.t_dst + k0, V.y, nz, lds);
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) {
+    for (int q = 0; q < kRpt; ++q) {
       T acc = 0;
       for (int k = a[q]; k < b[q]; ++k) acc += lds[k];
       s[q] = acc;
     }
   } else {
-    s[0] = long_row_sum<T, T>(S.t_col + k0, V.tv + k0, V.y, nz, red);
+    s[0] = long_row_sum<T, T, NT>(S.t_col + k0, V.tv + k0, V.y, nz, red);
     if (threadIdx.x != 0) return;
   }
   const T tau = (T)S.tau[0];
@@ -375,8 +378,8 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
   const T w = (T)((kk + 1.0) / (kk + 2.0));
   const T wa = (T)(1.0 / (kk + 2.0));
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int j = r0 + threadIdx.x + q * kThreads;
+  for (int q = 0; q < kRpt; ++q) {
+    const int j = r0 + threadIdx.x + q * NT;
     if (j >= r1) break;
     const T x = rebuild ? wp * xv[q] + wap * xa[q] : xv[q];
     const T l = (fl & kColL0) ? (T)0 : (fl & kColLInf) ? -(T)INFINITY : (fl & kColLNegU) ? -u[q] : lr[q];
@@ -395,12 +398,13 @@ __global__ __launch_bounds__(kThreads) void k_primal(const SlotDev* __restrict__
 // Dual half-step over the rows of A:
 //   y_hat = y + sigma (b - A xbar), projected to y >= 0 on rows i >= m_eq
 //   non-check: y <- w ((1+gamma) y_hat - gamma y) + (1 - w) y0 ; check: y_hat stored
-template <typename T, bool CHECK>
-__global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ slots,
+template <typename T, bool CHECK, int NT>
+__global__ __launch_bounds__(NT) void k_dual(const SlotDev* __restrict__ slots,
                                                    const Tile* __restrict__ tiles, int ntiles,
                                                    int jiter) {
   __shared__ T lds[kNnzTile];
-  __shared__ T red[kThreads / 64];
+  __shared__ T red[NT / 64];
+  constexpr int kRpt = kRowsPerBlock / NT;
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
   const Tile tl = tiles[t];
@@ -411,11 +415,11 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
   const int k0 = tl.k0;
   const int nz = tl.k1 - k0;
   // straight-line epilogue loads, as in k_primal
-  int a[kRowsPerThread], b[kRowsPerThread];
-  T bi[kRowsPerThread], y[kRowsPerThread], ya[kRowsPerThread];
+  int a[kRpt], b[kRpt];
+  T bi[kRpt], y[kRpt], ya[kRpt];
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int i = min(r0 + (int)threadIdx.x + q * kThreads, r1 - 1);
+  for (int q = 0; q < kRpt; ++q) {
+    const int i = min(r0 + (int)threadIdx.x + q * NT, r1 - 1);
     const int ap = rend[max(i - 1, r0)];
     a[q] = i == r0 ? 0 : ap;
     b[q] = rend[i];
@@ -423,21 +427,21 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
     y[q] = gld(V.y)[i];
     ya[q] = CHECK ? (T)0 : gld(V.y0)[i];
   }
-  T s[kRowsPerThread];
+  T s[kRpt];
   if (nz <= kNnzTile) {
     if (tl.base >= 0)
-      stage_packed<T, T>(S.a_pk + k0, V.avs + k0, tl.base, V.xbar, nz, lds);
+      stage_packed<T, T, NT>(S.a_pk + k0, V.avs + k0, tl.base, V.xbar, nz, lds);
     else
-      stage_sorted<T, T>(S.a_cs + k0, V.avs + k0, S.a_dst + k0, V.xbar, nz, lds);
+      stage_sorted<T, T, NT>(S.a_cs + k0, V.avs + k0, S.a_dst + k0, V.xbar, nz, lds);
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) {
+    for (int q = 0; q < kRpt; ++q) {
       T acc = 0;
       for (int k = a[q]; k < b[q]; ++k) acc += lds[k];
       s[q] = acc;
     }
   } else {
-    s[0] = long_row_sum<T, T>(S.a_col + k0, V.av + k0, V.xbar, nz, red);
+    s[0] = long_row_sum<T, T, NT>(S.a_col + k0, V.av + k0, V.xbar, nz, red);
     if (threadIdx.x != 0) return;
   }
   const T sigma = (T)S.sigma[0];
@@ -446,8 +450,8 @@ __global__ __launch_bounds__(kThreads) void k_dual(const SlotDev* __restrict__ s
   const T wa = (T)(1.0 / (kk + 2.0));
   const T g1 = (T)(1.0 + S.gamma), g = (T)S.gamma;
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int i = r0 + threadIdx.x + q * kThreads;
+  for (int q = 0; q < kRpt; ++q) {
+    const int i = r0 + threadIdx.x + q * NT;
     if (i >= r1) break;
     T yh = y[q] + sigma * (bi[q] - s[q]);
     if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
@@ -1523,12 +1527,39 @@ __global__ __launch_bounds__(kCopyThreads) void k_copy(const v4f* __restrict__ a
 
 static inline int nb(int64_t n, int t = kThreads) { return (int)((n + t - 1) / t); }
 
-template <typename K>
+template <int NT, typename K>
 static void launch_tiles(K kern, int ntiles, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
                          const SlotDev* slots, const Tile* tiles, int jiter) {
   const dim3 g(xcd_grid(ntiles));
-  if (e0 && e1) hipExtLaunchKernelGGL(kern, g, dim3(kThreads), 0, s, e0, e1, 0, slots, tiles, ntiles, jiter);
-  else kern<<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+  if (e0 && e1) hipExtLaunchKernelGGL(kern, g, dim3(NT), 0, s, e0, e1, 0, slots, tiles, ntiles, jiter);
+  else kern<<<g, NT, 0, s>>>(slots, tiles, ntiles, jiter);
+}
+
+// Workgroup size of the half-steps.  A launch of many tiles runs kThreads
+// threads with several rows and kNnzTile / kThreads staged entries each:
+// more loads in flight per thread, which is what a bandwidth-bound launch
+// needs.  A launch that fits the chip in one pass even with one row per
+// thread (kRowsPerBlock threads; four such workgroups per CU, 256 CUs) runs
+// that shape instead, which shortens each thread's serial chain.
+constexpr int kWideThreads = kRowsPerBlock;
+constexpr int kFewTiles = 1024;
+
+template <typename T, bool CHECK>
+static void launch_primal_t(int ntiles, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const SlotDev* slots,
+                            const Tile* tiles, int jiter) {
+  if (ntiles < kFewTiles)
+    launch_tiles<kWideThreads>(k_primal<T, CHECK, kWideThreads>, ntiles, s, e0, e1, slots, tiles, jiter);
+  else
+    launch_tiles<kThreads>(k_primal<T, CHECK, kThreads>, ntiles, s, e0, e1, slots, tiles, jiter);
+}
+
+template <typename T, bool CHECK>
+static void launch_dual_t(int ntiles, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const SlotDev* slots,
+                          const Tile* tiles, int jiter) {
+  if (ntiles < kFewTiles)
+    launch_tiles<kWideThreads>(k_dual<T, CHECK, kWideThreads>, ntiles, s, e0, e1, slots, tiles, jiter);
+  else
+    launch_tiles<kThreads>(k_dual<T, CHECK, kThreads>, ntiles, s, e0, e1, slots, tiles, jiter);
 }
 
 void launch_primal(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
@@ -1536,11 +1567,11 @@ void launch_primal(int prec, bool check, const SlotDev* slots, const Tile* tiles
   if (ntiles <= 0) return;
   (void)nscen;
   if (prec == 1) {
-    if (check) launch_tiles(k_primal<float, true>, ntiles, s, e0, e1, slots, tiles, jiter);
-    else launch_tiles(k_primal<float, false>, ntiles, s, e0, e1, slots, tiles, jiter);
+    if (check) launch_primal_t<float, true>(ntiles, s, e0, e1, slots, tiles, jiter);
+    else launch_primal_t<float, false>(ntiles, s, e0, e1, slots, tiles, jiter);
   } else {
-    if (check) launch_tiles(k_primal<double, true>, ntiles, s, e0, e1, slots, tiles, jiter);
-    else launch_tiles(k_primal<double, false>, ntiles, s, e0, e1, slots, tiles, jiter);
+    if (check) launch_primal_t<double, true>(ntiles, s, e0, e1, slots, tiles, jiter);
+    else launch_primal_t<double, false>(ntiles, s, e0, e1, slots, tiles, jiter);
   }
 }
 
@@ -1549,11 +1580,11 @@ void launch_dual(int prec, bool check, const SlotDev* slots, const Tile* tiles, 
   if (ntiles <= 0) return;
   (void)nscen;
   if (prec == 1) {
-    if (check) launch_tiles(k_dual<float, true>, ntiles, s, e0, e1, slots, tiles, jiter);
-    else launch_tiles(k_dual<float, false>, ntiles, s, e0, e1, slots, tiles, jiter);
+    if (check) launch_dual_t<float, true>(ntiles, s, e0, e1, slots, tiles, jiter);
+    else launch_dual_t<float, false>(ntiles, s, e0, e1, slots, tiles, jiter);
   } else {
-    if (check) launch_tiles(k_dual<double, true>, ntiles, s, e0, e1, slots, tiles, jiter);
-    else launch_tiles(k_dual<double, false>, ntiles, s, e0, e1, slots, tiles, jiter);
+    if (check) launch_dual_t<double, true>(ntiles, s, e0, e1, slots, tiles, jiter);
+    else launch_dual_t<double, false>(ntiles, s, e0, e1, slots, tiles, jiter);
   }
 }
 

@@ -9,7 +9,9 @@ namespace uclp {
 
 // Row blocks: at most kRowsPerBlock rows and kNnzTile entries, except a
 // block holding one row longer than kNnzTile (handled by a block-wide loop).
-// Thread t of a workgroup owns rows r0 + t + q * kThreads, q < kRowsPerThread.
+// Thread t of a workgroup owns rows r0 + t + q * kThreads, q < kRowsPerThread
+// (the half-step kernels of launches with few tiles run kRowsPerBlock
+// threads, one row each).
 constexpr int kThreads = 256;
 constexpr int kRowsPerThread = 2;
 constexpr int kRowsPerBlock = kThreads * kRowsPerThread;
