@@ -51,6 +51,31 @@ def test_alone_and_in_mix_are_bitwise_identical():
         assert k.rel_kkt <= 1e-7 * 1.001
 
 
+def test_both_half_step_shapes_give_identical_iterates():
+    # Alone, a 500-bus LP's half-steps are launches of a few hundred tiles and
+    # run one row per thread in 512-thread workgroups; beside the
+    # contingency-free 6,049-bus LP each launch holds over a thousand tiles
+    # and runs two rows per thread in 256-thread workgroups.  Each row's sum
+    # keeps CSR order in both shapes, so the iterates agree bit for bit.
+    few_tiles = 1024
+    small = make_instance("medium", 3)
+    big = make_instance("large_kc0", 3)
+    small_tiles_max = (small.m + small.n) // 512 + len(small.val) // 2048 + 2
+    assert small_tiles_max < few_tiles
+    assert min(big.m, big.n) // 512 >= few_tiles
+    opts = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-4)
+    say("alone", small.m, small.n)
+    a = serving.run_stream([small], [0.0], opts, max_slots=4, keep_solutions=True).served[0]
+    say("beside", big.m, big.n)
+    r = serving.run_stream([small, big], [0.0, 0.0], opts, max_slots=4, keep_solutions=True)
+    b = r.served[0]
+    say("iters", a.info["iters"], b.info["iters"], r.served[1].info["iters"])
+    assert a.info["status"] == uclp.UC_LP_OPTIMAL and b.info["status"] == uclp.UC_LP_OPTIMAL
+    assert r.served[1].info["status"] == uclp.UC_LP_OPTIMAL
+    assert a.info["iters"] == b.info["iters"] and a.info["restarts"] == b.info["restarts"]
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.y, b.y)
+
+
 def test_budget_admission_and_fifo():
     lps = requests(6, seed=1)
     need = []
