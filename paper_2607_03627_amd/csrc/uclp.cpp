@@ -151,6 +151,18 @@ static int validate_csr(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, co
   return UC_LP_OK;
 }
 
+// Runs f(t) for t in [0, count) on up to count host threads (the calling
+// thread takes t = 0) and joins them.  For independent per-scenario or
+// per-range host work; f must not throw.
+template <typename F>
+static void fork_join(int count, F f) {
+  std::vector<std::thread> th;
+  th.reserve(count > 1 ? count - 1 : 0);
+  for (int t = 1; t < count; ++t) th.emplace_back(f, t);
+  if (count > 0) f(0);
+  for (auto& x : th) x.join();
+}
+
 static int validate_data(int32_t m, int32_t n, const double* c, const double* b, const char* sense,
                          const double* lb, const double* ub) {
   if (!c || !b || !sense || !lb || !ub) return fail(UC_LP_EINVAL, "NULL data array");
@@ -2059,13 +2071,24 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   const int S = n_scen, n = P.n, m = P.m, ni = P.ni, mi = P.mi;
   // per-scenario validation and minimal presolve (same fixed-column structure as the base)
   std::vector<HostProblem> SP(S);
-  for (int s = 0; s < S; ++s) {
+  // each scenario's checks and presolve on a host thread of its own; an
+  // error is reported for the lowest-numbered failing scenario
+  std::vector<int> prc(S, UC_LP_OK);
+  std::vector<std::string> pmsg(S);
+  fork_join(S, [&](int s) {
     const double *cs = c + (size_t)s * n, *bs = b + (size_t)s * m, *ls = lb + (size_t)s * n, *us = ub + (size_t)s * n;
     int rc = validate_data(m, n, cs, bs, P.o_sense.data(), ls, us);
-    if (rc) return rc;
+    if (rc) {
+      prc[s] = rc;
+      pmsg[s] = g_err;
+      return;
+    }
     for (int32_t j = 0; j < n; ++j)
-      if ((ls[j] == us[j]) != (P.int_col[j] < 0))
-        return fail(UC_LP_ENOTSUP, "scenario %d: column %d differs from the base in being fixed", s, j);
+      if ((ls[j] == us[j]) != (P.int_col[j] < 0)) {
+        prc[s] = fail(UC_LP_ENOTSUP, "scenario %d: column %d differs from the base in being fixed", s, j);
+        pmsg[s] = g_err;
+        return;
+      }
     HostProblem& Q = SP[s];  // data only; the structure is the base's
     Q.m = m;
     Q.n = n;
@@ -2080,8 +2103,13 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
     Q.l.assign(ni, 0.0);
     Q.u.assign(ni, 0.0);
     presolve_data(Q, P);
-    if (Q.infeasible) return fail(UC_LP_EINVAL, "scenario %d is infeasible by its empty rows", s);
-  }
+    if (Q.infeasible) {
+      prc[s] = fail(UC_LP_EINVAL, "scenario %d is infeasible by its empty rows", s);
+      pmsg[s] = g_err;
+    }
+  });
+  for (int s = 0; s < S; ++s)
+    if (prc[s] != UC_LP_OK) return fail(prc[s], "%s", pmsg[s].c_str());
   // a block flag holds for the batch when it holds for every scenario
   std::vector<int> tflag = SP[0].t_flag, aflag = SP[0].a_flag;
   for (int s = 1; s < S; ++s) {
@@ -2139,10 +2167,16 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   std::vector<uc_lp_info> inf(S);
   std::vector<int> done(S, 0), status(S, UC_LP_RUNNING);
   const double t0 = now_s();
-  for (int s = 0; s < S; ++s) {
+  std::vector<double> cnorm(S), bnorm(S);
+  fork_join(S, [&](int s) {
     double cn = 0, bn = 0;
     for (int j = 0; j < ni; ++j) cn += (SP[s].c[j] * dc[j]) * (SP[s].c[j] * dc[j]);
     for (int i = 0; i < mi; ++i) bn += (SP[s].b[i] * dr[i]) * (SP[s].b[i] * dr[i]);
+    cnorm[s] = cn;
+    bnorm[s] = bn;
+  });
+  for (int s = 0; s < S; ++s) {
+    const double cn = cnorm[s], bn = bnorm[s];
     ps[s].eta = base->st.eta;
     ps[s].omega = (cn > 0 && bn > 0) ? std::sqrt(cn) / std::sqrt(bn) : 1.0;
     ps[s].prec = o.precision == UC_LP_FP64 ? 0 : 1;
@@ -2257,28 +2291,45 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   SCEN_HIP(hipStreamSynchronize(st));
   cleanup();
 #undef SCEN_HIP
+  const double t_end = now_s();
   for (int s = 0; s < S; ++s) {
     inf[s].status = status[s];
-    inf[s].t_total_s = now_s() - t0;
+    inf[s].t_total_s = t_end - t0;
     info[s] = inf[s];
-    const HostProblem& Q = SP[s];
+  }
+  // interleaved device order -> one array per scenario in the original
+  // numbering: each host thread reads a contiguous range of the interleaved
+  // results once and writes the S scenarios' entries of that range
+  const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  fork_join(nth, [&](int t) {
     if (x) {
-      double* xs = x + (size_t)s * n;
-      for (int32_t j = 0; j < n; ++j)
-        if (P.int_col[j] < 0) xs[j] = Q.o_lb[j];
-      for (int j = 0; j < ni; ++j)
-        xs[P.col_map[j]] = std::min(std::max(hx[(size_t)j * S + s], Q.l[j]), Q.u[j]);
+      const int j0 = (int)((int64_t)ni * t / nth), j1 = (int)((int64_t)ni * (t + 1) / nth);
+      for (int j = j0; j < j1; ++j) {
+        const int oj = P.col_map[j];
+        for (int s = 0; s < S; ++s)
+          x[(size_t)s * n + oj] = std::min(std::max(hx[(size_t)j * S + s], SP[s].l[j]), SP[s].u[j]);
+      }
+      const int f0 = (int)((int64_t)n * t / nth), f1 = (int)((int64_t)n * (t + 1) / nth);
+      for (int32_t j = f0; j < f1; ++j)
+        if (P.int_col[j] < 0)
+          for (int s = 0; s < S; ++s) x[(size_t)s * n + j] = SP[s].o_lb[j];
     }
     if (y) {
-      double* ys = y + (size_t)s * m;
-      std::fill(ys, ys + m, 0.0);
-      for (int i = 0; i < mi; ++i) {
-        const int enc = P.row_map[i];
-        const double v = hy[(size_t)i * S + s];
-        if (enc >= 0) ys[enc] = v;
-        else ys[-enc - 1] = -v;
-      }
+      const int r0 = (int)((int64_t)m * t / nth), r1 = (int)((int64_t)m * (t + 1) / nth);
+      for (int s = 0; s < S; ++s) std::fill(y + (size_t)s * m + r0, y + (size_t)s * m + r1, 0.0);
     }
-  }
+  });
+  if (y)  // after every thread has cleared its rows: the presolved rows scatter anywhere
+    fork_join(nth, [&](int t) {
+      const int i0 = (int)((int64_t)mi * t / nth), i1 = (int)((int64_t)mi * (t + 1) / nth);
+      for (int i = i0; i < i1; ++i) {
+        const int enc = P.row_map[i];
+        for (int s = 0; s < S; ++s) {
+          const double v = hy[(size_t)i * S + s];
+          if (enc >= 0) y[(size_t)s * m + enc] = v;
+          else y[(size_t)s * m + (-enc - 1)] = -v;
+        }
+      }
+    });
   return UC_LP_OK;
 }
