@@ -2029,6 +2029,30 @@ extern "C" int uc_copy_bench(int device, size_t bytes, int32_t reps, double* gbp
 // scenario batches over one matrix
 // ---------------------------------------------------------------------------
 
+// Lanes of an interleaved scenario array (element j of lane L at j * lanes +
+// L) kept by a batch after some of its scenarios have finished.
+struct LaneMap {
+  int src_lanes, dst_lanes;
+  int lane[kMaxScen];  // dst lane k <- src lane lane[k]
+};
+
+// dst[j * dst_lanes + k] = src[j * src_lanes + lane[k]] for j < rows.
+__global__ void k_compact_lanes(const double* __restrict__ src, double* __restrict__ dst, int64_t rows,
+                                LaneMap mp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * mp.dst_lanes) return;
+  const int64_t j = e / mp.dst_lanes;
+  const int k = (int)(e - j * mp.dst_lanes);
+  dst[e] = src[j * mp.src_lanes + mp.lane[k]];
+}
+
+static void launch_compact_lanes(const double* src, double* dst, int64_t rows, const LaneMap& mp, hipStream_t s) {
+  const int64_t total = rows * mp.dst_lanes;
+  if (total <= 0) return;
+  const int threads = 256;
+  k_compact_lanes<<<(unsigned)((total + threads - 1) / threads), threads, 0, s>>>(src, dst, rows, mp);
+}
+
 struct ScenArena {
   Arena ar;
   double *c_in, *l_in, *u_in, *b_in, *x_out, *y_out, *x_warm, *y_warm;
@@ -2135,7 +2159,11 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   A.ar.base = (char*)mem;
   A.ar.bytes = bytes;
   carve_scen(A, P, S);
-  auto cleanup = [&]() { (void)hipFree(mem); };
+  void* cmem = nullptr;  // FP64 arrays of the scenarios still running after the FP64 hand-over
+  auto cleanup = [&]() {
+    (void)hipFree(mem);
+    if (cmem) (void)hipFree(cmem);
+  };
 #define SCEN_HIP(call)                                                                           \
   do {                                                                                           \
     hipError_t e_ = (call);                                                                      \
@@ -2234,15 +2262,57 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   const Tile* TT = A.tiles;
   const Tile* TA = A.tiles + nt;
   const int K = o.kkt_every;
-  const int64_t NX = (int64_t)ni * S, NY = (int64_t)mi * S;
+  // lane L of the interleaved arrays holds scenario lane[L]; all S at first
+  std::vector<int> lane(S);
+  for (int s = 0; s < S; ++s) lane[s] = s;
+  int SL = S;
+  int64_t NX = (int64_t)ni * S, NY = (int64_t)mi * S;
   std::vector<double> q((size_t)kScal * S);
+  // final points of finished scenarios, unscaled, in the presolved numbering
+  std::vector<std::vector<double>> px(S), py(S);
+  std::vector<double> hx, hy;
+  // at the end the last lanes are read from hx / hy in place (end_lane)
+  std::vector<int> end_lane(S, -1);
+  auto take_points = [&](int lanes, bool at_end) -> hipError_t {
+    launch_unscale(A.slot_dev, phase, A.x_out, A.y_out, ni, mi, lanes, st);
+    hx.resize((size_t)ni * lanes);
+    hy.resize((size_t)mi * lanes);
+    hipError_t e = hipMemcpyAsync(hx.data(), A.x_out, hx.size() * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && mi) e = hipMemcpyAsync(hy.data(), A.y_out, hy.size() * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    std::vector<int> take;  // lanes whose scenario finished and has no point yet
+    for (int L = 0; L < lanes; ++L) {
+      const int s = lane[L];
+      if (done[s] != 1 || !px[s].empty()) continue;
+      if (at_end) {
+        end_lane[s] = L;
+        continue;
+      }
+      px[s].resize(ni);
+      py[s].resize(mi);
+      take.push_back(L);
+    }
+    if (take.empty()) return hipSuccess;
+    const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+    fork_join(nth, [&](int t) {  // each thread reads one range of the interleaved arrays in order
+      const int j0 = (int)((int64_t)ni * t / nth), j1 = (int)((int64_t)ni * (t + 1) / nth);
+      for (int j = j0; j < j1; ++j)
+        for (int L : take) px[lane[L]][j] = hx[(size_t)j * lanes + L];
+      const int i0 = (int)((int64_t)mi * t / nth), i1 = (int)((int64_t)mi * (t + 1) / nth);
+      for (int i = i0; i < i1; ++i)
+        for (int L : take) py[lane[L]][i] = hy[(size_t)i * lanes + L];
+    });
+    return hipSuccess;
+  };
   for (;;) {
-    for (int s = 0; s < S; ++s) {
-      SD.tau[s] = ps[s].eta / ps[s].omega;
-      SD.sigma[s] = ps[s].eta * ps[s].omega;
-      SD.k0[s] = ps[s].k_inner;
-      SD.restart[s] = 0;
-      SD.active[s] = done[s] ? 0 : 1;
+    for (int L = 0; L < SL; ++L) {
+      const int s = lane[L];
+      SD.tau[L] = ps[s].eta / ps[s].omega;
+      SD.sigma[L] = ps[s].eta * ps[s].omega;
+      SD.k0[L] = ps[s].k_inner;
+      SD.restart[L] = 0;
+      SD.active[L] = done[s] ? 0 : 1;
     }
     SCEN_HIP(hipMemcpyAsync(A.slot_dev, &SD, sizeof SD, hipMemcpyHostToDevice, st));
     for (int j = 0; j < K; ++j) {
@@ -2251,16 +2321,17 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
       launch_dual_ms(phase, check, A.slot_dev, TA, na, j, st);
     }
     launch_kkt_ms(phase, A.slot_dev, TT, nt, TA, na, A.red2, st);
-    SCEN_HIP(hipMemcpyAsync(q.data(), A.scal, q.size() * 8, hipMemcpyDeviceToHost, st));
+    SCEN_HIP(hipMemcpyAsync(q.data(), A.scal, (size_t)kScal * SL * 8, hipMemcpyDeviceToHost, st));
     SCEN_HIP(hipStreamSynchronize(st));
     SCEN_HIP(hipGetLastError());
     const double tnow = now_s();
     bool promote_ready = true, all_done = true;
-    for (int s = 0; s < S; ++s) {
+    for (int L = 0; L < SL; ++L) {
+      const int s = lane[L];
       if (done[s]) continue;
-      CheckOut out = check_core(ps[s], o, &q[(size_t)s * kScal], K, tnow, SP[s].obj_offset, SP[s].norm_b,
+      CheckOut out = check_core(ps[s], o, &q[(size_t)L * kScal], K, tnow, SP[s].obj_offset, SP[s].norm_b,
                                 SP[s].norm_c, base->cancel.load(), inf[s]);
-      SD.restart[s] = out.restart ? (o.restart_to_current ? 2 : 1) : 0;
+      SD.restart[L] = out.restart ? (o.restart_to_current ? 2 : 1) : 0;
       if (out.terminate) {
         done[s] = 1;
         status[s] = out.status;
@@ -2268,8 +2339,10 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
         done[s] = 2;  // waits, frozen, for the other scenarios of this phase
       }
     }
-    for (int s = 0; s < S; ++s) {
-      SD.active[s] = done[s] ? 0 : 1;
+    // scenarios without a lane have finished (done = 1)
+    for (int L = 0; L < SL; ++L) {
+      const int s = lane[L];
+      SD.active[L] = done[s] ? 0 : 1;
       promote_ready &= done[s] != 0;
       all_done &= done[s] == 1;
     }
@@ -2280,15 +2353,98 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
       // every scenario finished its FP32 phase: continue all waiting ones in FP64
       launch_promote_ms(A.slot_dev, NX, NY, st);
       phase = 0;
-      for (int s = 0; s < S; ++s)
-        if (done[s] == 2) done[s] = 0;
+      for (int L = 0; L < SL; ++L)
+        if (done[lane[L]] == 2) done[lane[L]] = 0;
+    }
+    int running = 0;
+    for (int L = 0; L < SL; ++L) running += done[lane[L]] == 0;
+    if (phase == 0 && running > 0 && 2 * running <= SL) {
+      // At most half the lanes still run in FP64.  The finished scenarios'
+      // points are taken now; the rest continue on arrays that hold only the
+      // scenarios still running, so a batch iteration reads those lanes only.
+      SCEN_HIP(take_points(SL, false));
+      std::vector<int> keep;
+      for (int L = 0; L < SL; ++L)
+        if (done[lane[L]] == 0) keep.push_back(L);
+      const int SC = (int)keep.size();
+      Arena dry;
+      Vecs<double> dn = SD.d;
+      double *cc = nullptr, *cl = nullptr, *cu = nullptr, *cb = nullptr;
+      void* nmem = nullptr;
+      for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+          const size_t cbytes = dry.used + 256;
+          if (hipMalloc(&nmem, cbytes) != hipSuccess) {
+            (void)hipGetLastError();
+            nmem = nullptr;
+            break;
+          }
+          dry = Arena();
+          dry.base = (char*)nmem;
+          dry.bytes = cbytes;
+        }
+        dn.x = dry.take<double>((size_t)ni * SC);
+        dn.x0 = dry.take<double>((size_t)ni * SC);
+        dn.xbar = dry.take<double>((size_t)ni * SC);
+        dn.xhat = dry.take<double>((size_t)ni * SC);
+        dn.y = dry.take<double>((size_t)mi * SC);
+        dn.y0 = dry.take<double>((size_t)mi * SC);
+        dn.yhat = dry.take<double>((size_t)mi * SC);
+        cc = dry.take<double>((size_t)ni * SC);
+        cl = dry.take<double>((size_t)ni * SC);
+        cu = dry.take<double>((size_t)ni * SC);
+        cb = dry.take<double>((size_t)mi * SC);
+      }
+      if (nmem) {
+        LaneMap mp;
+        std::memset(&mp, 0, sizeof mp);
+        mp.src_lanes = SL;
+        mp.dst_lanes = SC;
+        for (int k = 0; k < SC; ++k) mp.lane[k] = keep[k];
+        // x and y carry the Halpern state; xhat and yhat the last check's
+        // point; xbar is rewritten by the next primal half-step before use
+        launch_compact_lanes(SD.d.x, dn.x, ni, mp, st);
+        launch_compact_lanes(SD.d.x0, dn.x0, ni, mp, st);
+        launch_compact_lanes(SD.d.xhat, dn.xhat, ni, mp, st);
+        launch_compact_lanes(SD.d.c, cc, ni, mp, st);
+        launch_compact_lanes(SD.d.l, cl, ni, mp, st);
+        launch_compact_lanes(SD.d.u, cu, ni, mp, st);
+        launch_compact_lanes(SD.d.y, dn.y, mi, mp, st);
+        launch_compact_lanes(SD.d.y0, dn.y0, mi, mp, st);
+        launch_compact_lanes(SD.d.yhat, dn.yhat, mi, mp, st);
+        launch_compact_lanes(SD.d.b, cb, mi, mp, st);
+        SCEN_HIP(hipGetLastError());
+        SCEN_HIP(hipStreamSynchronize(st));  // the old arrays and slot table are released below
+        if (cmem) (void)hipFree(cmem);
+        cmem = nmem;
+        dn.c = cc;
+        dn.l = cl;
+        dn.u = cu;
+        dn.b = cb;
+        SD.d = dn;
+        SD.nscen = SC;
+        std::vector<int> nl(SC);
+        for (int k = 0; k < SC; ++k) nl[k] = lane[keep[k]];
+        lane = nl;
+        SL = SC;
+        NX = (int64_t)ni * SL;
+        NY = (int64_t)mi * SL;
+      }
     }
   }
-  launch_unscale(A.slot_dev, phase, A.x_out, A.y_out, ni, mi, S, st);
-  std::vector<double> hx((size_t)ni * S), hy((size_t)mi * S);
-  SCEN_HIP(hipMemcpyAsync(hx.data(), A.x_out, hx.size() * 8, hipMemcpyDeviceToHost, st));
-  if (mi) SCEN_HIP(hipMemcpyAsync(hy.data(), A.y_out, hy.size() * 8, hipMemcpyDeviceToHost, st));
-  SCEN_HIP(hipStreamSynchronize(st));
+  SCEN_HIP(take_points(SL, true));
+  for (int s = 0; s < S; ++s)
+    if (end_lane[s] < 0 && (px[s].size() != (size_t)ni || py[s].size() != (size_t)mi)) {
+      cleanup();
+      return fail(UC_LP_EHIP, "scenario %d: no final point was taken", s);
+    }
+  const int SE = SL;
+  auto xres = [&](int j, int s) {
+    return end_lane[s] >= 0 ? hx[(size_t)j * SE + end_lane[s]] : px[s][j];
+  };
+  auto yres = [&](int i, int s) {
+    return end_lane[s] >= 0 ? hy[(size_t)i * SE + end_lane[s]] : py[s][i];
+  };
   cleanup();
 #undef SCEN_HIP
   const double t_end = now_s();
@@ -2307,7 +2463,7 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
       for (int j = j0; j < j1; ++j) {
         const int oj = P.col_map[j];
         for (int s = 0; s < S; ++s)
-          x[(size_t)s * n + oj] = std::min(std::max(hx[(size_t)j * S + s], SP[s].l[j]), SP[s].u[j]);
+          x[(size_t)s * n + oj] = std::min(std::max(xres(j, s), SP[s].l[j]), SP[s].u[j]);
       }
       const int f0 = (int)((int64_t)n * t / nth), f1 = (int)((int64_t)n * (t + 1) / nth);
       for (int32_t j = f0; j < f1; ++j)
@@ -2325,7 +2481,7 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
       for (int i = i0; i < i1; ++i) {
         const int enc = P.row_map[i];
         for (int s = 0; s < S; ++s) {
-          const double v = hy[(size_t)i * S + s];
+          const double v = yres(i, s);
           if (enc >= 0) y[(size_t)s * m + enc] = v;
           else y[(size_t)s * m + (-enc - 1)] = -v;
         }

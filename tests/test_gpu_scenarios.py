@@ -69,6 +69,37 @@ def test_batch_equals_single_scenario_bitwise():
         assert o.rel_kkt <= 1e-7 * 1.001
 
 
+def test_fp64_tail_on_compacted_lanes_equals_single_scenario_bitwise():
+    # Cold, the sixteen load/cost scenarios of the 6,049-bus LP all hand over
+    # to FP64 near the target; most finish within 64 FP64 iterations and a
+    # few need about 2,000 more.  Once at most half the lanes still run, the
+    # batch continues on arrays that hold only those scenarios.  The lane
+    # layout does not enter any scenario's arithmetic, so a scenario of that
+    # tail, and one that finished before the compaction, equal the same
+    # scenario solved as a batch of one, bit for bit.
+    lp = make_instance("large", 0)
+    seeds = list(range(1, 17))
+    c, b, lb, ub = stack(lp, seeds)
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-4))
+    try:
+        say("case large 16 scenarios, cold")
+        x, y, infos = uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, c, b, lb, ub)
+        fp64 = [i.iters_fp64 for i in infos]
+        say("fp64 iterations", fp64)
+        assert all(i.status == uclp.UC_LP_OPTIMAL for i in infos)
+        tail = [k for k, f in enumerate(fp64) if f > 64]
+        early = [k for k, f in enumerate(fp64) if 0 < f <= 64]
+        assert tail and early and 2 * len(tail) <= len(seeds)
+        for k in (max(tail, key=lambda t: fp64[t]), early[0]):
+            say("single", k)
+            xs, ys, i1 = uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, c[k:k + 1], b[k:k + 1], lb[k:k + 1],
+                                                    ub[k:k + 1])
+            assert i1[0].iters == infos[k].iters and i1[0].iters_fp64 == infos[k].iters_fp64
+            assert np.array_equal(xs[0], x[k]) and np.array_equal(ys[0], y[k])
+    finally:
+        uclp.uc_lp_destroy(h)
+
+
 def test_warm_start_from_nominal_solution():
     lp = make_instance("tiny", 7)
     xn, yn, info = uclp.solve(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-8))
