@@ -2037,8 +2037,8 @@ struct LaneMap {
 };
 
 // dst[j * dst_lanes + k] = src[j * src_lanes + lane[k]] for j < rows.
-__global__ void k_compact_lanes(const double* __restrict__ src, double* __restrict__ dst, int64_t rows,
-                                LaneMap mp) {
+template <typename T>
+__global__ void k_compact_lanes(const T* __restrict__ src, T* __restrict__ dst, int64_t rows, LaneMap mp) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rows * mp.dst_lanes) return;
   const int64_t j = e / mp.dst_lanes;
@@ -2046,11 +2046,12 @@ __global__ void k_compact_lanes(const double* __restrict__ src, double* __restri
   dst[e] = src[j * mp.src_lanes + mp.lane[k]];
 }
 
-static void launch_compact_lanes(const double* src, double* dst, int64_t rows, const LaneMap& mp, hipStream_t s) {
+template <typename T>
+static void launch_compact_lanes(const T* src, T* dst, int64_t rows, const LaneMap& mp, hipStream_t s) {
   const int64_t total = rows * mp.dst_lanes;
   if (total <= 0) return;
   const int threads = 256;
-  k_compact_lanes<<<(unsigned)((total + threads - 1) / threads), threads, 0, s>>>(src, dst, rows, mp);
+  k_compact_lanes<T><<<(unsigned)((total + threads - 1) / threads), threads, 0, s>>>(src, dst, rows, mp);
 }
 
 struct ScenArena {
@@ -2305,6 +2306,120 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
     });
     return hipSuccess;
   };
+  // Moves the lanes `keep` of the current layout into new arrays holding
+  // only them.  In the FP32 phase the FP32 iterates and data move, the FP64
+  // data move and FP64 iterates are allocated for the hand-over; in the FP64
+  // phase the FP64 iterates and data move.  Without device memory for the
+  // new arrays the batch simply keeps its layout.
+  bool no_compact = false;  // set when the device had no memory for it
+  auto compact = [&](const std::vector<int>& keep) -> hipError_t {
+    const int SC = (int)keep.size();
+    const bool fp32 = phase == 1;
+    Arena ar;
+    Vecs<float> fn = SD.f;
+    Vecs<double> dn = SD.d;
+    float *fc = nullptr, *fl = nullptr, *fu = nullptr, *fb = nullptr;
+    double *dc_ = nullptr, *dl = nullptr, *du = nullptr, *db = nullptr;
+    void* nmem = nullptr;
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1) {
+        const size_t cbytes = ar.used + 256;
+        if (hipMalloc(&nmem, cbytes) != hipSuccess) {
+          (void)hipGetLastError();
+          no_compact = true;
+          return hipSuccess;
+        }
+        ar = Arena();
+        ar.base = (char*)nmem;
+        ar.bytes = cbytes;
+      }
+      dn.x = ar.take<double>((size_t)ni * SC);
+      dn.x0 = ar.take<double>((size_t)ni * SC);
+      dn.xbar = ar.take<double>((size_t)ni * SC);
+      dn.xhat = ar.take<double>((size_t)ni * SC);
+      dn.y = ar.take<double>((size_t)mi * SC);
+      dn.y0 = ar.take<double>((size_t)mi * SC);
+      dn.yhat = ar.take<double>((size_t)mi * SC);
+      dc_ = ar.take<double>((size_t)ni * SC);
+      dl = ar.take<double>((size_t)ni * SC);
+      du = ar.take<double>((size_t)ni * SC);
+      db = ar.take<double>((size_t)mi * SC);
+      if (fp32) {
+        fn.x = ar.take<float>((size_t)ni * SC);
+        fn.x0 = ar.take<float>((size_t)ni * SC);
+        fn.xbar = ar.take<float>((size_t)ni * SC);
+        fn.xhat = ar.take<float>((size_t)ni * SC);
+        fn.y = ar.take<float>((size_t)mi * SC);
+        fn.y0 = ar.take<float>((size_t)mi * SC);
+        fn.yhat = ar.take<float>((size_t)mi * SC);
+        fc = ar.take<float>((size_t)ni * SC);
+        fl = ar.take<float>((size_t)ni * SC);
+        fu = ar.take<float>((size_t)ni * SC);
+        fb = ar.take<float>((size_t)mi * SC);
+      }
+    }
+    LaneMap mp;
+    std::memset(&mp, 0, sizeof mp);
+    mp.src_lanes = SL;
+    mp.dst_lanes = SC;
+    for (int k = 0; k < SC; ++k) mp.lane[k] = keep[k];
+    // x and y carry the Halpern state; xhat and yhat the last check's point;
+    // xbar is rewritten by the next primal half-step before it is read
+    if (fp32) {
+      launch_compact_lanes(SD.f.x, fn.x, ni, mp, st);
+      launch_compact_lanes(SD.f.x0, fn.x0, ni, mp, st);
+      launch_compact_lanes(SD.f.xhat, fn.xhat, ni, mp, st);
+      launch_compact_lanes(SD.f.c, fc, ni, mp, st);
+      launch_compact_lanes(SD.f.l, fl, ni, mp, st);
+      launch_compact_lanes(SD.f.u, fu, ni, mp, st);
+      launch_compact_lanes(SD.f.y, fn.y, mi, mp, st);
+      launch_compact_lanes(SD.f.y0, fn.y0, mi, mp, st);
+      launch_compact_lanes(SD.f.yhat, fn.yhat, mi, mp, st);
+      launch_compact_lanes(SD.f.b, fb, mi, mp, st);
+    } else {
+      launch_compact_lanes(SD.d.x, dn.x, ni, mp, st);
+      launch_compact_lanes(SD.d.x0, dn.x0, ni, mp, st);
+      launch_compact_lanes(SD.d.xhat, dn.xhat, ni, mp, st);
+      launch_compact_lanes(SD.d.y, dn.y, mi, mp, st);
+      launch_compact_lanes(SD.d.y0, dn.y0, mi, mp, st);
+      launch_compact_lanes(SD.d.yhat, dn.yhat, mi, mp, st);
+    }
+    launch_compact_lanes(SD.d.c, dc_, ni, mp, st);
+    launch_compact_lanes(SD.d.l, dl, ni, mp, st);
+    launch_compact_lanes(SD.d.u, du, ni, mp, st);
+    launch_compact_lanes(SD.d.b, db, mi, mp, st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the old arrays and slot table are released below
+    if (e != hipSuccess) {
+      (void)hipFree(nmem);
+      return e;
+    }
+    if (cmem) (void)hipFree(cmem);
+    cmem = nmem;
+    dn.c = dc_;
+    dn.l = dl;
+    dn.u = du;
+    dn.b = db;
+    if (fp32) {
+      fn.c = fc;
+      fn.l = fl;
+      fn.u = fu;
+      fn.b = fb;
+    } else {  // the FP32 arrays are not read again
+      fn.x = fn.x0 = fn.xbar = fn.xhat = fn.y = fn.y0 = fn.yhat = nullptr;
+      fn.c = fn.l = fn.u = fn.b = nullptr;
+    }
+    SD.f = fn;
+    SD.d = dn;
+    SD.nscen = SC;
+    std::vector<int> nl(SC);
+    for (int k = 0; k < SC; ++k) nl[k] = lane[keep[k]];
+    lane = nl;
+    SL = SC;
+    NX = (int64_t)ni * SL;
+    NY = (int64_t)mi * SL;
+    return hipSuccess;
+  };
   for (;;) {
     for (int L = 0; L < SL; ++L) {
       const int s = lane[L];
@@ -2356,80 +2471,16 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
       for (int L = 0; L < SL; ++L)
         if (done[lane[L]] == 2) done[lane[L]] = 0;
     }
-    int running = 0;
-    for (int L = 0; L < SL; ++L) running += done[lane[L]] == 0;
-    if (phase == 0 && running > 0 && 2 * running <= SL) {
-      // At most half the lanes still run in FP64.  The finished scenarios'
-      // points are taken now; the rest continue on arrays that hold only the
-      // scenarios still running, so a batch iteration reads those lanes only.
+    // Once at most half the lanes hold a scenario that has not finished
+    // (running, or waiting for the FP64 hand-over), the finished scenarios'
+    // points are taken and the others continue on arrays that hold only
+    // their lanes, so a batch iteration reads those lanes only.
+    std::vector<int> keep;
+    for (int L = 0; L < SL; ++L)
+      if (done[lane[L]] != 1) keep.push_back(L);
+    if (!no_compact && !keep.empty() && 2 * (int)keep.size() <= SL) {
       SCEN_HIP(take_points(SL, false));
-      std::vector<int> keep;
-      for (int L = 0; L < SL; ++L)
-        if (done[lane[L]] == 0) keep.push_back(L);
-      const int SC = (int)keep.size();
-      Arena dry;
-      Vecs<double> dn = SD.d;
-      double *cc = nullptr, *cl = nullptr, *cu = nullptr, *cb = nullptr;
-      void* nmem = nullptr;
-      for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1) {
-          const size_t cbytes = dry.used + 256;
-          if (hipMalloc(&nmem, cbytes) != hipSuccess) {
-            (void)hipGetLastError();
-            nmem = nullptr;
-            break;
-          }
-          dry = Arena();
-          dry.base = (char*)nmem;
-          dry.bytes = cbytes;
-        }
-        dn.x = dry.take<double>((size_t)ni * SC);
-        dn.x0 = dry.take<double>((size_t)ni * SC);
-        dn.xbar = dry.take<double>((size_t)ni * SC);
-        dn.xhat = dry.take<double>((size_t)ni * SC);
-        dn.y = dry.take<double>((size_t)mi * SC);
-        dn.y0 = dry.take<double>((size_t)mi * SC);
-        dn.yhat = dry.take<double>((size_t)mi * SC);
-        cc = dry.take<double>((size_t)ni * SC);
-        cl = dry.take<double>((size_t)ni * SC);
-        cu = dry.take<double>((size_t)ni * SC);
-        cb = dry.take<double>((size_t)mi * SC);
-      }
-      if (nmem) {
-        LaneMap mp;
-        std::memset(&mp, 0, sizeof mp);
-        mp.src_lanes = SL;
-        mp.dst_lanes = SC;
-        for (int k = 0; k < SC; ++k) mp.lane[k] = keep[k];
-        // x and y carry the Halpern state; xhat and yhat the last check's
-        // point; xbar is rewritten by the next primal half-step before use
-        launch_compact_lanes(SD.d.x, dn.x, ni, mp, st);
-        launch_compact_lanes(SD.d.x0, dn.x0, ni, mp, st);
-        launch_compact_lanes(SD.d.xhat, dn.xhat, ni, mp, st);
-        launch_compact_lanes(SD.d.c, cc, ni, mp, st);
-        launch_compact_lanes(SD.d.l, cl, ni, mp, st);
-        launch_compact_lanes(SD.d.u, cu, ni, mp, st);
-        launch_compact_lanes(SD.d.y, dn.y, mi, mp, st);
-        launch_compact_lanes(SD.d.y0, dn.y0, mi, mp, st);
-        launch_compact_lanes(SD.d.yhat, dn.yhat, mi, mp, st);
-        launch_compact_lanes(SD.d.b, cb, mi, mp, st);
-        SCEN_HIP(hipGetLastError());
-        SCEN_HIP(hipStreamSynchronize(st));  // the old arrays and slot table are released below
-        if (cmem) (void)hipFree(cmem);
-        cmem = nmem;
-        dn.c = cc;
-        dn.l = cl;
-        dn.u = cu;
-        dn.b = cb;
-        SD.d = dn;
-        SD.nscen = SC;
-        std::vector<int> nl(SC);
-        for (int k = 0; k < SC; ++k) nl[k] = lane[keep[k]];
-        lane = nl;
-        SL = SC;
-        NX = (int64_t)ni * SL;
-        NY = (int64_t)mi * SL;
-      }
+      SCEN_HIP(compact(keep));
     }
   }
   SCEN_HIP(take_points(SL, true));
