@@ -254,7 +254,14 @@ const char* uc_lp_last_error(void);
  * half-step serves every scenario.  x0[n], y0[m] (may be NULL) warm-start all
  * scenarios from one point.  Blocks until all scenarios stop.  Solutions are
  * written to x[n_scen*n], y[n_scen*m] and per-scenario results to
- * info[n_scen].  n_scen in 1..16.  ENOTSUP for other counts. */
+ * info[n_scen].  n_scen in 1..16.  ENOTSUP for other counts.
+ * Device memory: the call allocates the scenarios' interleaved vectors for
+ * its duration (info[].device_bytes; ENOMEM if that fails).  Once at most
+ * half the scenarios are still unfinished it moves them to a smaller set of
+ * arrays holding only their lanes, allocated and released inside the call;
+ * without memory for that set it keeps the full layout.  Host threads: one
+ * per scenario for validation and presolve, up to 16 for unpacking the
+ * results.  uc_lp_cancel(base) from another thread stops the batch. */
 int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* c,
                           const double* b, const double* lb, const double* ub,
                           const double* x0, const double* y0, double* x,
