@@ -192,8 +192,15 @@ def halpern_update(z, z_hat, z_anchor, k, gamma=1.0):
 
 
 def fixed_point_residual(A, x, y, x_hat, y_hat, tau, sigma):
-    """||z - T(z)||_P with P = [[I/tau, -A'], [-A, I/sigma]]."""
+    """||z - T(z)||_P with P = [[I/tau, A'], [A, I/sigma]].
+
+    P is the metric in which the step of pdhg_step is a proximal-point step
+    for the Lagrangian c'x - y'(Ax - b): writing the optimality conditions of
+    the two projections as 0 in F(z+) + P (z+ - z), with F the (monotone)
+    saddle operator, gives the off-diagonal blocks +A' and +A (the primal
+    step uses the old y, the dual step the extrapolated 2 x_hat - x).  T is
+    firmly nonexpansive in this norm when tau sigma ||A||_2^2 < 1."""
     dx = x_hat - x
     dy = y_hat - y
-    q = dx @ dx / tau + dy @ dy / sigma - 2.0 * dy @ (A @ dx)
+    q = dx @ dx / tau + dy @ dy / sigma + 2.0 * dy @ (A @ dx)
     return math.sqrt(max(q, 0.0))

@@ -266,6 +266,67 @@ def test_kkt_hand_values_inequality_and_free():
     assert k.rel_kkt == 0.0
 
 
+def test_bound_multiplier_one_sided_hand_values():
+    from oracle.kkt import bound_multiplier
+    d = np.array([-1.0, 2.0, -3.0, 4.0, 5.0, -6.0, 7.0])
+    lb = np.array([0.0, 0.0, -np.inf, -np.inf, -np.inf, 1.0, 1.0])
+    ub = np.array([np.inf, np.inf, 5.0, 5.0, np.inf, 2.0, 2.0])
+    # only lb finite: max(d, 0); only ub finite: min(d, 0); free: 0; boxed: d
+    assert list(bound_multiplier(d, lb, ub)) == [0.0, 2.0, -3.0, 0.0, 0.0, -6.0, 7.0]
+
+
+def test_kkt_hand_values_one_sided_bounds():
+    # min -x1 + x2  s.t.  x1 + x2 = 1,  x1 <= 2 (no lower bound),  x2 >= 0 (no upper
+    # bound): optimum x = (1, 0), objective -1, y = -1, reduced costs d = (0, 2)
+    lp = dense_lp([[1.0, 1.0]], [1.0], "E", [-1.0, 1.0], [-np.inf, 0.0], [2.0, np.inf])
+    k = kkt(lp, [1.0, 0.0], [-1.0])
+    assert k.rel_kkt == 0.0 and k.pobj == -1.0 and k.dobj == -1.0
+    # y = 0: d = (-1, 1); x1 has only an upper bound, so lam1 = min(-1, 0) = -1
+    # enters the dual objective as ub1 * lam1 = -2; x2's lam2 = 1 adds lb2 * 1 = 0
+    k = kkt(lp, [1.0, 0.0], [0.0])
+    assert k.rho_d == 0.0 and k.dobj == -2.0
+    assert math.isclose(k.rel_gap, 1.0 / 4.0)
+    # y = -2: d = (1, 3); lam1 = min(1, 0) = 0 leaves a dual residual of 1
+    k = kkt(lp, [1.0, 0.0], [-2.0])
+    assert k.rho_d == 1.0 and k.dobj == -2.0
+    assert math.isclose(k.rel_d, 1.0 / (1.0 + math.sqrt(2.0)))
+
+
+def one_sided_uc(seed, periods=4):
+    """A small UC grid whose line flows lose one of their limits (lower or
+    upper, alternating over the lines) and whose units lose the lower bound
+    0 of their output (the rows p - Pmin u >= 0 keep p >= 0)."""
+    lp = make_instance("tiny", seed, n_periods=periods)
+    lb, ub = lp.lb.copy(), lp.ub.copy()
+    off, nt, L, G = lp.meta["col_off"], lp.meta["ncol_t"], lp.meta["L"], lp.meta["G"]
+    for t in range(lp.meta["T"]):
+        f0 = t * nt + off["f"]
+        ub[f0:f0 + L:2] = np.inf
+        lb[f0 + 1:f0 + L:2] = -np.inf
+        p0 = t * nt + off["p"]
+        lb[p0:p0 + G] = -np.inf
+    return lp.with_data(lb=lb, ub=ub)
+
+
+def test_simplex_on_one_sided_columns_agrees_with_highs():
+    # columns bounded on one side only are negated or kept by the simplex's
+    # set-up; HiGHS (a separate library) must find the same optimum, and the
+    # KKT evaluator's one-sided branches must certify the simplex point
+    lp = one_sided_uc(3)
+    res = simplex_solve(lp)
+    assert res.status == "optimal"
+    st, obj, x, y, _ = highs_solve(lp, "highs-ds")
+    assert st == 0
+    assert abs(res.obj - obj) <= 1e-9 * (1 + abs(obj))
+    k = kkt(lp, res.x, res.y)
+    assert k.rel_kkt <= 1e-9
+    lbo, ubo = np.isfinite(lp.lb) & ~np.isfinite(lp.ub), np.isfinite(lp.ub) & ~np.isfinite(lp.lb)
+    assert lbo.sum() > 0 and ubo.sum() > 0
+    # relaxing limits cannot raise the optimum
+    base = simplex_solve(make_instance("tiny", 3, n_periods=4))
+    assert res.obj <= base.obj + 1e-9 * abs(base.obj)
+
+
 def test_kkt_detects_flipped_dual_sign():
     lp = make_instance("tiny", 1, n_periods=3)
     res = simplex_solve(lp)
@@ -417,6 +478,57 @@ def test_internal_problem_maps_and_offsets():
     assert np.allclose(ip.matrix().toarray(), [[3, 1], [1, 0], [-1, -1]])
 
 
+def p_norm(A, ux, uy, tau, sigma):
+    """||(ux, uy)||_P through the oracle's residual with z = 0, T(z) = u."""
+    return ps.fixed_point_residual(A, np.zeros_like(ux), np.zeros_like(uy), ux, uy, tau, sigma)
+
+
+def test_fixed_point_residual_hand_values_with_cross_term():
+    # A = [[2]], dz = (1, 3), tau = 1/2, sigma = 1/4:
+    # 1/0.5 + 9/0.25 + 2 * 3 * (2 * 1) = 2 + 36 + 12 = 50
+    A = sp.csr_matrix(np.array([[2.0]]))
+    assert math.isclose(p_norm(A, np.array([1.0]), np.array([3.0]), 0.5, 0.25), math.sqrt(50.0))
+    # A = [[1, 0, 2], [0, -1, 1]], dx = (1, 2, -1), dy = (0.5, -1): A dx = (-1, -3),
+    # dy'A dx = 2.5; tau = 2, sigma = 1/2: 6/2 + 1.25/0.5 + 2 * 2.5 = 10.5
+    A = sp.csr_matrix(np.array([[1.0, 0.0, 2.0], [0.0, -1.0, 1.0]]))
+    r = ps.fixed_point_residual(A, np.array([1.0, 1.0, 1.0]), np.array([0.0, 1.0]),
+                                np.array([2.0, 3.0, 0.0]), np.array([0.5, 0.0]), 2.0, 0.5)
+    assert math.isclose(r, math.sqrt(10.5))
+
+
+def firm_nonexpansiveness_excess(residual, trials=200, seed=0):
+    """Largest relative excess of ||Tz - Tz'||^2 + ||(I-T)z - (I-T)z'||^2 over
+    ||z - z'||^2 in the norm `residual` measures, over random small LPs, step
+    pairs with tau sigma ||A||^2 < 1, and point pairs."""
+    rng = np.random.default_rng(seed)
+    worst = -np.inf
+    for _ in range(trials):
+        m, n, meq = 4, 5, 2
+        A = sp.csr_matrix(rng.normal(size=(m, n)))
+        nrm = np.linalg.svd(A.toarray(), compute_uv=False)[0]
+        tau = 0.9 / nrm * rng.uniform(0.3, 3.0)
+        sigma = 0.9 / (nrm * nrm * tau)
+        c, b = rng.normal(size=n), rng.normal(size=m)
+        l, u = -rng.uniform(0, 1, n), rng.uniform(0, 1, n)
+        z = [(rng.normal(size=n), rng.normal(size=m)) for _ in range(2)]
+        T = [ps.pdhg_step(A, c, b, l, u, meq, x, y, tau, sigma) for x, y in z]
+
+        def nsq(ux, uy):
+            return residual(A, np.zeros(n), np.zeros(m), ux, uy, tau, sigma) ** 2
+
+        lhs = nsq(T[0][0] - T[1][0], T[0][1] - T[1][1]) + \
+            nsq((z[0][0] - T[0][0]) - (z[1][0] - T[1][0]), (z[0][1] - T[0][1]) - (z[1][1] - T[1][1]))
+        rhs = nsq(z[0][0] - z[1][0], z[0][1] - z[1][1])
+        worst = max(worst, (lhs - rhs) / rhs)
+    return worst
+
+
+def test_fixed_point_residual_is_the_metric_of_the_step():
+    # the PDHG step is a proximal-point step, hence firmly nonexpansive, in the
+    # metric the residual measures; the restart test relies on that
+    assert firm_nonexpansiveness_excess(ps.fixed_point_residual) <= 1e-12
+
+
 # ---------------------------------------------------------------------------
 # planted mistakes in the oracle are caught by the pins above
 # ---------------------------------------------------------------------------
@@ -439,3 +551,17 @@ def test_planted_step_mistakes_break_the_fixed_point():
     assert np.max(np.abs(xh - x)) <= 1e-8 * (1 + np.max(np.abs(x)))
     xh, yh = wrong_sign(x, y, 0.3, 2.0)
     assert np.max(np.abs(xh - x)) > 1e-3
+
+
+def test_planted_sign_of_the_residual_cross_term_is_caught():
+    # the residual with the cross term's sign flipped is still a norm (for
+    # tau sigma ||A||^2 < 1) but the step is not nonexpansive in it, and the
+    # hand values differ
+    def flipped(A, x, y, x_hat, y_hat, tau, sigma):
+        dx, dy = x_hat - x, y_hat - y
+        return math.sqrt(max(dx @ dx / tau + dy @ dy / sigma - 2.0 * dy @ (A @ dx), 0.0))
+
+    assert firm_nonexpansiveness_excess(flipped) > 1e-2
+    A = sp.csr_matrix(np.array([[2.0]]))
+    assert not math.isclose(flipped(A, np.zeros(1), np.zeros(1), np.ones(1), np.full(1, 3.0), 0.5, 0.25),
+                            math.sqrt(50.0))
