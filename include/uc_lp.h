@@ -94,7 +94,8 @@ typedef struct {
                             The paper's PDHG runs set 1e-5 (Sec. II-D).        */
   double eps_polish;     /* relative KKT target of the FP64 polish, 1e-8       */
   double time_limit_s;   /* wall-clock limit of one solve, default 3600        */
-  double step_scale;     /* eta = step_scale / ||A_hat||_2, default 0.99       */
+  double step_scale;     /* eta = step_scale / (upper bound on ||A_hat||_2),
+                            default 0.99                                      */
   int32_t spmv_algo;     /* uc_lp_spmv_algo; the PDHG half-steps support
                             UC_LP_SPMV_ROWSPLIT only (ENOTSUP otherwise)       */
   int32_t verbose;       /* 0 = silent, 1 = one line per check on stderr       */
@@ -137,6 +138,21 @@ typedef struct {
                             UC_LP_FP32_MIXED_POLISH; default 0 (toward 1e-8
                             the term did not pay: the 64-LP serving stream took
                             8.21M iterations without it, 8.91M with 0.5)      */
+  double eps_gap_rel;    /* UC_LP_FP64 and UC_LP_FP32_MIXED: OPTIMAL also needs
+                            the relative duality gap |pobj - dobj| /
+                            (1 + |pobj| + |dobj|), accumulated in FP64, to be
+                            <= this; the solve continues past the eps_rel
+                            milestone (t_to_eps_s) until the gap closes.  In
+                            the FP32 phase a gap that stops improving
+                            (fp32_stall_checks checks without a 10% gain)
+                            continues in FP64.  A closed gap does not bound
+                            the objective error while the primal residual is
+                            still at the eps_rel level (on the 6,049-bus
+                            benchmark LP a gap of 8.7e-8 left the objective
+                            3e-6 away from the optimum at a primal residual of
+                            2e-5); UC_LP_FP32_MIXED_POLISH with a smaller
+                            eps_polish does.  Default 0 = off.  Ignored by
+                            UC_LP_FP32_MIXED_POLISH.                          */
 } uc_lp_opts;
 
 typedef struct {
@@ -157,7 +173,8 @@ typedef struct {
   double pobj_at_eps;      /* primal objective at the eps_rel milestone       */
   double rel_kkt_at_eps;
   int64_t iters_at_eps;    /* iterations at the eps_rel milestone             */
-  double norm_a_est;       /* power-iteration estimate of ||A_hat||_2         */
+  double norm_a_est;       /* power-iteration estimate ||B v||^(1/2) of
+                              ||A_hat||_2 (from below; see norm_a_bound)       */
   double omega;            /* current primal weight                           */
   double primal_kernel_us; /* mean duration of timed primal half-step kernels
                               (the FP32 ones when the solve had an FP32 phase) */
@@ -173,6 +190,16 @@ typedef struct {
                               (c, l, u skipped where a row block holds one
                               known value)                                     */
   double dual_bytes;       /* the same for one dual half-step launch           */
+  double rel_gap_at_eps;   /* relative duality gap at the eps_rel milestone    */
+  double fp_residual;      /* fixed-point residual ||z - T(z)||_P of the last
+                              check, in the scaled space, with P the metric of
+                              the PDHG step [[I/tau, A_hat'], [A_hat, I/sigma]]
+                              (the quantity the adaptive restarts compare)     */
+  double norm_a_bound;     /* upper bound on ||A_hat||_2 that sets the step:
+                              1, the bound the Pock-Chambolle scaling (alpha
+                              = 1) guarantees; norm_a_est shows its tightness */
+  double eta;              /* step: tau = eta / omega, sigma = eta * omega,
+                              eta = step_scale / norm_a_bound                 */
 } uc_lp_info;
 
 /* Fill *opts with the defaults listed in uc_lp_opts. */
@@ -304,6 +331,29 @@ int uc_lp_debug_step(uc_lp* lp, int32_t precision, const double* x, const double
                      double sigma, double* x_hat, double* y_hat, double* x_next,
                      double* y_next);
 
+/* `iters` consecutive PDHG iterations on the scaled internal problem, run
+ * by the same launches as one check interval of a solve: iterations
+ * 0 .. iters-2 are the solve's non-check half-steps (the Halpern step taken
+ * inside the kernels; with halpern_gamma = 1 the primal iterate is rebuilt
+ * from x_bar and the anchor instead of stored), iteration iters-1 is a
+ * check: x_hat, y_hat = T(z) are stored, the FP64 KKT kernels run on them,
+ * and the finish kernel takes the last Halpern step (no restart).
+ * Starting point z = (x, y) at inner index k with anchor (x0, y0).
+ * Outputs: x_hat, y_hat = T(z) of the last iteration, x_next, y_next the
+ * iterate after all `iters` steps, *fp_residual = ||z - T(z)||_P of the last
+ * iteration from the check kernels' FP64 scalars (P as in
+ * uc_lp_info.fp_residual, with the given tau, sigma).
+ * block_threads: workgroup size of the half-steps, 0 = the solve's own
+ * choice for this launch size, 256 or 512 to force one (the two give the
+ * same bits).  iters in 1..4096.  precision UC_LP_FP64 or UC_LP_FP32_MIXED
+ * (FP32 rounds the inputs and widens the outputs).  All vectors are FP64
+ * host arrays of internal length; fp_residual may be NULL.
+ * uc_lp_debug_step is this call with iters = 1. */
+int uc_lp_debug_iterate(uc_lp* lp, int32_t precision, int32_t iters, int32_t block_threads,
+                        const double* x, const double* y, const double* x0, const double* y0,
+                        int64_t k, double tau, double sigma, double* x_hat, double* y_hat,
+                        double* x_next, double* y_next, double* fp_residual);
+
 /* KKT quantities of an ORIGINAL-space pair (x[n], y[m]), evaluated by the
  * solver's own FP64 check kernels.  Fills pobj, dobj, rel_* and
  * abs_primal_inf of *out (other fields zero). */
@@ -324,6 +374,23 @@ int uc_spmv(int device, int32_t m, int32_t n, int64_t nnz, const int32_t* row_pt
 int uc_spmv_bench(int device, int32_t m, int32_t n, int64_t nnz, const int32_t* row_ptr,
                   const int32_t* col_idx, const double* val, int32_t precision,
                   int32_t algo, int32_t copies, int32_t reps, double* us_per_spmv);
+
+/* Time the solve's own half-step kernels (the non-check launches of the
+ * given precision, UC_LP_FP64 or UC_LP_FP32_MIXED) on `copies` device copies
+ * of this instance (matrix, scaled data and iterates), launched round-robin
+ * so that consecutive launches read different copies and, with enough
+ * copies, the working set exceeds the last-level cache.  `reps` iterations
+ * (one primal and one dual launch each, every launch timed by start/stop
+ * events attached to its dispatch).  Writes the mean duration of one primal
+ * and of one dual launch in microseconds, and their algorithmic bytes (the
+ * model of uc_lp_info.primal_bytes / dual_bytes; either pointer may be NULL).
+ * copies 1..64, reps 1..4096.  Needs a handle created with eng == NULL that
+ * is not running; allocates the copies for the duration of the call (ENOMEM
+ * if they do not fit).  The handle's iterates are reset as at a cold start
+ * (a later uc_lp_solve starts from its own initial point anyway). */
+int uc_lp_bench_half_steps(uc_lp* lp, int32_t precision, int32_t copies, int32_t reps,
+                           double* primal_us, double* dual_us, double* primal_bytes,
+                           double* dual_bytes);
 
 /* Device stream-copy bandwidth in GB/s for `bytes` per buffer (calibration
  * of the roofline and of hardware traffic counters). */

@@ -1340,72 +1340,149 @@ __global__ __launch_bounds__(kThreads) void k_spmv(const int* __restrict__ ptr, 
 
 // ---- merge-path SpMV (Merrill & Garland, SC'16) -----------------------------
 // The merge of the row-end list (row_ptr[1..m]) with the entry indices
-// 0..nnz-1 has m + nnz steps; each thread takes kMergeItems consecutive
-// steps.  A thread's first coordinate comes from a binary search along its
-// diagonal.  Rows finished inside a thread are written directly; the partial
-// sum of the row still open at the end of a thread is a carry, added by a
-// second kernel in thread order (deterministic).
+// 0..nnz-1 has m + nnz items; workgroup g takes items [g T, (g + 1) T) with
+// T = kMergeTile.  A small kernel finds every workgroup's start coordinate
+// (rows consumed, entries consumed) by a binary search along its diagonal.
+// A workgroup then stages its rows' ends and its entries' products in LDS
+// with coalesced loads, and each thread walks kMergeItems items of the
+// staged merge: a row end emits the row's sum, an entry adds its product.
+// A row that spans threads is completed by a segmented scan over the
+// threads' carries (in a fixed order); a row that spans workgroups gets the
+// carries of the earlier workgroups added, in workgroup order, by a fix-up
+// kernel.  Every sum is formed in an order fixed by the matrix alone.
 constexpr int kMergeItems = 8;
+constexpr int kMergeTile = kThreads * kMergeItems;
 
-__device__ inline void merge_search(int diag, const int* __restrict__ row_end, int m, int64_t nnz,
+__device__ inline void merge_search(int64_t diag, const int* __restrict__ row_end, int m, int64_t nnz,
                                     int& row, int& k) {
-  int lo = diag - (int)nnz > 0 ? diag - (int)nnz : 0;
-  int hi = diag < m ? diag : m;
+  int lo = (int)max(diag - nnz, (int64_t)0);
+  int hi = (int)min(diag, (int64_t)m);
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     // consume a row end before entry (diag - mid - 1) when row_end[mid] <= that entry
-    if (row_end[mid] <= diag - mid - 1) lo = mid + 1;
+    if ((int64_t)row_end[mid] <= diag - mid - 1) lo = mid + 1;
     else hi = mid;
   }
   row = lo;
-  k = diag - lo;
+  k = (int)(diag - lo);
+}
+
+__global__ void k_merge_coords(const int* __restrict__ ptr, int m, int64_t nnz, int nwg, int2* __restrict__ coord) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g > nwg) return;
+  const int64_t d = min((int64_t)g * kMergeTile, (int64_t)m + nnz);
+  int row, k;
+  merge_search(d, ptr + 1, m, nnz, row, k);
+  coord[g] = make_int2(row, k);
 }
 
 template <typename V>
-__global__ __launch_bounds__(kThreads) void k_spmv_merge(const int* __restrict__ ptr,
-                                                         const int* __restrict__ col,
-                                                         const V* __restrict__ val,
-                                                         const V* __restrict__ x, V* __restrict__ y,
-                                                         int m, int64_t nnz, int nthreads,
-                                                         int* __restrict__ carry_row,
-                                                         V* __restrict__ carry_val) {
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= nthreads) return;
-  const int64_t total = (int64_t)m + nnz;
-  const int d0 = (int)min((int64_t)tid * kMergeItems, total);
-  const int d1 = (int)min((int64_t)(tid + 1) * kMergeItems, total);
-  const int* row_end = ptr + 1;
-  int row, k, row1, k1;
-  merge_search(d0, row_end, m, nnz, row, k);
-  merge_search(d1, row_end, m, nnz, row1, k1);
-  V sum = 0;
-  for (; row < row1; ++row) {
-    const int e = row_end[row];
-    for (; k < e; ++k) sum += val[k] * x[col[k]];
-    y[row] = sum;
-    sum = 0;
+__global__ __launch_bounds__(kThreads) void k_spmv_merge(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                         const V* __restrict__ val, const V* __restrict__ x,
+                                                         V* __restrict__ y, const int2* __restrict__ coord,
+                                                         int* __restrict__ carry_row, V* __restrict__ carry_val) {
+  __shared__ int s_end[kMergeTile];
+  __shared__ V s_prod[kMergeTile];
+  __shared__ int s_crow[kThreads];
+  __shared__ V s_cval[kThreads];
+  const int g = blockIdx.x;
+  const int t = threadIdx.x;
+  const int2 c0 = coord[g], c1 = coord[g + 1];
+  const int row0 = c0.x, k0 = c0.y;
+  const int nrows = c1.x - c0.x;  // row ends this workgroup consumes
+  const int nk = c1.y - c0.y;     // entries it consumes
+  // staging: straight-line loads (items past the end re-read the last one)
+  if (nrows > 0) {
+    int e[kMergeItems];
+#pragma unroll
+    for (int u = 0; u < kMergeItems; ++u) e[u] = ptr[row0 + 1 + min(t + u * kThreads, nrows - 1)];
+#pragma unroll
+    for (int u = 0; u < kMergeItems; ++u)
+      if (t + u * kThreads < nrows) s_end[t + u * kThreads] = e[u];
   }
-  for (; k < k1; ++k) sum += val[k] * x[col[k]];
-  carry_row[tid] = row1 < m ? row1 : -1;
-  carry_val[tid] = sum;
+  if (nk > 0) {
+    int cc[kMergeItems];
+    V vv[kMergeItems], xx[kMergeItems];
+#pragma unroll
+    for (int u = 0; u < kMergeItems; ++u) {
+      const int kk = k0 + min(t + u * kThreads, nk - 1);
+      cc[u] = col[kk];
+      vv[u] = val[kk];
+    }
+#pragma unroll
+    for (int u = 0; u < kMergeItems; ++u) xx[u] = x[cc[u]];
+#pragma unroll
+    for (int u = 0; u < kMergeItems; ++u)
+      if (t + u * kThreads < nk) s_prod[t + u * kThreads] = vv[u] * xx[u];
+  }
+  __syncthreads();
+  // this thread's items [d0, d1) of the workgroup's merge, located by a
+  // binary search in LDS
+  const int total = nrows + nk;
+  const int d0 = min(t * kMergeItems, total), d1 = min(d0 + kMergeItems, total);
+  int lo = max(d0 - nk, 0), hi = min(d0, nrows);
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (s_end[mid] - k0 <= d0 - mid - 1) lo = mid + 1;
+    else hi = mid;
+  }
+  int r = lo, k = d0 - lo;
+  V sum = 0, first_val = 0;
+  int first_row = -1;
+  for (int it = d0; it < d1; ++it) {
+    if (r < nrows && s_end[r] - k0 <= k) {
+      if (first_row < 0) {
+        first_row = row0 + r;  // completed after the scan (carry-in from earlier threads)
+        first_val = sum;
+      } else {
+        y[row0 + r] = sum;
+      }
+      sum = 0;
+      ++r;
+    } else {
+      sum += s_prod[k];
+      ++k;
+    }
+  }
+  // carry-out: the row open at the end of this thread's items
+  const int crow = row0 + r;
+  s_crow[t] = crow;
+  s_cval[t] = sum;
+  __syncthreads();
+  // inclusive segmented scan of the carries over the threads; rows are
+  // non-decreasing across threads, so equal rows form contiguous runs
+  for (int o = 1; o < kThreads; o <<= 1) {
+    V add = 0;
+    if (t >= o && s_crow[t - o] == crow) add = s_cval[t - o];
+    __syncthreads();
+    s_cval[t] += add;
+    __syncthreads();
+  }
+  if (first_row >= 0) {
+    const V cin = (t > 0 && s_crow[t - 1] == first_row) ? s_cval[t - 1] : (V)0;
+    y[first_row] = cin + first_val;
+  }
+  if (t == kThreads - 1) {
+    carry_row[g] = crow;
+    carry_val[g] = s_cval[t];
+  }
 }
 
-// A row may collect carries from several consecutive threads and its final
-// piece from the thread where it ends (already written to y).  Thread t adds
-// its carry only if it is the first of its row's run, summing the whole run.
+// Rows open at the end of a workgroup collect that workgroup's carry, and
+// possibly those of the next ones, and are completed (written to y) by a
+// later workgroup.  Carry g adds its whole run of equal rows, in workgroup
+// order, if it is the first of that run.
 template <typename V>
-__global__ void k_merge_fixup(const int* __restrict__ carry_row, const V* __restrict__ carry_val,
-                              int nthreads, V* __restrict__ y, const int* __restrict__ ptr) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nthreads) return;
-  const int r = carry_row[t];
-  if (r < 0) return;
-  if (t > 0 && carry_row[t - 1] == r) return;
+__global__ void k_merge_fixup(const int* __restrict__ carry_row, const V* __restrict__ carry_val, int nwg, int m,
+                              V* __restrict__ y) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nwg) return;
+  const int r = carry_row[g];
+  if (r >= m) return;
+  if (g > 0 && carry_row[g - 1] == r) return;
   V s = 0;
-  for (int u = t; u < nthreads && carry_row[u] == r; ++u) s += carry_val[u];
-  // the row's own thread wrote y[r] = (its piece); carries precede it in order
+  for (int u = g; u < nwg && carry_row[u] == r; ++u) s += carry_val[u];
   y[r] = s + y[r];
-  (void)ptr;
 }
 
 // ---- reductions / vectors --------------------------------------------------
@@ -1542,12 +1619,11 @@ static void launch_tiles(K kern, int ntiles, hipStream_t s, hipEvent_t e0, hipEv
 // thread (kRowsPerBlock threads; four such workgroups per CU, 256 CUs) runs
 // that shape instead, which shortens each thread's serial chain.
 constexpr int kWideThreads = kRowsPerBlock;
-constexpr int kFewTiles = 1024;
 
 template <typename T, bool CHECK>
 static void launch_primal_t(int ntiles, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const SlotDev* slots,
-                            const Tile* tiles, int jiter) {
-  if (ntiles < kFewTiles)
+                            const Tile* tiles, int jiter, int threads) {
+  if (threads == kWideThreads || (threads == 0 && ntiles < kFewTiles))
     launch_tiles<kWideThreads>(k_primal<T, CHECK, kWideThreads>, ntiles, s, e0, e1, slots, tiles, jiter);
   else
     launch_tiles<kThreads>(k_primal<T, CHECK, kThreads>, ntiles, s, e0, e1, slots, tiles, jiter);
@@ -1555,36 +1631,36 @@ static void launch_primal_t(int ntiles, hipStream_t s, hipEvent_t e0, hipEvent_t
 
 template <typename T, bool CHECK>
 static void launch_dual_t(int ntiles, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const SlotDev* slots,
-                          const Tile* tiles, int jiter) {
-  if (ntiles < kFewTiles)
+                          const Tile* tiles, int jiter, int threads) {
+  if (threads == kWideThreads || (threads == 0 && ntiles < kFewTiles))
     launch_tiles<kWideThreads>(k_dual<T, CHECK, kWideThreads>, ntiles, s, e0, e1, slots, tiles, jiter);
   else
     launch_tiles<kThreads>(k_dual<T, CHECK, kThreads>, ntiles, s, e0, e1, slots, tiles, jiter);
 }
 
 void launch_primal(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
-                   int jiter, int nscen, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                   int jiter, int nscen, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int threads) {
   if (ntiles <= 0) return;
   (void)nscen;
   if (prec == 1) {
-    if (check) launch_primal_t<float, true>(ntiles, s, e0, e1, slots, tiles, jiter);
-    else launch_primal_t<float, false>(ntiles, s, e0, e1, slots, tiles, jiter);
+    if (check) launch_primal_t<float, true>(ntiles, s, e0, e1, slots, tiles, jiter, threads);
+    else launch_primal_t<float, false>(ntiles, s, e0, e1, slots, tiles, jiter, threads);
   } else {
-    if (check) launch_primal_t<double, true>(ntiles, s, e0, e1, slots, tiles, jiter);
-    else launch_primal_t<double, false>(ntiles, s, e0, e1, slots, tiles, jiter);
+    if (check) launch_primal_t<double, true>(ntiles, s, e0, e1, slots, tiles, jiter, threads);
+    else launch_primal_t<double, false>(ntiles, s, e0, e1, slots, tiles, jiter, threads);
   }
 }
 
 void launch_dual(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
-                 int jiter, int nscen, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                 int jiter, int nscen, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int threads) {
   if (ntiles <= 0) return;
   (void)nscen;
   if (prec == 1) {
-    if (check) launch_dual_t<float, true>(ntiles, s, e0, e1, slots, tiles, jiter);
-    else launch_dual_t<float, false>(ntiles, s, e0, e1, slots, tiles, jiter);
+    if (check) launch_dual_t<float, true>(ntiles, s, e0, e1, slots, tiles, jiter, threads);
+    else launch_dual_t<float, false>(ntiles, s, e0, e1, slots, tiles, jiter, threads);
   } else {
-    if (check) launch_dual_t<double, true>(ntiles, s, e0, e1, slots, tiles, jiter);
-    else launch_dual_t<double, false>(ntiles, s, e0, e1, slots, tiles, jiter);
+    if (check) launch_dual_t<double, true>(ntiles, s, e0, e1, slots, tiles, jiter, threads);
+    else launch_dual_t<double, false>(ntiles, s, e0, e1, slots, tiles, jiter, threads);
   }
 }
 
@@ -1730,24 +1806,28 @@ void launch_spmv32(const int* ptr, const int* col, const float* val, const float
   if (nblk > 0) k_spmv<float, float><<<xcd_grid(nblk), kThreads, 0, s>>>(ptr, col, val, x, y, blk, nblk);
 }
 
-int merge_carry_count(int m, int64_t nnz) {
-  return (int)(((int64_t)m + nnz + kMergeItems - 1) / kMergeItems);
+int merge_workgroups(int m, int64_t nnz) {
+  return (int)(((int64_t)m + nnz + kMergeTile - 1) / kMergeTile);
 }
 
-void launch_spmv_merge64(const int* ptr, const int* col, const double* val, const double* x, double* y,
-                         int m, int64_t nnz, int* carry_row, double* carry_val, hipStream_t s) {
-  const int nt = merge_carry_count(m, nnz);
-  if (nt <= 0) return;
-  k_spmv_merge<double><<<nb(nt), kThreads, 0, s>>>(ptr, col, val, x, y, m, nnz, nt, carry_row, carry_val);
-  k_merge_fixup<double><<<nb(nt), kThreads, 0, s>>>(carry_row, carry_val, nt, y, ptr);
+template <typename V>
+static void launch_spmv_merge_t(const int* ptr, const int* col, const V* val, const V* x, V* y, int m, int64_t nnz,
+                                int2* coord, int* carry_row, V* carry_val, hipStream_t s) {
+  const int nwg = merge_workgroups(m, nnz);
+  if (nwg <= 0) return;
+  k_merge_coords<<<nb(nwg + 1), kThreads, 0, s>>>(ptr, m, nnz, nwg, coord);
+  k_spmv_merge<V><<<nwg, kThreads, 0, s>>>(ptr, col, val, x, y, coord, carry_row, carry_val);
+  k_merge_fixup<V><<<nb(nwg), kThreads, 0, s>>>(carry_row, carry_val, nwg, m, y);
 }
 
-void launch_spmv_merge32(const int* ptr, const int* col, const float* val, const float* x, float* y,
-                         int m, int64_t nnz, int* carry_row, float* carry_val, hipStream_t s) {
-  const int nt = merge_carry_count(m, nnz);
-  if (nt <= 0) return;
-  k_spmv_merge<float><<<nb(nt), kThreads, 0, s>>>(ptr, col, val, x, y, m, nnz, nt, carry_row, carry_val);
-  k_merge_fixup<float><<<nb(nt), kThreads, 0, s>>>(carry_row, carry_val, nt, y, ptr);
+void launch_spmv_merge64(const int* ptr, const int* col, const double* val, const double* x, double* y, int m,
+                         int64_t nnz, int2* coord, int* carry_row, double* carry_val, hipStream_t s) {
+  launch_spmv_merge_t<double>(ptr, col, val, x, y, m, nnz, coord, carry_row, carry_val, s);
+}
+
+void launch_spmv_merge32(const int* ptr, const int* col, const float* val, const float* x, float* y, int m,
+                         int64_t nnz, int2* coord, int* carry_row, float* carry_val, hipStream_t s) {
+  launch_spmv_merge_t<float>(ptr, col, val, x, y, m, nnz, coord, carry_row, carry_val, s);
 }
 
 void launch_norm2(const double* v, int64_t n, double* part, double* out, hipStream_t s) {

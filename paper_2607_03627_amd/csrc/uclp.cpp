@@ -103,6 +103,7 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->pw_balance_polish = 0.0;
   o->fp32_stall_checks = 24;
   o->reserved = 0;
+  o->eps_gap_rel = 0.0;
 }
 
 static int check_opts(const uc_lp_opts& o) {
@@ -121,7 +122,7 @@ static int check_opts(const uc_lp_opts& o) {
       (o.restart_to_current != 0 && o.restart_to_current != 1) || !(o.halpern_gamma >= 0 && o.halpern_gamma <= 1) ||
       !(o.pw_max_change == 0 || o.pw_max_change >= 1) || o.fp32_stall_checks < 0 || o.reserved != 0 ||
       !(o.pw_integral >= 0 && o.pw_integral <= 1) || !(o.pw_balance >= 0 && o.pw_balance <= 1) ||
-      !(o.pw_balance_polish >= 0 && o.pw_balance_polish <= 1))
+      !(o.pw_balance_polish >= 0 && o.pw_balance_polish <= 1) || !(o.eps_gap_rel >= 0 && o.eps_gap_rel < 1))
     return fail(UC_LP_EINVAL, "restart / primal-weight parameters out of range");
   return UC_LP_OK;
 }
@@ -580,9 +581,10 @@ struct PdhgState {
   double r_start = 0, r_prev = 0;
   double t_start = 0;
   double pw_int = 0;         // running sum of primal-weight errors
-  double best_kkt = 0;       // FP32 phase: best relative KKT error so far
+  double best_kkt = 0;       // FP32 phase: best progress measure so far
   long long best_check = 0;  // check index at which it was reached
   long long checks = 0;
+  bool gap_phase = false;    // FP32 phase past the eps_rel milestone, closing the gap
 };
 
 struct uc_engine {
@@ -720,9 +722,7 @@ static void release(uc_lp* lp) {
   lp->setup_done = false;
 }
 
-static SlotDev make_slot(const uc_lp* lp) {
-  const HostProblem& P = lp->P;
-  const DevMem& D = lp->D;
+static SlotDev make_slot(const HostProblem& P, const DevMem& D, double gamma) {
   SlotDev S;
   std::memset((void*)&S, 0, sizeof S);
   S.a_ptr = D.a_ptr;
@@ -735,7 +735,7 @@ static SlotDev make_slot(const uc_lp* lp) {
   S.n = P.ni;
   S.m_eq = P.m_eq;
   S.nscen = 1;
-  S.gamma = lp->opts.halpern_gamma;
+  S.gamma = gamma;
   S.a_nblk = (int)P.a_blk.size() - 1;
   S.t_nblk = (int)P.t_blk.size() - 1;
   S.dr = D.dr;
@@ -763,6 +763,8 @@ static SlotDev make_slot(const uc_lp* lp) {
   S.scal = D.scal;
   return S;
 }
+
+static SlotDev make_slot(const uc_lp* lp) { return make_slot(lp->P, lp->D, lp->opts.halpern_gamma); }
 
 // Transpose, scaling, scaled data, power iteration.  Runs on `s`, synchronous.
 static int setup_device(uc_lp* lp) {
@@ -848,14 +850,21 @@ static int setup_device(uc_lp* lp) {
   HIPOK(hipMemcpyAsync(h, D.red_out, sizeof h, hipMemcpyDeviceToHost, s));
   HIPOK(hipStreamSynchronize(s));
   HIPOK(hipGetLastError());
+  // the power-iteration estimate approaches ||A_hat||_2 from below, so it is
+  // no safe step bound by itself; the step uses the Pock-Chambolle bound
+  // ||A_hat||_2 <= 1 that the alpha = 1 scaling guarantees (Schur test), and
+  // the estimate shows how tight that bound is
   const double norm_est = std::pow(std::max(h[0], 0.0), 0.25);
+  const double norm_bound = 1.0;
   const double cn = std::sqrt(h[1]), bn = std::sqrt(h[2]);
   PdhgState& st = lp->st;
-  st.eta = norm_est > 0 ? lp->opts.step_scale / norm_est : 1.0;
+  st.eta = norm_bound > 0 ? lp->opts.step_scale / norm_bound : 1.0;
   st.omega = (cn > 0 && bn > 0) ? cn / bn : 1.0;
   {
     std::lock_guard<std::mutex> g(lp->mu);
     lp->info.norm_a_est = norm_est;
+    lp->info.norm_a_bound = norm_bound;
+    lp->info.eta = st.eta;
     lp->info.omega = st.omega;
   }
   SlotDev S = make_slot(lp);
@@ -944,8 +953,10 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
   st.phase_total += K;
   const long long k_end = st.k_inner + K;
   const double dx2 = q[RQ_N + CQ_DX2], dy2 = q[RQ_DY2], cross = q[RQ_DYADX];
-  const double rfp2 = st.omega / st.eta * dx2 + dy2 / (st.omega * st.eta) - 2.0 * cross;
+  // ||z - T(z)||_P, P = [[I/tau, A_hat'], [A_hat, I/sigma]]: the metric of the PDHG step
+  const double rfp2 = st.omega / st.eta * dx2 + dy2 / (st.omega * st.eta) + 2.0 * cross;
   const double rfp = std::sqrt(std::max(rfp2, 0.0));
+  in.fp_residual = rfp;
   in.iters = st.iters;
   in.iters_fp64 = st.iters64;
   in.precision_now = st.prec == 1 ? UC_LP_FP32_MIXED : UC_LP_FP64;
@@ -960,27 +971,41 @@ static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, 
       in.t_to_eps_s = tnow - st.t_start;
       in.pobj_at_eps = in.pobj;
       in.rel_kkt_at_eps = in.rel_kkt;
+      in.rel_gap_at_eps = in.rel_gap;
       in.iters_at_eps = st.iters;
     }
-    const bool polish_phase = o.precision == UC_LP_FP32_MIXED_POLISH && st.prec == 0;
+    const bool polish_mode = o.precision == UC_LP_FP32_MIXED_POLISH;
+    const bool polish_phase = polish_mode && st.prec == 0;
     const double target = polish_phase ? o.eps_polish : o.eps_rel;
+    // outside the polish mode a returned point also closes the duality gap
+    const bool gap_rule = !polish_mode && o.eps_gap_rel > 0;
+    const bool gap_ok = !gap_rule || in.rel_gap <= o.eps_gap_rel;
     if (in.rel_kkt <= target && feas_ok) {
-      if (o.precision == UC_LP_FP32_MIXED_POLISH && st.prec == 1) {
+      if (polish_mode && st.prec == 1) {
         out.promote = true;
-      } else {
+      } else if (gap_ok) {
         out.terminate = true;
         out.status = UC_LP_OPTIMAL;
       }
     }
-    // an FP32 phase that stopped improving continues in FP64
+    // an FP32 phase that stopped improving continues in FP64.  Progress is
+    // the KKT error, and past the eps_rel milestone under the gap rule the
+    // larger of it and the gap, both relative to their targets
     ++st.checks;
-    if (st.prec == 1 && !out.terminate) {
-      if (st.best_check == 0 || in.rel_kkt < 0.9 * st.best_kkt) {
-        st.best_kkt = in.rel_kkt;
+    if (st.prec == 1 && !out.terminate && !out.promote) {
+      const bool continuing = gap_rule && in.t_to_eps_s >= 0;
+      const double err = continuing ? std::max(in.rel_kkt, in.rel_gap * (target / o.eps_gap_rel)) : in.rel_kkt;
+      if (continuing && !st.gap_phase) {
+        st.gap_phase = true;  // the progress measure changes: start its window afresh
+        st.best_check = 0;
+      }
+      if (st.best_check == 0 || err < 0.9 * st.best_kkt) {
+        st.best_kkt = err;
         st.best_check = st.checks;
       } else if (o.fp32_stall_checks > 0 && st.checks - st.best_check >= o.fp32_stall_checks &&
-                 st.best_kkt <= 10.0 * target) {
-        // a stall within a decade of the target is taken for the FP32 floor
+                 (continuing || st.best_kkt <= 10.0 * target)) {
+        // a stall within a decade of the target (or of the gap past the
+        // milestone) is taken for the FP32 floor
         out.promote = true;
       }
     }
@@ -1739,9 +1764,9 @@ static int get_vec(double* dst, const T* src, size_t n, hipStream_t s) {
 }
 
 template <typename T>
-static int debug_step_t(uc_lp* lp, const double* x, const double* y, const double* x0, const double* y0,
-                        int64_t k, double tau, double sigma, double* xh, double* yh, double* xn,
-                        double* yn) {
+static int debug_iterate_t(uc_lp* lp, int iters, int threads, const double* x, const double* y, const double* x0,
+                           const double* y0, int64_t k, double tau, double sigma, double* xh, double* yh, double* xn,
+                           double* yn, double* rfp) {
   const HostProblem& P = lp->P;
   DevMem& D = lp->D;
   uc_engine* E = lp->eng;
@@ -1756,7 +1781,8 @@ static int debug_step_t(uc_lp* lp, const double* x, const double* y, const doubl
   S.tau[0] = tau;
   S.sigma[0] = sigma;
   S.k0[0] = k;
-  S.kfin = k;
+  S.kfin = k + iters - 1;
+  S.restart[0] = 0;
   S.active[0] = 1;
   std::vector<Tile> tl;
   push_tiles(tl, 0, P.t_blk, P.t_ptr, &P.t_flag, &P.t_base);
@@ -1765,34 +1791,61 @@ static int debug_step_t(uc_lp* lp, const double* x, const double* y, const doubl
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(E->d_tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+  int zero = 0;
+  HIPOK(hipMemcpyAsync(E->d_ids, &zero, sizeof zero, hipMemcpyHostToDevice, s));
   const Tile* TT = E->d_tiles;
   const Tile* TA = E->d_tiles + S.t_nblk;
-  // check-mode half-steps write x_hat, y_hat and keep x, y; the finish kernel
-  // then applies the Halpern step exactly as in the solve
-  launch_primal(prec, true, E->d_slots, TT, S.t_nblk, 0, 1, s);
-  launch_dual(prec, true, E->d_slots, TA, S.a_nblk, 0, 1, s);
+  // the launch sequence of one check interval of the solve (run_epochs)
+  for (int j = 0; j < iters; ++j) {
+    const bool check = j == iters - 1;
+    launch_primal(prec, check, E->d_slots, TT, S.t_nblk, j, 1, s, nullptr, nullptr, threads);
+    launch_dual(prec, check, E->d_slots, TA, S.a_nblk, j, 1, s, nullptr, nullptr, threads);
+  }
+  launch_kkt(prec, E->d_slots, TT, S.t_nblk, TA, S.a_nblk, 1, s);
+  launch_reduce(E->d_slots, E->d_ids, 1, 1, E->d_red2, s);
   launch_finish(prec, E->d_slots, TT, S.t_nblk, TA, S.a_nblk, 0, 1, s);
+  double q[kScal];
+  HIPOK(hipMemcpyAsync(q, D.scal, sizeof q, hipMemcpyDeviceToHost, s));
   HIPOK(hipGetLastError());
   HIPOK(hipStreamSynchronize(s));
   if ((rc = get_vec<T>(xh, V.xhat, P.ni, s)) || (rc = get_vec<T>(yh, V.yhat, P.mi, s)) ||
       (rc = get_vec<T>(xn, V.x, P.ni, s)) || (rc = get_vec<T>(yn, V.y, P.mi, s)))
     return rc;
+  if (rfp) {
+    // the same scalars and metric as the restart test of a solve
+    const double r2 = q[RQ_N + CQ_DX2] / tau + q[RQ_DY2] / sigma + 2.0 * q[RQ_DYADX];
+    *rfp = std::sqrt(std::max(r2, 0.0));
+  }
   return UC_LP_OK;
 }
 
-extern "C" int uc_lp_debug_step(uc_lp* lp, int32_t precision, const double* x, const double* y,
-                                const double* x0, const double* y0, int64_t k, double tau, double sigma,
-                                double* x_hat, double* y_hat, double* x_next, double* y_next) {
+extern "C" int uc_lp_debug_iterate(uc_lp* lp, int32_t precision, int32_t iters, int32_t block_threads,
+                                   const double* x, const double* y, const double* x0, const double* y0, int64_t k,
+                                   double tau, double sigma, double* x_hat, double* y_hat, double* x_next,
+                                   double* y_next, double* fp_residual) {
   g_err.clear();
   int rc = debug_ready(lp);
   if (rc) return rc;
   if (!x || !y || !x0 || !y0 || !x_hat || !y_hat || !x_next || !y_next)
     return fail(UC_LP_EINVAL, "NULL vector");
   if (k < 0 || !(tau > 0) || !(sigma > 0)) return fail(UC_LP_EINVAL, "k, tau, sigma");
-  if (precision == UC_LP_FP64) return debug_step_t<double>(lp, x, y, x0, y0, k, tau, sigma, x_hat, y_hat, x_next, y_next);
+  if (iters < 1 || iters > 4096) return fail(UC_LP_EINVAL, "iters %d not in 1..4096", iters);
+  if (block_threads != 0 && block_threads != kThreads && block_threads != kRowsPerBlock)
+    return fail(UC_LP_EINVAL, "block_threads %d: 0, %d or %d", block_threads, kThreads, kRowsPerBlock);
+  if (precision == UC_LP_FP64)
+    return debug_iterate_t<double>(lp, iters, block_threads, x, y, x0, y0, k, tau, sigma, x_hat, y_hat, x_next,
+                                   y_next, fp_residual);
   if (precision == UC_LP_FP32_MIXED)
-    return debug_step_t<float>(lp, x, y, x0, y0, k, tau, sigma, x_hat, y_hat, x_next, y_next);
+    return debug_iterate_t<float>(lp, iters, block_threads, x, y, x0, y0, k, tau, sigma, x_hat, y_hat, x_next,
+                                  y_next, fp_residual);
   return fail(UC_LP_ENOTSUP, "precision %d", precision);
+}
+
+extern "C" int uc_lp_debug_step(uc_lp* lp, int32_t precision, const double* x, const double* y,
+                                const double* x0, const double* y0, int64_t k, double tau, double sigma,
+                                double* x_hat, double* y_hat, double* x_next, double* y_next) {
+  return uc_lp_debug_iterate(lp, precision, 1, 0, x, y, x0, y0, k, tau, sigma, x_hat, y_hat, x_next, y_next,
+                             nullptr);
 }
 
 extern "C" int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp_info* out) {
@@ -1854,11 +1907,12 @@ extern "C" int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp
 struct SpmvDev {
   int *ptr = nullptr, *col = nullptr, *blk = nullptr, *crow = nullptr;
   void *val = nullptr, *x = nullptr, *y = nullptr, *cval = nullptr;
+  int2* coord = nullptr;
   int nblk = 0;
 };
 
 static void spmv_free(SpmvDev& S) {
-  for (void* p : {(void*)S.ptr, (void*)S.col, (void*)S.blk, (void*)S.crow, S.val, S.x, S.y, S.cval})
+  for (void* p : {(void*)S.ptr, (void*)S.col, (void*)S.blk, (void*)S.crow, S.val, S.x, S.y, S.cval, (void*)S.coord})
     if (p) (void)hipFree(p);
 }
 
@@ -1874,9 +1928,10 @@ static int spmv_prepare(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, co
   HIPOK(hipMalloc(&S.val, vs * std::max<int64_t>(nnz, 1)));
   HIPOK(hipMalloc(&S.x, vs * n));
   HIPOK(hipMalloc(&S.y, vs * m));
-  const int nc = merge_carry_count(m, nnz);
+  const int nc = merge_workgroups(m, nnz);
   HIPOK(hipMalloc(&S.crow, sizeof(int) * std::max(nc, 1)));
   HIPOK(hipMalloc(&S.cval, vs * std::max(nc, 1)));
+  HIPOK(hipMalloc(&S.coord, sizeof(int2) * (nc + 1)));
   HIPOK(hipMemcpyAsync(S.ptr, rp, sizeof(int) * (m + 1), hipMemcpyHostToDevice, s));
   if (nnz) HIPOK(hipMemcpyAsync(S.col, ci, sizeof(int) * nnz, hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(S.blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice, s));
@@ -1905,14 +1960,14 @@ static int spmv_prepare(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, co
 static void spmv_launch(const SpmvDev& S, int32_t m, int64_t nnz, int prec, int algo, hipStream_t s) {
   if (prec == UC_LP_FP64) {
     if (algo == UC_LP_SPMV_MERGEPATH)
-      launch_spmv_merge64(S.ptr, S.col, (const double*)S.val, (const double*)S.x, (double*)S.y, m, nnz, S.crow,
-                          (double*)S.cval, s);
+      launch_spmv_merge64(S.ptr, S.col, (const double*)S.val, (const double*)S.x, (double*)S.y, m, nnz, S.coord,
+                          S.crow, (double*)S.cval, s);
     else
       launch_spmv64(S.ptr, S.col, (const double*)S.val, (const double*)S.x, (double*)S.y, S.blk, S.nblk, s);
   } else {
     if (algo == UC_LP_SPMV_MERGEPATH)
-      launch_spmv_merge32(S.ptr, S.col, (const float*)S.val, (const float*)S.x, (float*)S.y, m, nnz, S.crow,
-                          (float*)S.cval, s);
+      launch_spmv_merge32(S.ptr, S.col, (const float*)S.val, (const float*)S.x, (float*)S.y, m, nnz, S.coord,
+                          S.crow, (float*)S.cval, s);
     else
       launch_spmv32(S.ptr, S.col, (const float*)S.val, (const float*)S.x, (float*)S.y, S.blk, S.nblk, s);
   }
@@ -2023,6 +2078,110 @@ extern "C" int uc_copy_bench(int device, size_t bytes, int32_t reps, double* gbp
   (void)hipFree(a);
   (void)hipFree(b);
   return rc;
+}
+
+extern "C" int uc_lp_bench_half_steps(uc_lp* lp, int32_t precision, int32_t copies, int32_t reps,
+                                      double* primal_us, double* dual_us, double* primal_bytes,
+                                      double* dual_bytes) {
+  g_err.clear();
+  if (!primal_us || !dual_us) return fail(UC_LP_EINVAL, "NULL output");
+  if (copies < 1 || copies > 64 || reps < 1 || reps > 4096) return fail(UC_LP_EINVAL, "copies 1..64, reps 1..4096");
+  if (precision != UC_LP_FP64 && precision != UC_LP_FP32_MIXED) return fail(UC_LP_ENOTSUP, "precision %d", precision);
+  int rc = debug_ready(lp);
+  if (rc) return rc;
+  const int prec = precision == UC_LP_FP32_MIXED ? 1 : 0;
+  const HostProblem& P = lp->P;
+  uc_engine* E = lp->eng;
+  hipStream_t s = E->stream;
+  if ((rc = init_iterates(lp, prec))) return rc;
+  HIPOK(hipStreamSynchronize(s));
+  const size_t bytes = lp->D.ar.bytes;
+  std::vector<void*> mem(copies, nullptr);
+  SlotDev* d_slots = nullptr;
+  Tile* d_tiles = nullptr;
+  std::vector<hipEvent_t> ev;
+  auto cleanup = [&]() {
+    for (void* p : mem)
+      if (p) (void)hipFree(p);
+    if (d_slots) (void)hipFree(d_slots);
+    if (d_tiles) (void)hipFree(d_tiles);
+    for (auto e : ev) (void)hipEventDestroy(e);
+  };
+#define BENCH_HIP(call)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      cleanup();                                                                             \
+      return fail(UC_LP_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));                \
+    }                                                                                        \
+  } while (0)
+  // each copy is the instance's whole arena (matrix, scaled data, iterates),
+  // so its slot descriptor is carved the same way at another base
+  std::vector<SlotDev> slots(copies);
+  std::vector<Tile> tiles;
+  for (int c = 0; c < copies; ++c) {
+    if (hipMalloc(&mem[c], bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      cleanup();
+      return fail(UC_LP_ENOMEM, "copy %d of %zu bytes", c, bytes);
+    }
+    BENCH_HIP(hipMemcpyAsync(mem[c], lp->D.ar.base, bytes, hipMemcpyDeviceToDevice, s));
+    DevMem Dc;
+    std::memset((void*)&Dc, 0, sizeof Dc);
+    Dc.ar.base = (char*)mem[c];
+    Dc.ar.bytes = bytes;
+    carve(Dc, P, 1);
+    SlotDev S = make_slot(P, Dc, lp->opts.halpern_gamma);
+    S.tau[0] = lp->st.eta / lp->st.omega;
+    S.sigma[0] = lp->st.eta * lp->st.omega;
+    S.k0[0] = 0;
+    S.active[0] = 1;
+    slots[c] = S;
+    push_tiles(tiles, c, P.t_blk, P.t_ptr, &P.t_flag, &P.t_base);
+  }
+  const size_t nt = P.t_blk.size() - 1, na = P.a_blk.size() - 1;
+  for (int c = 0; c < copies; ++c) push_tiles(tiles, c, P.a_blk, P.a_ptr, &P.a_flag, &P.a_base);
+  BENCH_HIP(hipMalloc(&d_slots, sizeof(SlotDev) * copies));
+  BENCH_HIP(hipMalloc(&d_tiles, sizeof(Tile) * tiles.size()));
+  BENCH_HIP(hipMemcpyAsync(d_slots, slots.data(), sizeof(SlotDev) * copies, hipMemcpyHostToDevice, s));
+  BENCH_HIP(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s));
+  BENCH_HIP(hipStreamSynchronize(s));
+  ev.resize(4 * (size_t)reps, nullptr);
+  for (auto& e : ev) BENCH_HIP(hipEventCreate(&e));
+  auto tt = [&](int c) { return d_tiles + (size_t)c * nt; };
+  auto ta = [&](int c) { return d_tiles + (size_t)copies * nt + (size_t)c * na; };
+  // warm-up: one iteration on every copy
+  for (int c = 0; c < copies; ++c) {
+    launch_primal(prec, false, d_slots, tt(c), (int)nt, 1, 1, s);
+    launch_dual(prec, false, d_slots, ta(c), (int)na, 1, 1, s);
+  }
+  // iterations round-robin over the copies: launch r reads copy r % copies,
+  // as a solve's non-check launches (inner index 1..62, primal iterate rebuilt
+  // at full reflection); each launch carries its own start / stop events
+  for (int r = 0; r < reps; ++r) {
+    const int c = r % copies, j = 1 + r % 62;
+    launch_primal(prec, false, d_slots, tt(c), (int)nt, j, 1, s, ev[4 * r], ev[4 * r + 1]);
+    launch_dual(prec, false, d_slots, ta(c), (int)na, j, 1, s, ev[4 * r + 2], ev[4 * r + 3]);
+  }
+  BENCH_HIP(hipGetLastError());
+  BENCH_HIP(hipStreamSynchronize(s));
+  double tp = 0, td = 0;
+  for (int r = 0; r < reps; ++r) {
+    float a = 0, b = 0;
+    BENCH_HIP(hipEventElapsedTime(&a, ev[4 * r], ev[4 * r + 1]));
+    BENCH_HIP(hipEventElapsedTime(&b, ev[4 * r + 2], ev[4 * r + 3]));
+    tp += a;
+    td += b;
+  }
+  *primal_us = 1e3 * tp / reps;
+  *dual_us = 1e3 * td / reps;
+  double pb = 0, db = 0;
+  half_step_bytes(P, prec ? 4 : 8, lp->opts.halpern_gamma == 1.0, &pb, &db);
+  if (primal_bytes) *primal_bytes = pb;
+  if (dual_bytes) *dual_bytes = db;
+  cleanup();
+#undef BENCH_HIP
+  return UC_LP_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -2212,7 +2371,10 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
     ps[s].t_start = t0;
     std::memset(&inf[s], 0, sizeof inf[s]);
     inf[s].t_to_eps_s = -1;
-    inf[s].norm_a_est = get_info(base).norm_a_est;
+    const uc_lp_info bi = get_info(base);
+    inf[s].norm_a_est = bi.norm_a_est;
+    inf[s].norm_a_bound = bi.norm_a_bound;
+    inf[s].eta = bi.eta;
     inf[s].m_presolved = mi;
     inf[s].n_presolved = ni;
     inf[s].nnz_presolved = P.nnzi;

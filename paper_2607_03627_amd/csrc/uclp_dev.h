@@ -123,12 +123,15 @@ enum TileFlag {
 // ---- launchers (kernels.hip) --------------------------------------------
 // prec: 0 = FP64, 1 = FP32.  All launches go to `s`.
 // e0/e1 (optional): events that record the start and end of the kernel itself
+// threads: workgroup size of the half-steps, 0 = by launch size (kRowsPerBlock
+// threads, one row each, below kFewTiles tiles; kThreads otherwise)
+constexpr int kFewTiles = 1024;
 void launch_primal(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
                    int jiter, int nscen, hipStream_t s, hipEvent_t e0 = nullptr,
-                   hipEvent_t e1 = nullptr);
+                   hipEvent_t e1 = nullptr, int threads = 0);
 void launch_dual(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles,
                  int jiter, int nscen, hipStream_t s, hipEvent_t e0 = nullptr,
-                 hipEvent_t e1 = nullptr);
+                 hipEvent_t e1 = nullptr, int threads = 0);
 void launch_kkt(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles,
                 const Tile* atiles, int natiles, int nscen, hipStream_t s);
 // Two-level deterministic reduction of the KKT partials of each listed slot
@@ -191,13 +194,14 @@ void launch_spmv64(const int* ptr, const int* col, const double* val, const doub
                    const int* blk, int nblk, hipStream_t s);
 void launch_spmv32(const int* ptr, const int* col, const float* val, const float* x, float* y,
                    const int* blk, int nblk, hipStream_t s);
-// merge-path SpMV: carries[] sized merge_carry_count(m, nnz)
-int merge_carry_count(int m, int64_t nnz);
+// merge-path SpMV: nwg = merge_workgroups(m, nnz) workgroups; scratch of
+// coord[nwg + 1], carry_row[nwg], carry_val[nwg]
+int merge_workgroups(int m, int64_t nnz);
 void launch_spmv_merge64(const int* ptr, const int* col, const double* val, const double* x,
-                         double* y, int m, int64_t nnz, int* carry_row, double* carry_val,
+                         double* y, int m, int64_t nnz, int2* coord, int* carry_row, double* carry_val,
                          hipStream_t s);
 void launch_spmv_merge32(const int* ptr, const int* col, const float* val, const float* x, float* y,
-                         int m, int64_t nnz, int* carry_row, float* carry_val, hipStream_t s);
+                         int m, int64_t nnz, int2* coord, int* carry_row, float* carry_val, hipStream_t s);
 // sum of squares of v (n) into *out (deterministic two-pass); part sized >= 1024
 void launch_norm2(const double* v, int64_t n, double* part, double* out, hipStream_t s);
 // v = w / sqrt(*nrm2)

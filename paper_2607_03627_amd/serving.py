@@ -107,10 +107,21 @@ def run_stream(lps: Sequence, arrivals_s: Sequence[float], opts: uclp.uc_lp_opts
         x, y = sols.get(i, (None, None))
         served.append(Served(i, float(arrivals_s[i]), submit[i], done[i], infos[i], x, y))
     lat = [s.latency_s for s in served]
+    n_opt = sum(1 for s in served if s.info["status"] == uclp.UC_LP_OPTIMAL)
+    # throughput counts the requests that reached their tolerance; the others
+    # (iteration or time limit) are reported apart
     stats = dict(n=len(served), p50_s=nearest_rank(lat, 50), p99_s=nearest_rank(lat, 99),
-                 max_s=max(lat), mean_s=float(np.mean(lat)), solves_per_s=len(served) / makespan,
+                 max_s=max(lat), mean_s=float(np.mean(lat)), solves_per_s=n_opt / makespan,
+                 requests_per_s=len(served) / makespan, n_optimal=n_opt, n_not_optimal=len(served) - n_opt,
                  makespan_s=makespan,
                  statuses={k: sum(1 for s in served if s.info["status_name"] == k)
                            for k in sorted({s.info["status_name"] for s in served})},
                  iters_total=int(sum(s.info["iters"] for s in served)))
     return StreamResult(served, makespan, max_slots, hbm_budget_bytes, stats)
+
+
+def pooled_latency(results: Sequence[StreamResult]) -> dict:
+    """p50 / p99 by nearest rank over the requests of several streams."""
+    lat = [s.latency_s for r in results for s in r.served]
+    return dict(n=len(lat), p50_s=nearest_rank(lat, 50), p99_s=nearest_rank(lat, 99), max_s=max(lat),
+                n_not_optimal=sum(r.stats["n_not_optimal"] for r in results))

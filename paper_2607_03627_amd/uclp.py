@@ -40,7 +40,7 @@ class uc_lp_opts(C.Structure):
                 ("restart_artificial", C.c_double), ("pw_smoothing", C.c_double),
                 ("halpern_gamma", C.c_double), ("pw_max_change", C.c_double),
                 ("fp32_stall_checks", C.c_int32), ("reserved", C.c_int32), ("pw_integral", C.c_double),
-                ("pw_balance", C.c_double), ("pw_balance_polish", C.c_double)]
+                ("pw_balance", C.c_double), ("pw_balance_polish", C.c_double), ("eps_gap_rel", C.c_double)]
 
 
 class uc_lp_info(C.Structure):
@@ -55,7 +55,8 @@ class uc_lp_info(C.Structure):
                 ("primal_kernel_us", C.c_double), ("dual_kernel_us", C.c_double),
                 ("timed_launches", C.c_int64), ("m_presolved", C.c_int32), ("n_presolved", C.c_int32),
                 ("nnz_presolved", C.c_int64), ("device_bytes", C.c_int64),
-                ("primal_bytes", C.c_double), ("dual_bytes", C.c_double)]
+                ("primal_bytes", C.c_double), ("dual_bytes", C.c_double), ("rel_gap_at_eps", C.c_double),
+                ("fp_residual", C.c_double), ("norm_a_bound", C.c_double), ("eta", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -67,7 +68,7 @@ EXPORTS = ["uc_lp_opts_default", "uc_engine_create", "uc_engine_destroy", "uc_lp
            "uc_lp_update_data", "uc_lp_solve", "uc_lp_status", "uc_lp_wait", "uc_lp_cancel",
            "uc_lp_get_solution", "uc_lp_destroy", "uc_lp_last_error", "uc_lp_solve_scenarios",
            "uc_lp_internal_dims", "uc_lp_get_transpose", "uc_lp_get_scaling", "uc_lp_debug_step",
-           "uc_lp_eval_kkt", "uc_spmv", "uc_spmv_bench", "uc_copy_bench"]
+           "uc_lp_debug_iterate", "uc_lp_eval_kkt", "uc_spmv", "uc_spmv_bench", "uc_copy_bench", "uc_lp_bench_half_steps"]
 
 _lib: Optional[C.CDLL] = None
 
@@ -101,16 +102,20 @@ def _sig(lib):
     lib.uc_lp_get_scaling.argtypes = [_P, _D, _D, _D]
     lib.uc_lp_debug_step.argtypes = [_P, C.c_int32, _D, _D, _D, _D, C.c_int64, C.c_double, C.c_double,
                                      _D, _D, _D, _D]
+    lib.uc_lp_debug_iterate.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _D, _D, _D, _D, C.c_int64,
+                                        C.c_double, C.c_double, _D, _D, _D, _D, _D]
     lib.uc_lp_eval_kkt.argtypes = [_P, _D, _D, C.POINTER(uc_lp_info)]
     lib.uc_spmv.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int64, _I, _I, _D, _D, _D, C.c_int32,
                             C.c_int32]
     lib.uc_spmv_bench.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int64, _I, _I, _D, C.c_int32,
                                   C.c_int32, C.c_int32, C.c_int32, _D]
     lib.uc_copy_bench.argtypes = [C.c_int, C.c_size_t, C.c_int32, _D]
+    lib.uc_lp_bench_half_steps.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _D, _D, _D, _D]
     for name in ("uc_engine_create", "uc_lp_create", "uc_lp_update_data", "uc_lp_solve", "uc_lp_status",
                  "uc_lp_wait", "uc_lp_cancel", "uc_lp_get_solution", "uc_lp_solve_scenarios",
                  "uc_lp_internal_dims", "uc_lp_get_transpose", "uc_lp_get_scaling", "uc_lp_debug_step",
-                 "uc_lp_eval_kkt", "uc_spmv", "uc_spmv_bench", "uc_copy_bench"):
+                 "uc_lp_debug_iterate", "uc_lp_eval_kkt", "uc_spmv", "uc_spmv_bench", "uc_copy_bench",
+                 "uc_lp_bench_half_steps"):
         getattr(lib, name).restype = C.c_int
 
 
@@ -292,6 +297,17 @@ def uc_lp_debug_step(h, precision, x, y, x0, y0, k, tau, sigma):
     return xh, yh, xn, yn
 
 
+def uc_lp_debug_iterate(h, precision, iters, x, y, x0, y0, k, tau, sigma, block_threads=0):
+    """Returns x_hat, y_hat, x_next, y_next, fp_residual (see include/uc_lp.h)."""
+    x, y, x0, y0 = _f64(x), _f64(y), _f64(x0), _f64(y0)
+    xh, yh, xn, yn = np.empty_like(x), np.empty_like(y), np.empty_like(x), np.empty_like(y)
+    r = C.c_double()
+    _check(load().uc_lp_debug_iterate(h, int(precision), int(iters), int(block_threads), _d(x), _d(y), _d(x0),
+                                      _d(y0), int(k), float(tau), float(sigma), _d(xh), _d(yh), _d(xn), _d(yn),
+                                      C.byref(r)))
+    return xh, yh, xn, yn, r.value
+
+
 def uc_lp_eval_kkt(h, x, y) -> uc_lp_info:
     info = uc_lp_info()
     _check(load().uc_lp_eval_kkt(h, _d(_f64(x)), _d(_f64(y)), C.byref(info)))
@@ -313,6 +329,13 @@ def uc_spmv_bench(m, n, row_ptr, col_idx, val, precision=UC_LP_FP32_MIXED, algo=
     _check(load().uc_spmv_bench(device, int(m), int(n), int(len(ci)), _i(rp), _i(ci), _d(v), int(precision),
                                 int(algo), int(copies), int(reps), C.byref(us)))
     return us.value
+
+
+def uc_lp_bench_half_steps(h, precision=UC_LP_FP32_MIXED, copies=4, reps=64):
+    """Returns dict(primal_us, dual_us, primal_bytes, dual_bytes)."""
+    v = [C.c_double() for _ in range(4)]
+    _check(load().uc_lp_bench_half_steps(h, int(precision), int(copies), int(reps), *[C.byref(x) for x in v]))
+    return dict(primal_us=v[0].value, dual_us=v[1].value, primal_bytes=v[2].value, dual_bytes=v[3].value)
 
 
 def uc_copy_bench(nbytes: int, reps: int = 20, device: int = 0) -> float:

@@ -138,3 +138,40 @@ def test_scenario_count_limits():
         assert e.value.code == uclp.UC_LP_ENOTSUP
     finally:
         uclp.uc_lp_destroy(h)
+
+
+def test_fp32_phase_compaction_equals_single_scenario_bitwise():
+    # Four of eight scenarios are the 500-bus LP itself: warm-started at its
+    # FP64 optimum they stop at the first check, still in the FP32 phase, and
+    # the batch moves the other four (load / cost perturbations) to arrays of
+    # their own lanes while the FP32 phase goes on.  Short of 1e-6 their FP32
+    # iteration stalls and hands over to FP64, which finishes them.  A lane of
+    # each kind equals the same scenario solved as a batch of one, bit for bit.
+    lp = make_instance("medium", 0)
+    say("case medium 8 scenarios, FP32-phase compaction")
+    xn, yn, info = uclp.solve(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-8),
+                              timeout_s=300)
+    assert info["status"] == uclp.UC_LP_OPTIMAL
+    cs, bs, ls, us = stack(lp, [1, 2, 3, 4])
+    c = np.concatenate([np.tile(lp.c, (4, 1)), cs])
+    b = np.concatenate([np.tile(lp.b, (4, 1)), bs])
+    lb = np.concatenate([np.tile(lp.lb, (4, 1)), ls])
+    ub = np.concatenate([np.tile(lp.ub, (4, 1)), us])
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-6,
+                                                      fp32_stall_checks=2, iter_limit=200000))
+    try:
+        x, y, infos = uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, c, b, lb, ub, xn, yn)
+        say("iters", [i.iters for i in infos], "fp64", [i.iters_fp64 for i in infos])
+        assert all(i.status == uclp.UC_LP_OPTIMAL for i in infos)
+        early, late = range(4), range(4, 8)
+        assert all(infos[k].iters == 64 and infos[k].iters_fp64 == 0 for k in early)
+        assert all(infos[k].iters > 64 for k in late)
+        assert any(infos[k].iters_fp64 > 0 for k in late)
+        for k in (0, max(late, key=lambda t: (infos[t].iters_fp64, infos[t].iters))):
+            say("single", k)
+            xs, ys, i1 = uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, c[k:k + 1], b[k:k + 1], lb[k:k + 1],
+                                                    ub[k:k + 1], xn, yn)
+            assert i1[0].iters == infos[k].iters and i1[0].iters_fp64 == infos[k].iters_fp64
+            assert np.array_equal(xs[0], x[k]) and np.array_equal(ys[0], y[k])
+    finally:
+        uclp.uc_lp_destroy(h)

@@ -36,10 +36,44 @@ def test_library_exports_every_declared_symbol():
     assert sorted(declared_functions()) == sorted(uclp.EXPORTS)
 
 
+def c_layout(struct_name, fields):
+    """sizeof and field offsets of a struct of include/uc_lp.h, as the C
+    compiler lays it out (gcc on the host)."""
+    import shutil
+    import subprocess
+    import tempfile
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "uc_lp.h"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct_name}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct_name}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "lay.c"), os.path.join(d, "lay")
+        with open(src, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    vals = [int(v) for v in out]
+    return vals[0], vals[1:]
+
+
+@pytest.mark.parametrize("name", ["uc_lp_opts", "uc_lp_info"])
+def test_binding_struct_layout_equals_the_c_layout(name):
+    cls = getattr(uclp, name)
+    fields = [f for f, _ in cls._fields_]
+    size, offs = c_layout(name, fields)
+    assert ctypes.sizeof(cls) == size
+    assert [getattr(cls, f).offset for f in fields] == offs
+
+
 def test_binding_structs_match_header_layout():
     # the two structs are passed by pointer; their sizes must agree with the C layout
-    assert ctypes.sizeof(uclp.uc_lp_opts) == 4 * 4 + 8 + 5 * 8 + 4 * 4 + 6 * 8 + 2 * 4 + 3 * 8
+    assert ctypes.sizeof(uclp.uc_lp_opts) == 4 * 4 + 8 + 5 * 8 + 4 * 4 + 6 * 8 + 2 * 4 + 4 * 8
     o = uclp.uc_lp_opts_default()
+    assert o.eps_gap_rel == 0.0
     assert o.precision == uclp.UC_LP_FP32_MIXED_POLISH and o.kkt_every == 64
     assert o.iter_limit == 100000 and o.eps_rel == 1e-4 and o.eps_polish == 1e-8
     assert (o.restart_sufficient, o.restart_necessary, o.restart_artificial, o.pw_smoothing) == \
