@@ -36,8 +36,15 @@ def load():
 
 
 def save(d):
-    with open(OUT, "w") as f:
-        json.dump(d, f, indent=1, sort_keys=True)
+    # merge with what is on disk, so that two runs writing different keys
+    # (a long 6,049-bus job beside a short one) do not drop each other's
+    disk = load()
+    disk.update(d)
+    d.update(disk)
+    tmp = OUT + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(disk, f, indent=1, sort_keys=True)
+    os.replace(tmp, OUT)
 
 
 def record(d, key, lp, method):
