@@ -249,6 +249,62 @@ def race_leg(large_lp):
     return {"poll_s": 0.5, "cases": rows, "wins": wins}
 
 
+def size_sweep_leg(time_limit_s=60.0):
+    """GPU PDHG against the CPU oracle leg across problem sizes: where does the
+    GPU stop paying off?  Each LP is solved by the library (FP32 to 1e-4, and
+    FP32 + FP64 polish to 1e-8) and by HiGHS interior point with crossover on
+    the host cores (stopped at a time limit)."""
+    from oracle.reference import highs_solve, host_threads
+    from paper_2607_03627_amd import uclp
+    from paper_2607_03627_amd.instances import make_instance
+
+    cases = [("tiny", 0, {}), ("medium", 0, {"n_periods": 12}), ("medium", 0, {}), ("large_kc0", 0, {}),
+             ("large", 0, {})]
+    rows = []
+    for shape, seed, kw in cases:
+        lp = make_instance(shape, seed, **kw)
+        r = {"case": f"{shape}/{seed}" + ("" if not kw else f" {kw}"), "rows": lp.m, "cols": lp.n, "nnz": lp.nnz}
+        for label, o in (("gpu_fp32_1e-4", dict(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-4)),
+                         ("gpu_polish_1e-8", dict(precision=uclp.UC_LP_FP32_MIXED_POLISH, eps_rel=1e-4,
+                                                  eps_polish=1e-8))):
+            t = time.perf_counter()
+            _, _, info = uclp.solve(lp, uclp.uc_lp_opts_default(**o), timeout_s=600)
+            r[label] = {"create_to_done_s": time.perf_counter() - t, "solve_s": info["t_total_s"],
+                        "status": info["status_name"], "iters": info["iters"], "pobj": info["pobj"]}
+        st, obj, _, _, secs = highs_solve(lp, "highs-ipm", time_limit=time_limit_s)
+        r["cpu_highs_ipm"] = {"s": secs, "status": st, "obj": obj, "finished": st == 0,
+                              "host_cores": host_threads()}
+        log(f"[bench] size sweep {r}")
+        rows.append(r)
+    return {"time_limit_s": time_limit_s, "cases": rows}
+
+
+def dual_form_leg():
+    """The same library on the LP and on its dual (paper_2607_03627_amd/
+    dual_form.py): time, iterations and objective of each form."""
+    from paper_2607_03627_amd import uclp
+    from paper_2607_03627_amd.dual_form import dual_form
+    from paper_2607_03627_amd.instances import make_instance
+
+    rows = []
+    for shape, seed in (("medium", 0), ("large_kc0", 0)):
+        lp = make_instance(shape, seed)
+        df = dual_form(lp)
+        r = {"case": f"{shape}/{seed}", "primal_size": [lp.m, lp.n, lp.nnz],
+             "dual_size": [df.lp.m, df.lp.n, df.lp.nnz], "oracle_obj": golden_objective(f"{shape}/{seed}")}
+        for form, L, sgn in (("primal", lp, 1.0), ("dual", df.lp, -1.0)):
+            for label, o in (("fp32_1e-4", dict(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-4)),
+                             ("polish_1e-8", dict(precision=uclp.UC_LP_FP32_MIXED_POLISH, eps_rel=1e-4,
+                                                  eps_polish=1e-8))):
+                _, _, info = uclp.solve(L, uclp.uc_lp_opts_default(**o), timeout_s=600)
+                r[f"{form}_{label}"] = {"solve_s": info["t_total_s"], "t_to_1e-4_s": info["t_to_eps_s"],
+                                        "status": info["status_name"], "iters": info["iters"],
+                                        "objective": sgn * info["pobj"]}
+        log(f"[bench] dual form {r}")
+        rows.append(r)
+    return {"cases": rows}
+
+
 def golden_objective(key):
     """The oracle's optimum of a seeded instance as stored by
     tests/golden/make_golden.py (None when not stored)."""
@@ -275,6 +331,8 @@ def main():
     ap.add_argument("--scenarios-full", action="store_true",
                     help="scenario leg with the cold batch and sequential FP32 solves")
     ap.add_argument("--race", action="store_true", help="also run the GPU-CPU race on five LPs")
+    ap.add_argument("--size-sweep", action="store_true", help="GPU vs CPU oracle across problem sizes")
+    ap.add_argument("--dual-form", action="store_true", help="the LP and its dual on the same library")
     ap.add_argument("--serving-streams", type=int, default=1,
                     help="batched serving over this many streams (latencies pooled for p50 / p99)")
     args = ap.parse_args()
@@ -461,6 +519,16 @@ def main():
             out["scenarios"] = scenario_leg(lp, full=args.scenarios_full)
         except Exception as e:
             out["scenarios"] = {"error": repr(e)}
+    if args.size_sweep:
+        try:
+            out["size_sweep"] = size_sweep_leg()
+        except Exception as e:
+            out["size_sweep"] = {"error": repr(e)}
+    if args.dual_form:
+        try:
+            out["dual_form"] = dual_form_leg()
+        except Exception as e:
+            out["dual_form"] = {"error": repr(e)}
     if args.race:
         try:
             out["race"] = race_leg(lp)

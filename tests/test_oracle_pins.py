@@ -565,3 +565,4 @@ def test_planted_sign_of_the_residual_cross_term_is_caught():
     A = sp.csr_matrix(np.array([[2.0]]))
     assert not math.isclose(flipped(A, np.zeros(1), np.zeros(1), np.ones(1), np.full(1, 3.0), 0.5, 0.25),
                             math.sqrt(50.0))
+
