@@ -142,11 +142,12 @@ def test_scenario_count_limits():
 
 def test_fp32_phase_compaction_equals_single_scenario_bitwise():
     # Four of eight scenarios are the 500-bus LP itself: warm-started at its
-    # FP64 optimum they stop at the first check, still in the FP32 phase, and
+    # FP64 optimum they meet 1e-4 at the first check, in the FP32 phase, and
     # the batch moves the other four (load / cost perturbations) to arrays of
-    # their own lanes while the FP32 phase goes on.  Short of 1e-6 their FP32
-    # iteration stalls and hands over to FP64, which finishes them.  A lane of
-    # each kind equals the same scenario solved as a batch of one, bit for bit.
+    # their own lanes while the FP32 phase goes on.  With a stall window of
+    # one check those four hand over to FP64 near the target, which finishes
+    # them.  A lane of each kind equals the same scenario solved as a batch of
+    # one, bit for bit.
     lp = make_instance("medium", 0)
     say("case medium 8 scenarios, FP32-phase compaction")
     xn, yn, info = uclp.solve(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=1e-8),
@@ -157,8 +158,8 @@ def test_fp32_phase_compaction_equals_single_scenario_bitwise():
     b = np.concatenate([np.tile(lp.b, (4, 1)), bs])
     lb = np.concatenate([np.tile(lp.lb, (4, 1)), ls])
     ub = np.concatenate([np.tile(lp.ub, (4, 1)), us])
-    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-6,
-                                                      fp32_stall_checks=2, iter_limit=200000))
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED, eps_rel=1e-4,
+                                                      fp32_stall_checks=1, iter_limit=200000))
     try:
         x, y, infos = uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, c, b, lb, ub, xn, yn)
         say("iters", [i.iters for i in infos], "fp64", [i.iters_fp64 for i in infos])
