@@ -392,6 +392,30 @@ int uc_lp_bench_half_steps(uc_lp* lp, int32_t precision, int32_t copies, int32_t
                            double* primal_us, double* dual_us, double* primal_bytes,
                            double* dual_bytes);
 
+/* Merge-path SpMV y = A x (the kernels of uc_spmv with UC_LP_SPMV_MERGEPATH)
+ * on caller-owned DEVICE arrays, allocating nothing: for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).
+ * row_ptr[m+1], col_idx[nnz] int32 and val[nnz], x[n], y[m] of the precision
+ * (UC_LP_FP64: double, UC_LP_FP32_MIXED: float, FP32 accumulation) are device
+ * (or managed) memory of `device`; the CSR must be valid (row_ptr[0] = 0,
+ * non-decreasing, row_ptr[m] = nnz, column indices in [0, n)): it is on the
+ * device and is not checked.  The kernels run on hip_stream (NULL: the null
+ * stream) and the call returns once they are enqueued; y is complete when
+ * the stream reaches them.  Same results, bit for bit, as uc_spmv on the
+ * same values.
+ * Scratch: a static 4 MiB array on each device (workgroup coordinates and
+ * carries, 20 bytes per 2,048 rows + entries), held until the process ends;
+ * m + nnz up to about 4.2e8.  Larger inputs: ENOTSUP, before any launch.  The
+ * kernels overwrite every scratch entry they read, so nothing needs clearing,
+ * but calls that overlap in time on one device (other streams, other host
+ * threads) share the scratch and race: serialize them.
+ * EINVAL: bad sizes, NULL or non-device pointers.  EHIP: launch failure.
+ * The caller's current device is restored on return. */
+int uc_spmv_merge_noalloc(int device, int32_t m, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                          const int32_t* col_idx, const void* val, const void* x, void* y,
+                          int32_t precision, void* hip_stream);
+
 /* Device stream-copy bandwidth in GB/s for `bytes` per buffer (calibration
  * of the roofline and of hardware traffic counters). */
 int uc_copy_bench(int device, size_t bytes, int32_t reps, double* gbps);

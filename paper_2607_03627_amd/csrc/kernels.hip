@@ -1350,9 +1350,6 @@ __global__ __launch_bounds__(kThreads) void k_spmv(const int* __restrict__ ptr, 
 // threads' carries (in a fixed order); a row that spans workgroups gets the
 // carries of the earlier workgroups added, in workgroup order, by a fix-up
 // kernel.  Every sum is formed in an order fixed by the matrix alone.
-constexpr int kMergeItems = 8;
-constexpr int kMergeTile = kThreads * kMergeItems;
-
 __device__ inline void merge_search(int64_t diag, const int* __restrict__ row_end, int m, int64_t nnz,
                                     int& row, int& k) {
   int lo = (int)max(diag - nnz, (int64_t)0);

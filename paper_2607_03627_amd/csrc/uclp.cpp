@@ -2185,6 +2185,109 @@ extern "C" int uc_lp_bench_half_steps(uc_lp* lp, int32_t precision, int32_t copi
 }
 
 // ---------------------------------------------------------------------------
+// merge-path SpMV on caller-owned device arrays, without allocation
+// ---------------------------------------------------------------------------
+
+// Scratch of the allocation-free SpMV (workgroup coordinates and carries of
+// the merge-path kernels): one static array per device, held until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is a stand-in, not a device address); it passes the device address
+// that hipGetSymbolAddress returns for each device, looked up once per device
+// with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxScratchDevices];
+
+// Device address of `scratch` on `device`, which must be current.
+static int scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(UC_LP_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return UC_LP_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Offsets of the merge-path scratch for nwg workgroups with vb-byte values:
+// coord[nwg + 1] (int2), carry_row[nwg], carry_val[nwg].
+static size_t merge_scratch_layout(int nwg, size_t vb, size_t* off_row, size_t* off_val) {
+  *off_row = align256((size_t)(nwg + 1) * sizeof(int2));
+  *off_val = align256(*off_row + (size_t)nwg * sizeof(int));
+  return *off_val + (size_t)nwg * vb;
+}
+
+// The memory behind p must be device (or managed) memory of `device`.
+static int check_device_pointer(const void* p, int device, const char* what) {
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof a);
+  const hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(UC_LP_EINVAL, "%s is not device memory (%s)", what, hipGetErrorString(e));
+  }
+  if (!(a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) || a.device != device)
+    return fail(UC_LP_EINVAL, "%s is not device memory of device %d (type %d, device %d)", what, device, (int)a.type,
+                a.device);
+  return UC_LP_OK;
+}
+
+extern "C" int uc_spmv_merge_noalloc(int device, int32_t m, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                                     const int32_t* col_idx, const void* val, const void* x, void* y,
+                                     int32_t precision, void* hip_stream) {
+  g_err.clear();
+  if (m < 1 || n < 1) return fail(UC_LP_EINVAL, "m=%d n=%d must be >= 1", m, n);
+  if (nnz < 0 || nnz > INT32_MAX) return fail(UC_LP_EINVAL, "nnz=%lld out of range", (long long)nnz);
+  if (!row_ptr || !x || !y || (nnz > 0 && (!col_idx || !val))) return fail(UC_LP_EINVAL, "NULL array");
+  if (precision != UC_LP_FP64 && precision != UC_LP_FP32_MIXED) return fail(UC_LP_ENOTSUP, "precision %d", precision);
+  const size_t vb = precision == UC_LP_FP64 ? 8 : 4;
+  const int64_t items = (int64_t)m + nnz;
+  const int64_t nwg64 = (items + kMergeTile - 1) / kMergeTile;
+  size_t off_row = 0, off_val = 0;
+  const size_t need = nwg64 < INT32_MAX ? merge_scratch_layout((int)nwg64, vb, &off_row, &off_val) : SIZE_MAX;
+  if (need > kNoAllocScratchBytes)
+    return fail(UC_LP_ENOTSUP, "m + nnz = %lld needs %zu bytes of scratch; the static scratch holds %zu bytes",
+                (long long)items, need, kNoAllocScratchBytes);
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(UC_LP_EHIP, "no HIP device");
+  if (device < 0 || device >= count || device >= kMaxScratchDevices)
+    return fail(UC_LP_EINVAL, "device %d of %d", device, count);
+  int prev = 0;
+  HIPOK(hipGetDevice(&prev));
+  HIPOK(hipSetDevice(device));
+  int rc = UC_LP_OK;
+  const void* ptrs[5] = {row_ptr, col_idx, val, x, y};
+  const char* names[5] = {"row_ptr", "col_idx", "val", "x", "y"};
+  for (int i = 0; i < 5 && rc == UC_LP_OK; ++i)
+    if (ptrs[i]) rc = check_device_pointer(ptrs[i], device, names[i]);
+  void* sp = nullptr;
+  if (rc == UC_LP_OK) rc = scratch_address(device, &sp);
+  if (rc == UC_LP_OK) {
+    char* base = (char*)sp;
+    int2* coord = (int2*)base;
+    int* crow = (int*)(base + off_row);
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (precision == UC_LP_FP64)
+      launch_spmv_merge64(row_ptr, col_idx, (const double*)val, (const double*)x, (double*)y, m, nnz, coord, crow,
+                          (double*)(base + off_val), s);
+    else
+      launch_spmv_merge32(row_ptr, col_idx, (const float*)val, (const float*)x, (float*)y, m, nnz, coord, crow,
+                          (float*)(base + off_val), s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = fail(UC_LP_EHIP, "merge-path launch: %s", hipGetErrorString(e));
+  }
+  (void)hipSetDevice(prev);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
 // scenario batches over one matrix
 // ---------------------------------------------------------------------------
 

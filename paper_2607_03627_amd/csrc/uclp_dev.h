@@ -194,8 +194,11 @@ void launch_spmv64(const int* ptr, const int* col, const double* val, const doub
                    const int* blk, int nblk, hipStream_t s);
 void launch_spmv32(const int* ptr, const int* col, const float* val, const float* x, float* y,
                    const int* blk, int nblk, hipStream_t s);
-// merge-path SpMV: nwg = merge_workgroups(m, nnz) workgroups; scratch of
-// coord[nwg + 1], carry_row[nwg], carry_val[nwg]
+// merge-path SpMV: kMergeItems merge items (row ends + entries) per thread,
+// kMergeTile per workgroup; nwg = merge_workgroups(m, nnz) workgroups and
+// scratch of coord[nwg + 1], carry_row[nwg], carry_val[nwg]
+constexpr int kMergeItems = 8;
+constexpr int kMergeTile = kThreads * kMergeItems;
 int merge_workgroups(int m, int64_t nnz);
 void launch_spmv_merge64(const int* ptr, const int* col, const double* val, const double* x,
                          double* y, int m, int64_t nnz, int2* coord, int* carry_row, double* carry_val,

@@ -68,7 +68,8 @@ EXPORTS = ["uc_lp_opts_default", "uc_engine_create", "uc_engine_destroy", "uc_lp
            "uc_lp_update_data", "uc_lp_solve", "uc_lp_status", "uc_lp_wait", "uc_lp_cancel",
            "uc_lp_get_solution", "uc_lp_destroy", "uc_lp_last_error", "uc_lp_solve_scenarios",
            "uc_lp_internal_dims", "uc_lp_get_transpose", "uc_lp_get_scaling", "uc_lp_debug_step",
-           "uc_lp_debug_iterate", "uc_lp_eval_kkt", "uc_spmv", "uc_spmv_bench", "uc_copy_bench", "uc_lp_bench_half_steps"]
+           "uc_lp_debug_iterate", "uc_lp_eval_kkt", "uc_spmv", "uc_spmv_bench", "uc_copy_bench", "uc_lp_bench_half_steps",
+           "uc_spmv_merge_noalloc"]
 
 _lib: Optional[C.CDLL] = None
 
@@ -111,11 +112,13 @@ def _sig(lib):
                                   C.c_int32, C.c_int32, C.c_int32, _D]
     lib.uc_copy_bench.argtypes = [C.c_int, C.c_size_t, C.c_int32, _D]
     lib.uc_lp_bench_half_steps.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _D, _D, _D, _D]
+    lib.uc_spmv_merge_noalloc.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32,
+                                          _P]
     for name in ("uc_engine_create", "uc_lp_create", "uc_lp_update_data", "uc_lp_solve", "uc_lp_status",
                  "uc_lp_wait", "uc_lp_cancel", "uc_lp_get_solution", "uc_lp_solve_scenarios",
                  "uc_lp_internal_dims", "uc_lp_get_transpose", "uc_lp_get_scaling", "uc_lp_debug_step",
                  "uc_lp_debug_iterate", "uc_lp_eval_kkt", "uc_spmv", "uc_spmv_bench", "uc_copy_bench",
-                 "uc_lp_bench_half_steps"):
+                 "uc_lp_bench_half_steps", "uc_spmv_merge_noalloc"):
         getattr(lib, name).restype = C.c_int
 
 
@@ -336,6 +339,15 @@ def uc_lp_bench_half_steps(h, precision=UC_LP_FP32_MIXED, copies=4, reps=64):
     v = [C.c_double() for _ in range(4)]
     _check(load().uc_lp_bench_half_steps(h, int(precision), int(copies), int(reps), *[C.byref(x) for x in v]))
     return dict(primal_us=v[0].value, dual_us=v[1].value, primal_bytes=v[2].value, dual_bytes=v[3].value)
+
+
+def uc_spmv_merge_noalloc(m, n, nnz, row_ptr, col_idx, val, x, y, precision=UC_LP_FP64, stream=None, device=0,
+                          raw=False):
+    """Device addresses (ints) of caller-owned arrays; stream: a hipStream_t
+    address or None.  raw=True returns the error code instead of raising."""
+    rc = load().uc_spmv_merge_noalloc(int(device), int(m), int(n), int(nnz), _P(row_ptr), _P(col_idx), _P(val),
+                                      _P(x), _P(y), int(precision), _P(stream) if stream else None)
+    return rc if raw else _check(rc)
 
 
 def uc_copy_bench(nbytes: int, reps: int = 20, device: int = 0) -> float:
