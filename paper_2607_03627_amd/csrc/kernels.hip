@@ -21,6 +21,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "check.h"
 #include "uclp_dev.h"
 
 namespace uclp {
@@ -318,6 +319,7 @@ __global__ __launch_bounds__(NT) void k_primal(const SlotDev* __restrict__ slots
   if (t < 0) return;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
+  if (!S.active[0]) return;  // frozen slot: finished or waiting for a precision switch
   const Vecs<T>& V = vecs<T>(S);
   const int r0 = tl.r0, r1 = tl.r1;
   const UCLP_GLOBAL unsigned short* rend = gld(S.t_end);
@@ -409,6 +411,7 @@ __global__ __launch_bounds__(NT) void k_dual(const SlotDev* __restrict__ slots,
   if (t < 0) return;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
+  if (!S.active[0]) return;
   const Vecs<T>& V = vecs<T>(S);
   const int r0 = tl.r0, r1 = tl.r1;
   const UCLP_GLOBAL unsigned short* rend = gld(S.a_end);
@@ -473,6 +476,7 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict
   if (t < 0) return;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
+  if (!S.active[0]) return;
   const Vecs<T>& V = vecs<T>(S);
   const int r0 = tl.r0, r1 = tl.r1;
   const int* __restrict__ ptr = S.a_ptr;
@@ -577,6 +581,7 @@ __global__ __launch_bounds__(kThreads) void k_kkt_cols(const SlotDev* __restrict
   if (t < 0) return;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
+  if (!S.active[0]) return;
   const Vecs<T>& V = vecs<T>(S);
   const int r0 = tl.r0, r1 = tl.r1;
   const int* __restrict__ col = S.t_col;
@@ -690,6 +695,7 @@ __global__ __launch_bounds__(kThreads) void k_finish_x(const SlotDev* __restrict
   if (t < 0) return;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
+  if (!S.active[0]) return;
   const Vecs<T>& V = vecs<T>(S);
   const double k = (double)(S.kfin + kk);
   const T w = (T)((k + 1.0) / (k + 2.0));
@@ -716,6 +722,7 @@ __global__ __launch_bounds__(kThreads) void k_finish_y(const SlotDev* __restrict
   if (t < 0) return;
   const Tile tl = tiles[t];
   const SlotDev& S = slots[tl.slot];
+  if (!S.active[0]) return;
   const Vecs<T>& V = vecs<T>(S);
   const double k = (double)(S.kfin + kk);
   const T w = (T)((k + 1.0) / (k + 2.0));
@@ -760,6 +767,35 @@ __global__ __launch_bounds__(kThreads) void k_promote_y(const SlotDev* __restric
     S.d.y0[i] = v;
     S.d.yhat[i] = v;
   }
+}
+
+// The engine's per-check decisions on the device: one thread per slot runs
+// the check of its run on the reduced scalars, then sets what the finish
+// kernel and the next epoch read (restart flag, Halpern index, steps).  A run
+// that ends, or whose FP32 phase ends, is frozen (active = 0) until the host
+// retires or switches it.
+__global__ void k_engine_check(SlotDev* __restrict__ slots, ChkState* __restrict__ chk,
+                               const ChkParams* __restrict__ prm, int nslots) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nslots) return;
+  SlotDev& S = slots[a];
+  if (!S.active[0]) return;
+  ChkState st = chk[a];
+  if (st.status != UC_LP_RUNNING) return;
+  const ChkParams p = prm[a];
+  const long long k0 = S.k0[0];
+  check_step(st, p, S.scal, 0, wall_clock64());
+  S.kfin = k0 + p.K - 1;  // the check step the finish kernel completes
+  S.restart[0] = st.restart;
+  S.k0[0] = st.k_inner;
+  S.tau[0] = st.eta / st.omega;
+  S.sigma[0] = st.eta * st.omega;
+  if (st.status != UC_LP_RUNNING || st.promote) S.active[0] = 0;
+  chk[a] = st;
+}
+
+__global__ void k_stamp(unsigned long long* t) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *t = wall_clock64();
 }
 
 // ---------------------------------------------------------------------------
@@ -1692,6 +1728,12 @@ void launch_finish(int prec, const SlotDev* slots, const Tile* ttiles, int nttil
     if (natiles > 0) k_finish_y<double><<<xcd_grid(natiles), kThreads, 0, s>>>(slots, atiles, natiles, kk);
   }
 }
+
+void launch_engine_check(SlotDev* slots, ChkState* chk, const ChkParams* prm, int nslots, hipStream_t s) {
+  if (nslots > 0) k_engine_check<<<nb(nslots, 64), 64, 0, s>>>(slots, chk, prm, nslots);
+}
+
+void launch_stamp(unsigned long long* t, hipStream_t s) { k_stamp<<<1, 64, 0, s>>>(t); }
 
 void launch_promote(const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
                     int natiles, int nscen, hipStream_t s) {

@@ -38,6 +38,7 @@
 #include <vector>
 
 #include "../../include/uc_lp.h"
+#include "check.h"
 #include "uclp_dev.h"
 
 using namespace uclp;
@@ -491,6 +492,7 @@ struct DevMem {
   Vecs<float> f;
   Vecs<double> d;
   SlotDev* slot_dev;  // device copy of this instance's descriptor
+  unsigned long long* tick;  // device clock stamp
 };
 
 static void carve(DevMem& D, const HostProblem& P, int ns) {
@@ -558,6 +560,7 @@ static void carve(DevMem& D, const HostProblem& P, int ns) {
   carve_vecs(A, D.f, n, m, ns);
   carve_vecs(A, D.d, n, m, ns);
   D.slot_dev = A.take<SlotDev>(1);
+  D.tick = A.take<unsigned long long>(1);
 }
 
 static size_t arena_bytes(const HostProblem& P, int ns) {
@@ -571,21 +574,9 @@ static size_t arena_bytes(const HostProblem& P, int ns) {
 // engine and instance
 // ---------------------------------------------------------------------------
 
-struct PdhgState {
-  int prec = 1;          // 1: FP32 phase, 0: FP64 phase
-  double eta = 0, omega = 1;
-  long long k_inner = 0;    // steps since the last restart
-  long long phase_total = 0;
-  long long iters = 0, iters64 = 0, restarts = 0;
-  bool r_start_set = false, r_prev_set = false;
-  double r_start = 0, r_prev = 0;
-  double t_start = 0;
-  double pw_int = 0;         // running sum of primal-weight errors
-  double best_kkt = 0;       // FP32 phase: best progress measure so far
-  long long best_check = 0;  // check index at which it was reached
-  long long checks = 0;
-  bool gap_phase = false;    // FP32 phase past the eps_rel milestone, closing the gap
-};
+// Epochs in flight: the worker enqueues epoch e + 1 before it reads the
+// status of epoch e, so the device never waits for the host between epochs.
+constexpr int kRing = 2;
 
 struct uc_engine {
   int device = 0;
@@ -599,25 +590,24 @@ struct uc_engine {
   std::deque<uc_lp*> queue;
   std::vector<uc_lp*> active;
   bool shutdown = false;
-  // d_slots already holds the next epoch's parameters of the current layout
-  // (uploaded with the last check's restart flags)
-  bool slots_current = false;
-  bool pending_upload = false;  // that upload was not followed by a sync
-  // device tables
+  // device tables of the current layout
+  bool layout_valid = false;  // false: rebuilt before the next epoch
   SlotDev* d_slots = nullptr;
   Tile* d_tiles = nullptr;
   size_t tile_cap = 0;
   int* d_ids = nullptr;
-  double* h_scal = nullptr;  // pinned, max_slots * kScal
-  double* d_scal = nullptr;  // device, max_slots * kScal (one copy per check)
-  double* d_red2 = nullptr;  // device, max_slots * kRedChunks * (RQ_N + CQ_N)
-  // tile layout of the current active set, rebuilt when the set or a
-  // precision changes
-  std::vector<std::pair<const uc_lp*, int>> layout;
+  double* d_scal = nullptr;   // device, max_slots * kScal (one copy per check)
+  double* d_red2 = nullptr;   // device, max_slots * kRedChunks * (RQ_N + CQ_N)
+  ChkState* d_chk = nullptr;  // device, max_slots: run state, advanced by the check kernel
+  ChkParams* d_prm = nullptr; // device, max_slots
+  ChkState* h_ring = nullptr; // pinned, kRing * max_slots: run state after each epoch
   size_t off_t0 = 0, off_a1 = 0, off_a0 = 0;
-  int nT1 = 0, nT0 = 0, nA1 = 0, nA0 = 0;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  SlotDev* h_slots = nullptr;  // pinned, max_slots; rewritten only after a sync
+  int nT1 = 0, nT0 = 0, nA1 = 0, nA0 = 0, K = 64;
+  bool timing = false;
+  hipEvent_t ring_ev[kRing] = {};
+  hipEvent_t tev[kRing][4] = {};  // start / stop of the timed primal and dual launch of each epoch
+  SlotDev* h_slots = nullptr;  // pinned, max_slots
+  double tick_rate = 0;        // device clock ticks per second
   std::string err;
 };
 
@@ -638,7 +628,12 @@ struct uc_lp {
   std::vector<double> warm_x, warm_y;  // internal space
   bool has_warm = false;
   std::vector<double> sol_x, sol_y;    // original space
-  PdhgState st;
+  ChkState chk;             // run state (the device's copy is ahead while epochs run)
+  ChkParams prm;
+  double t_start = 0;       // host clock at admission
+  double t_stamp = 0;       // host clock at the device clock stamp
+  uint64_t tick_start = 0;  // device clock when iterations start
+  int host_stop = 0;        // terminal status the host imposes (time limit, cancel)
   int slot = -1;
   double t_request = 0;
   double hs_bytes[2][2] = {{0, 0}, {0, 0}};  // [precision][primal, dual] per half-step launch
@@ -736,6 +731,7 @@ static SlotDev make_slot(const HostProblem& P, const DevMem& D, double gamma) {
   S.m_eq = P.m_eq;
   S.nscen = 1;
   S.gamma = gamma;
+  S.active[0] = 1;
   S.a_nblk = (int)P.a_blk.size() - 1;
   S.t_nblk = (int)P.t_blk.size() - 1;
   S.dr = D.dr;
@@ -857,7 +853,7 @@ static int setup_device(uc_lp* lp) {
   const double norm_est = std::pow(std::max(h[0], 0.0), 0.25);
   const double norm_bound = 1.0;
   const double cn = std::sqrt(h[1]), bn = std::sqrt(h[2]);
-  PdhgState& st = lp->st;
+  ChkState& st = lp->chk;
   st.eta = norm_bound > 0 ? lp->opts.step_scale / norm_bound : 1.0;
   st.omega = (cn > 0 && bn > 0) ? cn / bn : 1.0;
   {
@@ -916,13 +912,6 @@ static int fetch_solution(uc_lp* lp, int prec) {
 
 // ---- the KKT check: scalars -> info, restart / termination decisions -------
 
-struct CheckOut {
-  bool terminate = false;
-  int status = UC_LP_RUNNING;
-  bool restart = false;
-  bool promote = false;
-};
-
 static void kkt_scalars(const double* q, double offset, double norm_b, double norm_c, uc_lp_info& in) {
   const double rho_p = std::sqrt(std::max(q[RQ_RES2], 0.0));
   const double rho_d = std::sqrt(std::max(q[RQ_N + CQ_DRES2] + q[RQ_YNEG2], 0.0));
@@ -941,138 +930,70 @@ static void kkt_from_scalars(const uc_lp* lp, const double* q, uc_lp_info& in) {
   kkt_scalars(q, lp->P.obj_offset, lp->P.norm_b, lp->P.norm_c, in);
 }
 
-// One check of one PDHG run: KKT from the FP64 scalars, the eps milestone,
-// termination, and the restart / primal-weight decision.  `in` carries the
-// run's info between checks.
-static CheckOut check_core(PdhgState& st, const uc_lp_opts& o, const double* q, int K, double tnow,
-                           double offset, double norm_b, double norm_c, bool cancel, uc_lp_info& in) {
-  CheckOut out;
-  kkt_scalars(q, offset, norm_b, norm_c, in);
-  st.iters += K;
-  if (st.prec == 0) st.iters64 += K;
-  st.phase_total += K;
-  const long long k_end = st.k_inner + K;
-  const double dx2 = q[RQ_N + CQ_DX2], dy2 = q[RQ_DY2], cross = q[RQ_DYADX];
-  // ||z - T(z)||_P, P = [[I/tau, A_hat'], [A_hat, I/sigma]]: the metric of the PDHG step
-  const double rfp2 = st.omega / st.eta * dx2 + dy2 / (st.omega * st.eta) + 2.0 * cross;
-  const double rfp = std::sqrt(std::max(rfp2, 0.0));
-  in.fp_residual = rfp;
-  in.iters = st.iters;
-  in.iters_fp64 = st.iters64;
-  in.precision_now = st.prec == 1 ? UC_LP_FP32_MIXED : UC_LP_FP64;
-  in.t_total_s = tnow - st.t_start;
-  const bool feas_ok = o.eps_abs_feas <= 0 || in.abs_primal_inf <= o.eps_abs_feas;
-  const bool finite = std::isfinite(in.rel_kkt) && std::isfinite(rfp) && std::isfinite(in.pobj);
-  if (!finite) {
-    out.terminate = true;
-    out.status = UC_LP_NUMERICAL;
-  } else {
-    if (in.t_to_eps_s < 0 && in.rel_kkt <= o.eps_rel && feas_ok) {
-      in.t_to_eps_s = tnow - st.t_start;
-      in.pobj_at_eps = in.pobj;
-      in.rel_kkt_at_eps = in.rel_kkt;
-      in.rel_gap_at_eps = in.rel_gap;
-      in.iters_at_eps = st.iters;
-    }
-    const bool polish_mode = o.precision == UC_LP_FP32_MIXED_POLISH;
-    const bool polish_phase = polish_mode && st.prec == 0;
-    const double target = polish_phase ? o.eps_polish : o.eps_rel;
-    // outside the polish mode a returned point also closes the duality gap
-    const bool gap_rule = !polish_mode && o.eps_gap_rel > 0;
-    const bool gap_ok = !gap_rule || in.rel_gap <= o.eps_gap_rel;
-    if (in.rel_kkt <= target && feas_ok) {
-      if (polish_mode && st.prec == 1) {
-        out.promote = true;
-      } else if (gap_ok) {
-        out.terminate = true;
-        out.status = UC_LP_OPTIMAL;
-      }
-    }
-    // an FP32 phase that stopped improving continues in FP64.  Progress is
-    // the KKT error, and past the eps_rel milestone under the gap rule the
-    // larger of it and the gap, both relative to their targets
-    ++st.checks;
-    if (st.prec == 1 && !out.terminate && !out.promote) {
-      const bool continuing = gap_rule && in.t_to_eps_s >= 0;
-      const double err = continuing ? std::max(in.rel_kkt, in.rel_gap * (target / o.eps_gap_rel)) : in.rel_kkt;
-      if (continuing && !st.gap_phase) {
-        st.gap_phase = true;  // the progress measure changes: start its window afresh
-        st.best_check = 0;
-      }
-      if (st.best_check == 0 || err < 0.9 * st.best_kkt) {
-        st.best_kkt = err;
-        st.best_check = st.checks;
-      } else if (o.fp32_stall_checks > 0 && st.checks - st.best_check >= o.fp32_stall_checks &&
-                 (continuing || st.best_kkt <= 10.0 * target)) {
-        // a stall within a decade of the target (or of the gap past the
-        // milestone) is taken for the FP32 floor
-        out.promote = true;
-      }
-    }
-    if (!out.terminate && st.iters >= o.iter_limit) {
-      out.terminate = true;
-      out.status = UC_LP_ITER_LIMIT;
-    }
-    if (!out.terminate && in.t_total_s >= o.time_limit_s) {
-      out.terminate = true;
-      out.status = UC_LP_TIME_LIMIT;
-    }
-    if (!out.terminate && cancel) {
-      out.terminate = true;
-      out.status = UC_LP_CANCELLED;
-    }
+// The decision parameters of a run of `o` on the data P.
+static ChkParams make_params(const uc_lp_opts& o, const HostProblem& P) {
+  ChkParams p;
+  std::memset(&p, 0, sizeof p);
+  p.mode = o.precision;
+  p.K = o.kkt_every;
+  p.restart_to_current = o.restart_to_current;
+  p.fp32_stall_checks = o.fp32_stall_checks;
+  p.iter_limit = o.iter_limit;
+  p.eps_rel = o.eps_rel;
+  p.eps_polish = o.eps_polish;
+  p.eps_gap_rel = o.eps_gap_rel;
+  p.eps_abs_feas = o.eps_abs_feas;
+  p.restart_sufficient = o.restart_sufficient;
+  p.restart_necessary = o.restart_necessary;
+  p.restart_artificial = o.restart_artificial;
+  p.pw_smoothing = o.pw_smoothing;
+  p.pw_max_change = o.pw_max_change;
+  p.pw_integral = o.pw_integral;
+  p.pw_balance = o.precision == UC_LP_FP32_MIXED_POLISH ? o.pw_balance_polish : o.pw_balance;
+  p.norm_b = P.norm_b;
+  p.norm_c = P.norm_c;
+  p.obj_offset = P.obj_offset;
+  return p;
+}
+
+static ChkState fresh_state(int prec, double eta, double omega) {
+  ChkState c;
+  std::memset(&c, 0, sizeof c);
+  c.prec = prec;
+  c.status = UC_LP_RUNNING;
+  c.eta = eta;
+  c.omega = omega;
+  return c;
+}
+
+// Run state -> the fields of uc_lp_info it determines.
+static void info_from_state(const ChkState& c, uc_lp_info& in) {
+  in.precision_now = c.prec == 1 ? UC_LP_FP32_MIXED : UC_LP_FP64;
+  in.iters = c.iters;
+  in.iters_fp64 = c.iters64;
+  in.restarts = c.restarts;
+  in.pobj = c.pobj;
+  in.dobj = c.dobj;
+  in.rel_primal = c.rel_primal;
+  in.rel_dual = c.rel_dual;
+  in.rel_gap = c.rel_gap;
+  in.rel_kkt = c.rel_kkt;
+  in.abs_primal_inf = c.abs_primal_inf;
+  in.fp_residual = c.fp_residual;
+  in.omega = c.omega;
+  in.eta = c.eta;
+  if (c.eps_reached) {
+    in.pobj_at_eps = c.pobj_at_eps;
+    in.rel_kkt_at_eps = c.rel_kkt_at_eps;
+    in.rel_gap_at_eps = c.rel_gap_at_eps;
+    in.iters_at_eps = c.iters_at_eps;
   }
-  if (out.terminate) out.promote = false;
-  if (!out.terminate && !out.promote) {
-    if (!st.r_start_set) {
-      st.r_start = rfp;
-      st.r_start_set = true;
-    }
-    bool rs = rfp <= o.restart_sufficient * st.r_start;
-    if (!rs && rfp <= o.restart_necessary * st.r_start && st.r_prev_set && rfp > st.r_prev) rs = true;
-    if (!rs && (double)k_end >= o.restart_artificial * (double)st.phase_total) rs = true;
-    st.r_prev = rfp;
-    st.r_prev_set = true;
-    if (rs) {
-      const double dX = std::sqrt(std::max(q[RQ_N + CQ_DX0], 0.0));
-      const double dY = std::sqrt(std::max(q[RQ_DY0], 0.0));
-      const double th = o.pw_smoothing;
-      if (dX > 1e-10 && dY > 1e-10) {
-        // log w <- log w - th e - ki sum(e), e = log w - log(dY / dX)
-        const double e = std::log(st.omega) - std::log(dY / dX);
-        st.pw_int += e;
-        double lw = std::log(st.omega) - th * e - o.pw_integral * st.pw_int;
-        // residual balance: a primal residual above the dual one raises w
-        const double gb = o.precision == UC_LP_FP32_MIXED_POLISH ? o.pw_balance_polish : o.pw_balance;
-        if (gb > 0 && in.rel_primal > 0 && in.rel_dual > 0) lw += gb * std::log(in.rel_primal / in.rel_dual);
-        double w = std::exp(lw);
-        if (o.pw_max_change >= 1) w = std::min(std::max(w, st.omega / o.pw_max_change), st.omega * o.pw_max_change);
-        st.omega = w;
-      }
-      st.k_inner = 0;
-      st.r_start_set = false;
-      st.r_prev_set = false;
-      ++st.restarts;
-      out.restart = true;
-    } else {
-      st.k_inner = k_end;
-    }
-  }
-  if (out.promote) {
-    // the FP64 phase starts at (x_hat, y_hat) as after a restart
-    st.prec = 0;
-    st.k_inner = 0;
-    st.phase_total = 0;
-    st.r_start_set = false;
-    st.r_prev_set = false;
-  }
-  in.restarts = st.restarts;
-  in.omega = st.omega;
-  if (o.verbose)
-    fprintf(stderr, "[uclp] it %lld prec %s kkt %.2e (p %.1e d %.1e g %.1e) pobj %.10g omega %.3g rfp %.3e rs %lld\n",
-            st.iters, st.prec ? "fp32" : "fp64", in.rel_kkt, in.rel_primal, in.rel_dual, in.rel_gap, in.pobj,
-            st.omega, rfp, st.restarts);
-  return out;
+}
+
+static void print_check(const ChkState& c) {
+  fprintf(stderr, "[uclp] it %lld prec %s kkt %.2e (p %.1e d %.1e g %.1e) pobj %.10g omega %.3g rfp %.3e rs %lld\n",
+          (long long)c.iters, c.prec ? "fp32" : "fp64", c.rel_kkt, c.rel_primal, c.rel_dual, c.rel_gap, c.pobj,
+          c.omega, c.fp_residual, (long long)c.restarts);
 }
 
 // Algorithmic bytes of one non-check half-step launch with vb-byte values:
@@ -1095,10 +1016,15 @@ static void half_step_bytes(const HostProblem& P, int vb, bool full, double* pb,
   *db = d;
 }
 
-static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
-  uc_lp_info in = get_info(lp);
-  CheckOut out = check_core(lp->st, lp->opts, q, K, tnow, lp->P.obj_offset, lp->P.norm_b, lp->P.norm_c,
-                            lp->cancel.load(), in);
+// The instance's info after a check whose run state is c (the engine's
+// device clock dates the eps_rel milestone).
+static void publish_state(uc_engine* E, uc_lp* lp, const ChkState& c, double tnow) {
+  std::lock_guard<std::mutex> g(lp->mu);
+  uc_lp_info& in = lp->info;
+  info_from_state(c, in);
+  in.t_total_s = tnow - lp->t_start;
+  if (c.eps_reached && in.t_to_eps_s < 0 && E->tick_rate > 0)
+    in.t_to_eps_s = (lp->t_stamp - lp->t_start) + (double)(int64_t)(c.tick_at_eps - lp->tick_start) / E->tick_rate;
   // report the FP32 launches when there are any (an FP32 solve that hands
   // over to FP64 near its end still reports its FP32 kernels), with the
   // algorithmic bytes of that precision
@@ -1108,14 +1034,23 @@ static CheckOut process_check(uc_lp* lp, const double* q, int K, double tnow) {
     in.dual_kernel_us = 1e3 * lp->timed_dual_ms[tp] / lp->timed_n[tp];
     in.timed_launches = lp->timed_n[tp];
   }
-  const int bp = lp->timed_n[0] + lp->timed_n[1] > 0 ? tp : lp->st.prec;
+  const int bp = lp->timed_n[0] + lp->timed_n[1] > 0 ? tp : c.prec;
   in.primal_bytes = lp->hs_bytes[bp][0];
   in.dual_bytes = lp->hs_bytes[bp][1];
-  set_info(lp, in);
-  return out;
 }
 
 // ---- engine worker -----------------------------------------------------------
+//
+// The worker admits queued instances, builds the tile layout of the active
+// set and then runs epochs of K iterations with no host round-trip: each
+// epoch ends with the FP64 check kernels, a check kernel that takes every
+// instance's restart / primal-weight / termination decision on the device
+// (one thread per instance, state in d_chk), the finish kernels, and an
+// asynchronous copy of the run states into a pinned ring.  The next epoch is
+// already enqueued when the worker reads an epoch's states.  An instance
+// whose run ends (or that switches precision) is frozen by the check kernel,
+// so later launches skip its tiles; the worker then drains the stream and
+// retires, promotes and admits before it rebuilds the layout.
 
 static int engine_tables(uc_engine* E, size_t ntiles) {
   if (ntiles > E->tile_cap) {
@@ -1141,8 +1076,8 @@ static void worker_fail(uc_engine* E, uc_lp* lp) {
 
 static void start_instance(uc_engine* E, uc_lp* lp) {
   const double t0 = now_s();
-  lp->st = PdhgState();
-  lp->st.t_start = t0;
+  lp->t_start = t0;
+  lp->host_stop = 0;
   for (int p = 0; p < 2; ++p) {
     lp->timed_primal_ms[p] = lp->timed_dual_ms[p] = 0;
     lp->timed_n[p] = 0;
@@ -1168,10 +1103,22 @@ static void start_instance(uc_engine* E, uc_lp* lp) {
   int rc = UC_LP_OK;
   if (!lp->uploaded) rc = upload(lp);
   if (rc == UC_LP_OK) rc = setup_device(lp);
-  lp->st.prec = lp->opts.precision == UC_LP_FP64 ? 0 : 1;
+  const int prec = lp->opts.precision == UC_LP_FP64 ? 0 : 1;
+  lp->chk = fresh_state(prec, lp->chk.eta, lp->chk.omega);
+  lp->prm = make_params(lp->opts, lp->P);
   for (int p = 0; p < 2; ++p)
     half_step_bytes(lp->P, p ? 4 : 8, lp->opts.halpern_gamma == 1.0, &lp->hs_bytes[p][0], &lp->hs_bytes[p][1]);
-  if (rc == UC_LP_OK) rc = init_iterates(lp, lp->st.prec);
+  if (rc == UC_LP_OK) rc = init_iterates(lp, prec);
+  if (rc == UC_LP_OK) {
+    // device clock at the start of the iterations (the stream is idle here)
+    launch_stamp(lp->D.tick, E->stream);
+    unsigned long long tk = 0;
+    hipError_t e = hipMemcpyAsync(&tk, lp->D.tick, sizeof tk, hipMemcpyDeviceToHost, E->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(E->stream);
+    if (e != hipSuccess) rc = fail(UC_LP_EHIP, "clock stamp: %s", hipGetErrorString(e));
+    lp->tick_start = tk;
+    lp->t_stamp = now_s();
+  }
   if (rc != UC_LP_OK) {
     worker_fail(E, lp);
     return;
@@ -1179,13 +1126,15 @@ static void start_instance(uc_engine* E, uc_lp* lp) {
   {
     std::lock_guard<std::mutex> g(lp->mu);
     lp->info.t_setup_s = now_s() - t0;
-    lp->info.omega = lp->st.omega;
+    lp->info.omega = lp->chk.omega;
+    lp->info.eta = lp->chk.eta;
   }
   E->active.push_back(lp);
+  E->layout_valid = false;
 }
 
 static void retire(uc_engine* E, uc_lp* lp, int status) {
-  int rc = fetch_solution(lp, lp->st.prec);
+  int rc = fetch_solution(lp, lp->chk.prec);
   if (!E->private_engine) {
     release(lp);
     std::lock_guard<std::mutex> g(E->mu);
@@ -1193,178 +1142,208 @@ static void retire(uc_engine* E, uc_lp* lp, int status) {
   }
   {
     std::lock_guard<std::mutex> g(lp->mu);
-    lp->info.t_total_s = now_s() - lp->st.t_start;
+    lp->info.t_total_s = now_s() - lp->t_start;
   }
   if (rc != UC_LP_OK) worker_fail(E, lp);
   else finish_status(lp, status);
 }
 
-static void run_epochs(uc_engine* E) {
+static void fail_all(uc_engine* E, const char* what, hipError_t e) {
+  fail(UC_LP_EHIP, "%s: %s", what, hipGetErrorString(e));
+  for (auto* lp : E->active) worker_fail(E, lp);
+  E->active.clear();
+  E->layout_valid = false;
+}
+
+// Slot table, tiles, run states and parameters of the active set.  Called
+// with nothing in flight.
+static hipError_t build_layout(uc_engine* E) {
   hipStream_t s = E->stream;
-  // batch layout: slots 0..A-1 are the active instances in order
   const int A = (int)E->active.size();
   int K = 1 << 30;
-  for (auto* lp : E->active) K = std::min(K, lp->opts.kkt_every);
-  std::vector<std::pair<const uc_lp*, int>> sig(A);
-  for (int a = 0; a < A; ++a) sig[a] = {E->active[a], E->active[a]->st.prec + 2 * E->active[a]->data_gen};
-  // an unchanged batch continues on the parameters uploaded after its last
-  // check; otherwise the slot table is rebuilt from the instances' state
-  const bool same = sig == E->layout && E->slots_current;
-  if (!same) {
-    if (E->pending_upload) (void)hipStreamSynchronize(s);  // h_slots may still be read
-    E->pending_upload = false;
-    for (int a = 0; a < A; ++a) {
-      uc_lp* lp = E->active[a];
-      lp->slot = a;
-      SlotDev S = make_slot(lp);
-      S.scal = E->d_scal + (size_t)a * kScal;
-      S.tau[0] = lp->st.eta / lp->st.omega;
-      S.sigma[0] = lp->st.eta * lp->st.omega;
-      S.k0[0] = lp->st.k_inner;
-      S.restart[0] = 0;
-      S.active[0] = 1;
-      E->h_slots[a] = S;
-    }
+  bool timing = false;
+  for (auto* lp : E->active) {
+    K = std::min(K, lp->opts.kkt_every);
+    timing |= lp->opts.timing != 0;
   }
-  E->slots_current = false;
-  hipError_t e = hipSuccess;
+  E->K = K;
+  E->timing = timing;
+  std::vector<Tile> tt[2], at[2];
+  std::vector<int> ids(A);
+  std::vector<ChkState> chk(A);
+  std::vector<ChkParams> prm(A);
+  for (int a = 0; a < A; ++a) {
+    uc_lp* lp = E->active[a];
+    lp->slot = a;
+    ids[a] = a;
+    const int p = lp->chk.prec;
+    push_tiles(tt[p], a, lp->P.t_blk, lp->P.t_ptr, &lp->P.t_flag, &lp->P.t_base);
+    push_tiles(at[p], a, lp->P.a_blk, lp->P.a_ptr, &lp->P.a_flag, &lp->P.a_base);
+    SlotDev S = make_slot(lp);
+    S.scal = E->d_scal + (size_t)a * kScal;
+    S.tau[0] = lp->chk.eta / lp->chk.omega;
+    S.sigma[0] = lp->chk.eta * lp->chk.omega;
+    S.k0[0] = lp->chk.k_inner;
+    S.restart[0] = 0;
+    S.active[0] = 1;
+    E->h_slots[a] = S;
+    chk[a] = lp->chk;
+    prm[a] = lp->prm;
+    prm[a].K = K;
+  }
+  E->nT1 = (int)tt[1].size();
+  E->nT0 = (int)tt[0].size();
+  E->nA1 = (int)at[1].size();
+  E->nA0 = (int)at[0].size();
+  E->off_t0 = tt[1].size();
+  E->off_a1 = E->off_t0 + tt[0].size();
+  E->off_a0 = E->off_a1 + at[1].size();
+  const size_t total = E->off_a0 + at[0].size();
+  if (engine_tables(E, total) != UC_LP_OK) return hipErrorOutOfMemory;
   std::vector<Tile> all;
-  if (sig != E->layout) {
-    std::vector<Tile> tt[2], at[2];
-    std::vector<int> ids(A);
-    for (int a = 0; a < A; ++a) {
-      ids[a] = a;
-      const int p = E->active[a]->st.prec;
-      const HostProblem& Q = E->active[a]->P;
-      push_tiles(tt[p], a, Q.t_blk, Q.t_ptr, &Q.t_flag, &Q.t_base);
-      push_tiles(at[p], a, Q.a_blk, Q.a_ptr, &Q.a_flag, &Q.a_base);
-    }
-    E->nT1 = (int)tt[1].size();
-    E->nT0 = (int)tt[0].size();
-    E->nA1 = (int)at[1].size();
-    E->nA0 = (int)at[0].size();
-    E->off_t0 = tt[1].size();
-    E->off_a1 = E->off_t0 + tt[0].size();
-    E->off_a0 = E->off_a1 + at[1].size();
-    const size_t total = E->off_a0 + at[0].size();
-    if (engine_tables(E, total) != UC_LP_OK) {
-      for (auto* lp : E->active) worker_fail(E, lp);
-      E->active.clear();
-      E->layout.clear();
-      return;
-    }
-    all.reserve(total);
-    all.insert(all.end(), tt[1].begin(), tt[1].end());
-    all.insert(all.end(), tt[0].begin(), tt[0].end());
-    all.insert(all.end(), at[1].begin(), at[1].end());
-    all.insert(all.end(), at[0].begin(), at[0].end());
-    if (total) e = hipMemcpyAsync(E->d_tiles, all.data(), total * sizeof(Tile), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(E->d_ids, ids.data(), A * sizeof(int), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors die at scope end
-    E->layout = sig;
-  }
-  if (e == hipSuccess && !same)
-    e = hipMemcpyAsync(E->d_slots, E->h_slots, A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
+  all.reserve(total);
+  all.insert(all.end(), tt[1].begin(), tt[1].end());
+  all.insert(all.end(), tt[0].begin(), tt[0].end());
+  all.insert(all.end(), at[1].begin(), at[1].end());
+  all.insert(all.end(), at[0].begin(), at[0].end());
+  hipError_t e = hipSuccess;
+  if (total) e = hipMemcpyAsync(E->d_tiles, all.data(), total * sizeof(Tile), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(E->d_ids, ids.data(), A * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(E->d_slots, E->h_slots, A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(E->d_chk, chk.data(), A * sizeof(ChkState), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(E->d_prm, prm.data(), A * sizeof(ChkParams), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors die at scope end
+  E->layout_valid = e == hipSuccess;
+  return e;
+}
+
+// One epoch of K iterations over the active set, its check and the copy of
+// the run states into ring entry r.
+static void enqueue_epoch(uc_engine* E, int r) {
+  hipStream_t s = E->stream;
+  const int A = (int)E->active.size(), K = E->K;
   const Tile* T1 = E->d_tiles;
   const Tile* T0 = E->d_tiles + E->off_t0;
   const Tile* A1 = E->d_tiles + E->off_a1;
   const Tile* A0 = E->d_tiles + E->off_a0;
   const int nT1 = E->nT1, nT0 = E->nT0, nA1 = E->nA1, nA0 = E->nA0;
-  bool timing = false;
-  for (auto* lp : E->active) timing |= lp->opts.timing != 0;
-  for (int j = 0; j < K && e == hipSuccess; ++j) {
+  hipEvent_t* ev = E->tev[r];
+  for (int j = 0; j < K; ++j) {
     const bool check = j == K - 1;
-    // the middle iteration of an epoch (not the first launch after the host
-    // synchronisation, not the check) carries dispatch-attached timing events
-    // on the first non-empty precision group
-    const bool tj = timing && j == K / 2;
+    // the middle iteration carries dispatch-attached timing events on the
+    // first non-empty precision group
+    const bool tj = E->timing && j == K / 2;
     const bool t1 = tj && nT1 > 0, t0 = tj && nT1 == 0;
-    launch_primal(1, check, E->d_slots, T1, nT1, j, 1, s, t1 ? E->ev[0] : nullptr, t1 ? E->ev[1] : nullptr);
-    launch_primal(0, check, E->d_slots, T0, nT0, j, 1, s, t0 ? E->ev[0] : nullptr, t0 ? E->ev[1] : nullptr);
-    launch_dual(1, check, E->d_slots, A1, nA1, j, 1, s, t1 ? E->ev[2] : nullptr, t1 ? E->ev[3] : nullptr);
-    launch_dual(0, check, E->d_slots, A0, nA0, j, 1, s, t0 ? E->ev[2] : nullptr, t0 ? E->ev[3] : nullptr);
+    launch_primal(1, check, E->d_slots, T1, nT1, j, 1, s, t1 ? ev[0] : nullptr, t1 ? ev[1] : nullptr);
+    launch_primal(0, check, E->d_slots, T0, nT0, j, 1, s, t0 ? ev[0] : nullptr, t0 ? ev[1] : nullptr);
+    launch_dual(1, check, E->d_slots, A1, nA1, j, 1, s, t1 ? ev[2] : nullptr, t1 ? ev[3] : nullptr);
+    launch_dual(0, check, E->d_slots, A0, nA0, j, 1, s, t0 ? ev[2] : nullptr, t0 ? ev[3] : nullptr);
   }
   launch_kkt(1, E->d_slots, T1, nT1, A1, nA1, 1, s);
   launch_kkt(0, E->d_slots, T0, nT0, A0, nA0, 1, s);
   launch_reduce(E->d_slots, E->d_ids, A, 1, E->d_red2, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(E->h_scal, E->d_scal, (size_t)A * kScal * sizeof(double), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e == hipSuccess) e = hipGetLastError();
-  if (e != hipSuccess) {
-    fail(UC_LP_EHIP, "epoch failed: %s", hipGetErrorString(e));
-    for (auto* lp : E->active) worker_fail(E, lp);
-    E->active.clear();
-    E->layout.clear();
-    return;
-  }
-  if (timing) {
-    float t01 = 0, t12 = 0;
-    if (hipEventElapsedTime(&t01, E->ev[0], E->ev[1]) == hipSuccess &&
-        hipEventElapsedTime(&t12, E->ev[2], E->ev[3]) == hipSuccess) {
-      const int tp = nT1 > 0 ? 1 : 0;  // the group that carried the events
+  launch_engine_check(E->d_slots, E->d_chk, E->d_prm, A, s);
+  launch_finish(1, E->d_slots, T1, nT1, A1, nA1, 0, 1, s);
+  launch_finish(0, E->d_slots, T0, nT0, A0, nA0, 0, 1, s);
+  (void)hipMemcpyAsync(E->h_ring + (size_t)r * E->max_slots, E->d_chk, A * sizeof(ChkState), hipMemcpyDeviceToHost,
+                       s);
+  (void)hipEventRecord(E->ring_ev[r], s);
+}
+
+// Reads ring entry r (its epoch has completed): publishes every instance's
+// state and timing; true when the active set has to change (a run ended or
+// switches precision, the host stops one, a queued request fits, shutdown).
+static bool process_epoch(uc_engine* E, int r) {
+  const int A = (int)E->active.size();
+  const double tnow = now_s();
+  if (E->timing) {
+    float t01 = 0, t23 = 0;
+    if (hipEventElapsedTime(&t01, E->tev[r][0], E->tev[r][1]) == hipSuccess &&
+        hipEventElapsedTime(&t23, E->tev[r][2], E->tev[r][3]) == hipSuccess) {
+      const int tp = E->nT1 > 0 ? 1 : 0;  // the group that carried the events
       for (auto* lp : E->active)
         if (lp->opts.timing) {
           lp->timed_primal_ms[tp] += t01;
-          lp->timed_dual_ms[tp] += t12;
+          lp->timed_dual_ms[tp] += t23;
           ++lp->timed_n[tp];
         }
     }
   }
+  bool change = false;
+  for (int a = 0; a < A; ++a) {
+    uc_lp* lp = E->active[a];
+    const ChkState& c = E->h_ring[(size_t)r * E->max_slots + a];
+    publish_state(E, lp, c, tnow);
+    if (lp->opts.verbose) print_check(c);
+    if (c.status != UC_LP_RUNNING || c.promote) change = true;
+    if (lp->cancel.load()) {
+      lp->host_stop = UC_LP_CANCELLED;
+      change = true;
+    } else if (tnow - lp->t_start >= lp->opts.time_limit_s) {
+      lp->host_stop = UC_LP_TIME_LIMIT;
+      change = true;
+    }
+  }
+  std::lock_guard<std::mutex> g(E->mu);
+  if (E->shutdown) change = true;
+  if (!E->queue.empty() && (int)E->active.size() < E->max_slots &&
+      (E->private_engine || E->used + E->queue.front()->need_bytes <= E->budget))
+    change = true;
+  return change;
+}
+
+// Epochs until the active set has to change, then a drain: every instance's
+// device state is read back; finished runs retire, FP32 runs that reached
+// their hand-over switch to FP64 (promote kernels), host-stopped runs end.
+static void run_epochs(uc_engine* E) {
+  hipStream_t s = E->stream;
+  if (!E->layout_valid) {
+    const hipError_t e = build_layout(E);
+    if (e != hipSuccess) return fail_all(E, "layout upload", e);
+  }
+  long long issued = 0, done = 0;
+  bool change = false;
+  while (!change) {
+    while (issued - done < kRing) enqueue_epoch(E, (int)(issued++ % kRing));
+    const hipError_t e = hipEventSynchronize(E->ring_ev[done % kRing]);
+    if (e != hipSuccess) return fail_all(E, "epoch", e);
+    change = process_epoch(E, (int)(done++ % kRing));
+  }
+  const int A = (int)E->active.size();
+  std::vector<ChkState> chk(A);
+  hipError_t e = hipMemcpyAsync(chk.data(), E->d_chk, A * sizeof(ChkState), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail_all(E, "epoch", e);
   const double tnow = now_s();
-  std::vector<CheckOut> outs(A);
-  bool changed = false;
+  std::vector<Tile> pt, pa;
   for (int a = 0; a < A; ++a) {
     uc_lp* lp = E->active[a];
-    outs[a] = process_check(lp, E->h_scal + (size_t)a * kScal, K, tnow);
-    changed |= outs[a].terminate || outs[a].promote;
-    // one upload serves the finish kernel (restart decision, the check
-    // step's index) and the next epoch (its k0, tau, sigma)
-    SlotDev& S = E->h_slots[a];
-    S.restart[0] = outs[a].restart ? (lp->opts.restart_to_current ? 2 : 1) : 0;
-    S.kfin = S.k0[0] + K - 1;
-    S.k0[0] = lp->st.k_inner;
-    S.tau[0] = lp->st.eta / lp->st.omega;
-    S.sigma[0] = lp->st.eta * lp->st.omega;
-  }
-  e = hipMemcpyAsync(E->d_slots, E->h_slots, A * sizeof(SlotDev), hipMemcpyHostToDevice, s);
-  launch_finish(1, E->d_slots, T1, nT1, A1, nA1, 0, 1, s);
-  launch_finish(0, E->d_slots, T0, nT0, A0, nA0, 0, 1, s);
-  if (!changed && e == hipSuccess) {
-    // nothing leaves or switches precision: the next epoch follows on the
-    // stream without waiting for the finish kernels (the half-steps do not
-    // read the restart flag)
-    E->slots_current = true;
-    E->pending_upload = true;
-    return;
-  }
-  // precision switches: FP32 x_hat, y_hat -> FP64 iterates of the same slot
-  std::vector<Tile> pt, pa, both;
-  for (int a = 0; a < A; ++a)
-    if (outs[a].promote) {
-      push_tiles(pt, a, E->active[a]->P.t_blk, E->active[a]->P.t_ptr);
-      push_tiles(pa, a, E->active[a]->P.a_blk, E->active[a]->P.a_ptr);
+    lp->chk = chk[a];
+    publish_state(E, lp, chk[a], tnow);
+    if (lp->chk.status == UC_LP_RUNNING && lp->chk.promote && !lp->host_stop) {
+      // FP32 x_hat, y_hat -> FP64 iterates of the same slot
+      push_tiles(pt, a, lp->P.t_blk, lp->P.t_ptr);
+      push_tiles(pa, a, lp->P.a_blk, lp->P.a_ptr);
+      lp->chk.promote = 0;
     }
+  }
+  E->layout_valid = false;
   if (!pt.empty() || !pa.empty()) {
-    // reuse the tile buffer after the epoch's kernels (same stream, ordered)
-    both = pt;
+    std::vector<Tile> both = pt;
     both.insert(both.end(), pa.begin(), pa.end());
-    // the promote tiles overwrite the cached layout, which is rebuilt next epoch
-    E->layout.clear();
-    if (engine_tables(E, both.size()) == UC_LP_OK) {
-      (void)hipMemcpyAsync(E->d_tiles, both.data(), both.size() * sizeof(Tile), hipMemcpyHostToDevice, s);
-      launch_promote(E->d_slots, E->d_tiles, (int)pt.size(), E->d_tiles + pt.size(), (int)pa.size(), 1, s);
-    }
+    if (engine_tables(E, both.size()) != UC_LP_OK) return fail_all(E, "promote tiles", hipErrorOutOfMemory);
+    e = hipMemcpyAsync(E->d_tiles, both.data(), both.size() * sizeof(Tile), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) launch_promote(E->d_slots, E->d_tiles, (int)pt.size(), E->d_tiles + pt.size(), (int)pa.size(), 1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_all(E, "promote", e);
   }
-  (void)hipStreamSynchronize(s);
   std::vector<uc_lp*> keep;
-  for (int a = 0; a < A; ++a) {
-    uc_lp* lp = E->active[a];
-    if (outs[a].terminate) retire(E, lp, outs[a].status);
+  for (auto* lp : E->active) {
+    const int st = lp->chk.status != UC_LP_RUNNING ? lp->chk.status : lp->host_stop;
+    if (st != 0 && st != UC_LP_RUNNING) retire(E, lp, st);
     else keep.push_back(lp);
   }
-  // a retired handle's address may be reused by a later instance
-  if (keep.size() != E->active.size()) E->layout.clear();
   E->active.swap(keep);
 }
 
@@ -1415,11 +1394,19 @@ static int engine_init(uc_engine* E) {
   HIPOK(hipStreamCreate(&E->stream));
   HIPOK(hipMalloc(&E->d_slots, sizeof(SlotDev) * E->max_slots));
   HIPOK(hipMalloc(&E->d_ids, sizeof(int) * E->max_slots));
-  HIPOK(hipHostMalloc((void**)&E->h_scal, sizeof(double) * kScal * E->max_slots, hipHostMallocDefault));
   HIPOK(hipHostMalloc((void**)&E->h_slots, sizeof(SlotDev) * E->max_slots, hipHostMallocDefault));
+  HIPOK(hipHostMalloc((void**)&E->h_ring, sizeof(ChkState) * kRing * E->max_slots, hipHostMallocDefault));
   HIPOK(hipMalloc(&E->d_scal, sizeof(double) * kScal * E->max_slots));
   HIPOK(hipMalloc(&E->d_red2, sizeof(double) * kRedChunks * (RQ_N + CQ_N) * E->max_slots));
-  for (auto& ev : E->ev) HIPOK(hipEventCreate(&ev));
+  HIPOK(hipMalloc(&E->d_chk, sizeof(ChkState) * E->max_slots));
+  HIPOK(hipMalloc(&E->d_prm, sizeof(ChkParams) * E->max_slots));
+  for (int r = 0; r < kRing; ++r) {
+    HIPOK(hipEventCreate(&E->ring_ev[r]));
+    for (auto& ev : E->tev[r]) HIPOK(hipEventCreate(&ev));
+  }
+  int khz = 0;
+  HIPOK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, E->device));
+  E->tick_rate = 1e3 * (double)khz;
   E->worker = std::thread(worker_main, E);
   return UC_LP_OK;
 }
@@ -1433,15 +1420,16 @@ static void engine_free(uc_engine* E) {
   E->cv.notify_all();
   if (E->worker.joinable()) E->worker.join();
   (void)hipSetDevice(E->device);
-  if (E->d_slots) (void)hipFree(E->d_slots);
-  if (E->d_ids) (void)hipFree(E->d_ids);
-  if (E->d_tiles) (void)hipFree(E->d_tiles);
-  if (E->d_scal) (void)hipFree(E->d_scal);
-  if (E->d_red2) (void)hipFree(E->d_red2);
-  if (E->h_scal) (void)hipHostFree(E->h_scal);
+  for (void* p : {(void*)E->d_slots, (void*)E->d_ids, (void*)E->d_tiles, (void*)E->d_scal, (void*)E->d_red2,
+                  (void*)E->d_chk, (void*)E->d_prm})
+    if (p) (void)hipFree(p);
   if (E->h_slots) (void)hipHostFree(E->h_slots);
-  for (auto& ev : E->ev)
-    if (ev) (void)hipEventDestroy(ev);
+  if (E->h_ring) (void)hipHostFree(E->h_ring);
+  for (int r = 0; r < kRing; ++r) {
+    if (E->ring_ev[r]) (void)hipEventDestroy(E->ring_ev[r]);
+    for (auto ev : E->tev[r])
+      if (ev) (void)hipEventDestroy(ev);
+  }
   if (E->stream) (void)hipStreamDestroy(E->stream);
   delete E;
 }
@@ -1619,7 +1607,7 @@ extern "C" int uc_lp_status(const uc_lp* lp, uc_lp_info* out) {
   if (!lp || !out) return fail(UC_LP_EINVAL, "NULL argument");
   *out = get_info(lp);
   out->status = lp->status.load();
-  if (out->status == UC_LP_RUNNING && lp->st.t_start > 0) out->t_total_s = now_s() - lp->st.t_start;
+  if (out->status == UC_LP_RUNNING && lp->t_start > 0) out->t_total_s = now_s() - lp->t_start;
   return UC_LP_OK;
 }
 
@@ -1787,7 +1775,7 @@ static int debug_iterate_t(uc_lp* lp, int iters, int threads, const double* x, c
   std::vector<Tile> tl;
   push_tiles(tl, 0, P.t_blk, P.t_ptr, &P.t_flag, &P.t_base);
   push_tiles(tl, 0, P.a_blk, P.a_ptr, &P.a_flag, &P.a_base);
-  E->layout.clear();  // the engine's tile and slot tables are overwritten below
+  E->layout_valid = false;  // the engine's tile and slot tables are overwritten below
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(E->d_tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
@@ -1876,7 +1864,7 @@ extern "C" int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp
   std::vector<Tile> tl;
   push_tiles(tl, 0, P.t_blk, P.t_ptr, &P.t_flag, &P.t_base);
   push_tiles(tl, 0, P.a_blk, P.a_ptr, &P.a_flag, &P.a_base);
-  E->layout.clear();  // the engine's tile and slot tables are overwritten below
+  E->layout_valid = false;  // the engine's tile and slot tables are overwritten below
   if ((rc = engine_tables(E, tl.size()))) return rc;
   HIPOK(hipMemcpyAsync(E->d_slots, &S, sizeof S, hipMemcpyHostToDevice, s));
   HIPOK(hipMemcpyAsync(E->d_tiles, tl.data(), tl.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
@@ -2132,8 +2120,8 @@ extern "C" int uc_lp_bench_half_steps(uc_lp* lp, int32_t precision, int32_t copi
     Dc.ar.bytes = bytes;
     carve(Dc, P, 1);
     SlotDev S = make_slot(P, Dc, lp->opts.halpern_gamma);
-    S.tau[0] = lp->st.eta / lp->st.omega;
-    S.sigma[0] = lp->st.eta * lp->st.omega;
+    S.tau[0] = lp->chk.eta / lp->chk.omega;
+    S.sigma[0] = lp->chk.eta * lp->chk.omega;
     S.k0[0] = 0;
     S.active[0] = 1;
     slots[c] = S;
@@ -2454,7 +2442,8 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   if (mi) SCEN_HIP(hipMemcpyAsync(dr.data(), base->D.dr, 8 * mi, hipMemcpyDeviceToHost, st));
   SCEN_HIP(hipMemcpyAsync(dc.data(), base->D.dc, 8 * ni, hipMemcpyDeviceToHost, st));
   SCEN_HIP(hipStreamSynchronize(st));
-  std::vector<PdhgState> ps(S);
+  std::vector<ChkState> ps(S);
+  std::vector<ChkParams> pp(S);
   std::vector<uc_lp_info> inf(S);
   std::vector<int> done(S, 0), status(S, UC_LP_RUNNING);
   const double t0 = now_s();
@@ -2468,10 +2457,9 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   });
   for (int s = 0; s < S; ++s) {
     const double cn = cnorm[s], bn = bnorm[s];
-    ps[s].eta = base->st.eta;
-    ps[s].omega = (cn > 0 && bn > 0) ? std::sqrt(cn) / std::sqrt(bn) : 1.0;
-    ps[s].prec = o.precision == UC_LP_FP64 ? 0 : 1;
-    ps[s].t_start = t0;
+    ps[s] = fresh_state(o.precision == UC_LP_FP64 ? 0 : 1, base->chk.eta,
+                        (cn > 0 && bn > 0) ? std::sqrt(cn) / std::sqrt(bn) : 1.0);
+    pp[s] = make_params(o, SP[s]);
     std::memset(&inf[s], 0, sizeof inf[s]);
     inf[s].t_to_eps_s = -1;
     const uc_lp_info bi = get_info(base);
@@ -2709,13 +2697,20 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
     for (int L = 0; L < SL; ++L) {
       const int s = lane[L];
       if (done[s]) continue;
-      CheckOut out = check_core(ps[s], o, &q[(size_t)L * kScal], K, tnow, SP[s].obj_offset, SP[s].norm_b,
-                                SP[s].norm_c, base->cancel.load(), inf[s]);
-      SD.restart[L] = out.restart ? (o.restart_to_current ? 2 : 1) : 0;
-      if (out.terminate) {
+      const bool had_eps = ps[s].eps_reached != 0;
+      int32_t stop = 0;
+      if (base->cancel.load()) stop = UC_LP_CANCELLED;
+      else if (tnow - t0 >= o.time_limit_s) stop = UC_LP_TIME_LIMIT;
+      check_step(ps[s], pp[s], &q[(size_t)L * kScal], stop, 0);
+      info_from_state(ps[s], inf[s]);
+      inf[s].t_total_s = tnow - t0;
+      if (!had_eps && ps[s].eps_reached) inf[s].t_to_eps_s = tnow - t0;
+      if (o.verbose) print_check(ps[s]);
+      SD.restart[L] = ps[s].restart;
+      if (ps[s].status != UC_LP_RUNNING) {
         done[s] = 1;
-        status[s] = out.status;
-      } else if (out.promote) {
+        status[s] = ps[s].status;
+      } else if (ps[s].promote) {
         done[s] = 2;  // waits, frozen, for the other scenarios of this phase
       }
     }

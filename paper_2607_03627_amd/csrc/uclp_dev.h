@@ -145,6 +145,11 @@ void launch_finish(int prec, const SlotDev* slots, const Tile* ttiles, int nttil
                    const Tile* atiles, int natiles, int kk, int nscen, hipStream_t s);
 void launch_promote(const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
                     int natiles, int nscen, hipStream_t s);
+// the engine's check of every active slot (check.h), and a device clock stamp
+struct ChkState;
+struct ChkParams;
+void launch_engine_check(SlotDev* slots, ChkState* chk, const ChkParams* prm, int nslots, hipStream_t s);
+void launch_stamp(unsigned long long* t, hipStream_t s);
 
 // scenario batches (nscen <= kMaxScen interleaved scenarios in slot 0)
 void launch_primal_ms(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles, int jiter,
