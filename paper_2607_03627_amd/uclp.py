@@ -122,9 +122,13 @@ def _sig(lib):
         getattr(lib, name).restype = C.c_int
 
 
-def load(path: str = LIB_PATH) -> C.CDLL:
-    """Load the built library; raises if it is missing (build it first)."""
+def load(path: str = None) -> C.CDLL:
+    """Load the built library; raises if it is missing (build it first).
+    UCLP_LIB in the environment names another build of it (the host
+    sanitizer build the CPU tests run against)."""
     global _lib
+    if path is None:
+        path = os.environ.get("UCLP_LIB", LIB_PATH)
     if _lib is None:
         if not os.path.exists(path):
             raise RuntimeError(f"libuclp not built: {path} is missing "

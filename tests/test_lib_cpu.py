@@ -156,3 +156,25 @@ def test_null_handles_are_safe():
     lib.uc_engine_destroy(None)
     assert lib.uc_lp_cancel(None) == uclp.UC_LP_EINVAL
     assert lib.uc_lp_status(None, None) == uclp.UC_LP_EINVAL
+
+
+def test_valid_lps_pass_validation_and_presolve():
+    # valid inputs of every column / row kind go through validation, the
+    # minimal presolve (fixed columns, empty rows, 'L' rows) and the row-block
+    # and tile construction on the host; without a GPU the call then fails at
+    # the device, with one it succeeds
+    lp = make_instance("tiny", 1, n_periods=3)
+    lb, ub = lp.lb.copy(), lp.ub.copy()
+    ub[::7] = np.inf
+    lb[1::7] = -np.inf
+    lb[2::11] = ub[2::11] = np.clip(0.0, lp.lb[2::11], lp.ub[2::11])   # fixed columns
+    sense = lp.sense.copy()
+    sense[5::9] = ord("L")
+    variants = [lp, lp.with_data(lb=lb, ub=ub), LP(m=lp.m, n=lp.n, row_ptr=lp.row_ptr, col_idx=lp.col_idx,
+                                                     val=lp.val, c=lp.c, b=-lp.b, sense=sense, lb=lp.lb, ub=lp.ub)]
+    for v in variants:
+        rc, h = uclp.uc_lp_create(v, raw=True)
+        if rc == uclp.UC_LP_OK:
+            uclp.uc_lp_destroy(h)
+        else:
+            assert rc == uclp.UC_LP_EHIP and "device" in uclp.uc_lp_last_error()
