@@ -478,6 +478,19 @@ def main():
                                 "pobj": i64[0]["pobj"], "primal_us": i64[0]["primal_kernel_us"],
                                 "dual_us": i64[0]["dual_kernel_us"],
                                 "obj_err_vs_oracle": abs(i64[0]["pobj"] - zstar) / abs(zstar) if zstar else None}
+            # FP32 to 1e-4, then FP64 to 5e-6: the returned point whose objective
+            # matches the oracle's optimum within 1e-6
+            h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED_POLISH,
+                                                               eps_rel=1e-4, eps_polish=5e-6))
+            try:
+                wq, iq = run(h, 1, "polish5e-6")
+            finally:
+                uclp.uc_lp_destroy(h)
+            ex["returned_point_polish_5e-6"] = {
+                "wall_s": wq[0], "t_to_1e-4_s": iq[0]["t_to_eps_s"], "solve_s": iq[0]["t_total_s"],
+                "iters": iq[0]["iters"], "iters_fp64": iq[0]["iters_fp64"], "status": iq[0]["status_name"],
+                "rel_kkt": iq[0]["rel_kkt"], "pobj": iq[0]["pobj"],
+                "obj_err_vs_oracle": abs(iq[0]["pobj"] - zstar) / abs(zstar) if zstar else None}
             # FP32 + FP64 polish to 1e-8
             h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED_POLISH,
                                                                eps_rel=1e-4, eps_polish=1e-8))

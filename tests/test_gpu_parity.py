@@ -354,20 +354,21 @@ def test_full_size_solve_in_the_benchmark_configuration():
 
 def test_full_size_objective_matches_oracle():
     # The 1e-4 point of the benchmark is ~2e-5 away from the optimum in
-    # objective; FP32 to 1e-4 followed by FP64 to 1e-5 relative KKT returns a
-    # point whose objective matches the oracle's optimum of this LP within
-    # 1e-6 (within the paper's 100,000-iteration limit)
+    # objective, and at 1e-5 relative KKT the FP64 iterates of this LP were
+    # still 5e-7 - 2e-6 away; FP32 to 1e-4 followed by FP64 to 5e-6 returns a
+    # point whose objective matches the oracle's optimum within 1e-6 (inside
+    # the paper's 100,000-iteration limit)
     lp, _ = full_size_case()
     if "large/0" not in GOLDEN:
         pytest.skip("no stored oracle objective for the 6,049-bus LP (tests/golden/make_golden.py --large)")
     z = GOLDEN["large/0"]["obj"]
     say("case large 0 objective")
-    x, y, info = solve(lp, precision=uclp.UC_LP_FP32_MIXED_POLISH, eps_rel=1e-4, eps_polish=1e-5)
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP32_MIXED_POLISH, eps_rel=1e-4, eps_polish=5e-6)
     assert info["status"] == uclp.UC_LP_OPTIMAL, info
     k = kkt(lp, x, y)
     say("  oracle", z, "returned", k.pobj, abs(k.pobj - z) / abs(z), "at 1e-4", info["pobj_at_eps"],
         abs(info["pobj_at_eps"] - z) / abs(z), "iters", info["iters"], info["iters_fp64"], info["t_total_s"])
-    assert k.rel_kkt <= 1e-5 * 1.001
+    assert k.rel_kkt <= 5e-6 * 1.001
     assert abs(k.pobj - z) <= 1e-6 * abs(z)
 
 
@@ -691,3 +692,28 @@ def test_update_data_and_infeasible_empty_row():
              b=np.append(lp.b, 1.0), sense=np.append(lp.sense, ord("E")).astype(np.uint8), lb=lp.lb, ub=lp.ub)
     x, y, info = solve(bad)
     assert info["status"] == uclp.UC_LP_INFEASIBLE
+
+
+# ---------------------------------------------------------------------------
+# crossover from the PDHG point to a vertex
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_crossover_from_the_pdhg_point_reaches_the_oracle_optimum(seed):
+    # the library's FP32 + FP64-polish point (rel. KKT 1e-8) of the 30-bus
+    # grid, then crossover on the host: an optimal vertex whose objective is
+    # the oracle's optimum
+    from paper_2607_03627_amd.crossover import crossover
+
+    lp = make_instance("tiny", seed)
+    say("case crossover", seed)
+    z = GOLDEN[f"tiny/{seed}"]["obj"]
+    x, y, info = solve(lp, precision=uclp.UC_LP_FP32_MIXED_POLISH, eps_polish=1e-8)
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    r = crossover(lp, x, y)
+    say("  ", r.status, r.obj, z, "pivots", r.pivots, r.phase1_pivots, "candidates", r.candidates, r.seconds)
+    assert r.status == "optimal"
+    assert abs(r.obj - z) <= 1e-9 * abs(z)
+    k = kkt(lp, r.x, r.y)
+    assert k.rel_kkt <= 1e-9
+    assert np.all(r.x >= lp.lb - 1e-9) and np.all(r.x <= lp.ub + 1e-9)
