@@ -88,27 +88,81 @@ def measured_traffic(kernel="k_primal"):
     return rec.get(kernel, {}).get("traffic_bytes")
 
 
-def cpu_baseline(lp, time_limit_s=25.0):
-    """The oracle (HiGHS interior point through oracle/reference.py) on the
-    workload itself, stopped at a time limit: the measured time if it
-    finishes, else a lower bound on its time to solve."""
-    from oracle.reference import highs_solve, host_threads
+def _cpu_baseline_child(workload, seed, time_limit_s, q):
+    """Child process of cpu_baseline: builds the workload and runs the oracle
+    on it, then reports status, wall and CPU seconds of the solve."""
+    from oracle.reference import highs_solve
+    from paper_2607_03627_amd.instances import make_instance
 
+    lp = make_instance(workload, seed)
+    q.put(("start", time.perf_counter()))
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
-    st, obj, x, y, highs_s = highs_solve(lp, "highs-ipm", time_limit=time_limit_s)
+    st = highs_solve(lp, "highs-ipm", time_limit=time_limit_s)[0]
     wall = time.perf_counter() - t0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    q.put(("done", int(st), wall, (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)))
+
+
+def cpu_baseline(lp, workload, seed, time_limit_s=25.0, hard_limit_s=60.0):
+    """The oracle (HiGHS interior point through oracle/reference.py) on the
+    workload itself, in a child process: the measured time if it finishes,
+    else a lower bound.  HiGHS checks its own time limit only between
+    iterations, so the child is also stopped at a hard wall-clock limit."""
+    import multiprocessing as mp
+    import queue as _queue
+
+    from oracle.reference import host_threads
+
+    ctx = mp.get_context("spawn")
+    q = ctx.Queue()
+    ru0 = resource.getrusage(resource.RUSAGE_CHILDREN)
+    proc = ctx.Process(target=_cpu_baseline_child, args=(workload, seed, time_limit_s, q), daemon=True)
+    proc.start()
+    t_start, res = None, None
+    t_spawn = time.perf_counter()
+    last_log = t_spawn
+    while True:
+        try:
+            msg = q.get(timeout=1.0)
+            if msg[0] == "start":
+                t_start = time.perf_counter()
+            else:
+                res = msg
+                break
+        except _queue.Empty:
+            pass
+        now = time.perf_counter()
+        if now - last_log >= 15.0:
+            log(f"[bench] cpu_baseline: oracle running for {now - (t_start or t_spawn):.0f} s")
+            last_log = now
+        if t_start is not None and now - t_start >= hard_limit_s:
+            break
+        if not proc.is_alive() and q.empty():
+            break
+    stopped = res is None
+    if stopped and proc.is_alive():
+        proc.kill()
+    proc.join(30)
+    if res is not None:
+        st, wall, cpu = res[1], res[2], res[3]
+    else:
+        st = None
+        wall = time.perf_counter() - (t_start or t_spawn)
+        ru1 = resource.getrusage(resource.RUSAGE_CHILDREN)
+        cpu = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
     done = st == 0
+    how = ("finished" if done else
+           f"stopped at the {hard_limit_s:.0f} s wall-clock limit, value is a lower bound" if stopped else
+           f"status {st}, not finished, value is a lower bound")
     return {
         "value": wall, "unit": "s", "cores": max(1, round(cpu / max(wall, 1e-9))), "kind": "oracle",
         "bound": "measured" if done else "lower",
         "host_cores": host_threads(),
         "sample": (f"HiGHS interior point with crossover (oracle/reference.py) on the workload itself "
                    f"({lp.m} rows, {lp.n} cols, {lp.nnz} nnz), model set-up included, HiGHS time limit "
-                   f"{time_limit_s:.0f} s: status {st}, {'finished' if done else 'not finished, value is a lower bound'}; "
-                   f"{wall:.1f} s wall, {cpu:.1f} s CPU ({host_threads()} host cores available)"),
+                   f"{time_limit_s:.0f} s, hard limit {hard_limit_s:.0f} s: {how}; {wall:.1f} s wall, "
+                   f"{cpu:.1f} s CPU ({host_threads()} host cores available)"),
     }
 
 
@@ -128,7 +182,8 @@ def serving_leg(seed=0, n_requests=64, eps=1e-8, iter_limit=400000, extra_stream
            "rows": [lp.m for lp in lps], "nnz_total": int(sum(lp.nnz for lp in lps))}
     ob = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_MIXED_POLISH, eps_rel=1e-4, eps_polish=eps,
                                  iter_limit=iter_limit)
-    rb = serving.run_stream(lps, arr, ob, max_slots=64, hbm_budget_bytes=200 << 30)
+    rb = serving.run_stream(lps, arr, ob, max_slots=64, hbm_budget_bytes=200 << 30,
+                            progress=lambda m: log(f"[bench] serving batched: {m}"))
     out["batched_fp32_polish"] = rb.stats
     log(f"[bench] serving batched: {rb.stats}")
     if extra_streams > 0:
@@ -136,14 +191,16 @@ def serving_leg(seed=0, n_requests=64, eps=1e-8, iter_limit=400000, extra_stream
         for sd in range(seed + 1, seed + 1 + extra_streams):
             rq = serving_stream(sd, n_requests)
             r = serving.run_stream([make_instance(q.shape, q.seed) for q in rq], [q.arrival_s for q in rq], ob,
-                                   max_slots=64, hbm_budget_bytes=200 << 30)
+                                   max_slots=64, hbm_budget_bytes=200 << 30,
+                                   progress=lambda m: log(f"[bench] serving stream {sd}: {m}"))
             log(f"[bench] serving batched stream {sd}: {r.stats}")
             more.append(r)
         out["batched_pooled"] = serving.pooled_latency(more)
         out["batched_pooled"]["streams"] = len(more)
         out["batched_pooled"]["solves_per_s_by_stream"] = [r.stats["solves_per_s"] for r in more]
     of = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=eps, iter_limit=iter_limit)
-    rf = serving.run_stream(lps, arr, of, max_slots=1, hbm_budget_bytes=200 << 30)
+    rf = serving.run_stream(lps, arr, of, max_slots=1, hbm_budget_bytes=200 << 30,
+                            progress=lambda m: log(f"[bench] serving fp64 fifo: {m}"))
     out["fp64_one_at_a_time"] = rf.stats
     log(f"[bench] serving fp64 fifo: {rf.stats}")
     out["throughput_ratio"] = rb.stats["solves_per_s"] / rf.stats["solves_per_s"]
@@ -549,7 +606,7 @@ def main():
             out["race"] = {"error": repr(e)}
     if not args.no_cpu:
         try:
-            out["cpu_baseline"] = cpu_baseline(lp)
+            out["cpu_baseline"] = cpu_baseline(lp, args.workload, args.seed)
         except Exception as e:
             out["cpu_baseline"] = {"value": None, "error": repr(e)}
     print(json.dumps(out), flush=True)

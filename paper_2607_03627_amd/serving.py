@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import time
 from dataclasses import dataclass, field
-from typing import List, Optional, Sequence
+from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
@@ -57,8 +57,11 @@ def nearest_rank(values: Sequence[float], q: float) -> float:
 
 def run_stream(lps: Sequence, arrivals_s: Sequence[float], opts: uclp.uc_lp_opts, *,
                max_slots: int = 64, hbm_budget_bytes: int = 200 << 30, keep_solutions: bool = False,
-               poll_s: float = 0.0005, device: int = 0, timeout_s: float = 600.0) -> StreamResult:
-    """Serve `lps` arriving at `arrivals_s` (seconds from start) on one engine."""
+               poll_s: float = 0.0005, device: int = 0, timeout_s: float = 600.0,
+               progress: Optional[Callable[[str], None]] = None, progress_every_s: float = 15.0) -> StreamResult:
+    """Serve `lps` arriving at `arrivals_s` (seconds from start) on one engine.
+    progress, if given, receives a one-line count of finished requests at
+    most every progress_every_s seconds."""
     order = np.argsort(np.asarray(arrivals_s), kind="stable")
     eng = uclp.uc_engine_create(device, int(hbm_budget_bytes), int(max_slots))
     handles = {}
@@ -68,6 +71,7 @@ def run_stream(lps: Sequence, arrivals_s: Sequence[float], opts: uclp.uc_lp_opts
     sols = {}
     try:
         t0 = time.perf_counter()
+        last_report = t0
         nxt = 0
         while len(done) < len(lps):
             now = time.perf_counter() - t0
@@ -91,6 +95,9 @@ def run_stream(lps: Sequence, arrivals_s: Sequence[float], opts: uclp.uc_lp_opts
                         sols[i] = uclp.uc_lp_get_solution(h, lps[i].n, lps[i].m)
                     uclp.uc_lp_destroy(h)
                     handles[i] = None
+            if progress is not None and time.perf_counter() - last_report >= progress_every_s:
+                last_report = time.perf_counter()
+                progress(f"{len(done)}/{len(lps)} requests finished after {last_report - t0:.0f} s")
             if len(done) < len(lps):
                 wait = poll_s
                 if nxt < len(order) and not any(h for h in handles.values()):
