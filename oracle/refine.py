@@ -35,9 +35,11 @@ and a simplex, whose points are exactly complementary):
     delta_D = || dual residual of y* ||_2      (d - lam(d), as in kkt.py)
     D_P = min(1 / delta_P, growth * D_P_prev)  (growth * D_P_prev if delta_P = 0)
     D_D = min(1 / delta_D, growth * D_D_prev)
-and the primal weight of the correction solve starts at
-||c~||_2 / ||b~||_2 = (D_D ||d||_2) / (D_P ||r||_2), the usual
-||c|| / ||b|| start on the correction data.
+and the primal weight carries over from the solve that produced the
+correction: PDHG on data whose primal part is scaled by D_P and dual part by
+D_D takes the same steps as on the unscaled error when its primal weight is
+multiplied by D_D / D_P, so a round starts at
+omega_prev * (D_D / D_P) / (D_D_prev / D_P_prev).
 
 The new point of a round is x* <- proj_[l,u](x* + x~ / D_P),
 y* <- y* + y~ / D_D with y*_G projected to >= 0 (the first round takes the
@@ -84,7 +86,7 @@ class Round:
     dres: np.ndarray       # d - lam(d)
     delta_p: float         # D_P
     delta_d: float         # D_D
-    omega: float           # starting primal weight of the correction solve
+    omega: float           # starting primal weight of the next correction solve
     c_t: np.ndarray        # correction data, FP64
     b_t: np.ndarray
     l_t: np.ndarray
@@ -126,8 +128,7 @@ def refine_round(A: sp.csr_matrix, c, b, l, u, m_eq: int, x_star, y_star, x_corr
     delta_d_err = float(np.linalg.norm(dres))
     dp = min(1.0 / delta_p_err, growth * dp_prev) if delta_p_err > 0 else growth * dp_prev
     dd = min(1.0 / delta_d_err, growth * dd_prev) if delta_d_err > 0 else growth * dd_prev
-    nr, nd = float(np.linalg.norm(r)), float(np.linalg.norm(d))
-    omega = (dd * nd) / (dp * nr) if nr > 0 and nd > 0 else omega_prev
+    omega = omega_prev * (dd / dp) / (dd_prev / dp_prev)
     ylo = np.where(isG, -dd * y, -np.inf)
     return Round(x=x, y=y, r=r, d=d, viol=viol, dres=dres, delta_p=dp, delta_d=dd, omega=omega,
                  c_t=dd * d, b_t=dp * r, l_t=dp * (l - x), u_t=dp * (u - x), ylo=ylo)

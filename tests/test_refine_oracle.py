@@ -40,7 +40,7 @@ def test_round_by_hand_one_dimensional():
     assert r.dres[0] == 0.0                      # boxed column: lam = d
     assert math.isclose(r.delta_p, 10.0, rel_tol=1e-14)
     assert r.delta_d == 1e4                      # no dual residual: growth cap
-    assert math.isclose(r.omega, 1e4 * 0.2 / (10.0 * 0.1), rel_tol=1e-14)
+    assert math.isclose(r.omega, 3.0 * 1e4 / 10.0, rel_tol=1e-14)   # weight 3 carried over
     assert math.isclose(r.c_t[0], -2000.0, rel_tol=1e-14)
     assert math.isclose(r.b_t[0], 1.0, rel_tol=1e-14)
     assert math.isclose(r.l_t[0], -9.0, rel_tol=1e-14) and math.isclose(r.u_t[0], 41.0, rel_tol=1e-14)
@@ -168,6 +168,39 @@ def test_planted_shift_sign_is_caught():
     x, y = rf.map_back(bad, ip.m_eq, corr.x, corr.y)
     k = kkt(ilp, x, y)
     assert k.rel_kkt > 1e-6 or abs(k.pobj - opt.obj) > 1e-6 * (1 + abs(opt.obj))
+
+
+def test_scaled_correction_step_is_the_scaled_error_step():
+    """The weight carried over: one PDHG step on the correction data scaled
+    by (D_P, D_D) with primal weight omega * D_D / D_P is the step on the
+    unscaled error (D = 1, weight omega), scaled by D_P and D_D."""
+    lp = make_instance("tiny", 1, n_periods=3)
+    ip = ps.internal_problem(lp)
+    A, ilp, c, b, l, u = internal_lp(ip)
+    m = ip.m
+    rng = np.random.default_rng(5)
+    x0 = np.clip(rng.normal(size=ip.n), l, u)
+    y0 = 100.0 * rng.normal(size=m)
+    # a growth cap below every 1 / delta gives D_P = D_D = 1e-6; without it
+    # D_P = 1 / delta_P and D_D = 1 / delta_D differ
+    one = rf.refine_round(A, c, b, l, u, m, None, None, x0, y0, 1.0, 1.0, True, 1.0, 1.0, 1e-6, 1.0)
+    big = rf.refine_round(A, c, b, l, u, m, None, None, x0, y0, 1.0, 1.0, True, 1.0, 1.0, 1e4, 1.0)
+    assert one.delta_p == 1e-6 and one.delta_d == 1e-6
+    assert abs((big.delta_d / big.delta_p) / (one.delta_d / one.delta_p) - 1) > 0.1
+    ex, ey = rng.normal(size=ip.n) * 1e-3, rng.normal(size=m) * 1e-3
+    eta, omega = 0.9, 2.5
+    dp1, dd1 = one.delta_p, one.delta_d
+    w1 = omega * (dd1 / dp1)
+    xs1, ys1 = ps.pdhg_step(A, one.c_t, one.b_t, one.l_t, one.u_t, m, dp1 * ex, dd1 * ey, eta / w1, eta * w1)
+    wb = w1 * (big.delta_d / big.delta_p) / (dd1 / dp1)
+    xsb, ysb = ps.pdhg_step(A, big.c_t, big.b_t, big.l_t, big.u_t, m, big.delta_p * ex, big.delta_d * ey,
+                            eta / wb, eta * wb)
+    assert np.allclose(xsb / big.delta_p, xs1 / dp1, rtol=1e-9, atol=1e-12)
+    assert np.allclose(ysb / big.delta_d, ys1 / dd1, rtol=1e-9, atol=1e-12)
+    # a weight that does not carry the change of D_D / D_P takes another step
+    xsw, _ = ps.pdhg_step(A, big.c_t, big.b_t, big.l_t, big.u_t, m, big.delta_p * ex, big.delta_d * ey,
+                          eta / w1, eta * w1)
+    assert not np.allclose(xsw / big.delta_p, xs1 / dp1, rtol=1e-6, atol=1e-9)
 
 
 def test_directed_rounding_against_neighbouring_floats():
