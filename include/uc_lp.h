@@ -59,7 +59,12 @@ enum uc_lp_err {
 enum uc_lp_precision {
   UC_LP_FP64 = 0,              /* FP64 matrix values and iterates                  */
   UC_LP_FP32_MIXED = 1,        /* FP32 values/iterates; FP64 KKT, restart, gap     */
-  UC_LP_FP32_MIXED_POLISH = 2  /* FP32 until eps_rel, then FP64 until eps_polish   */
+  UC_LP_FP32_MIXED_POLISH = 2, /* FP32 until eps_rel, then FP64 until eps_polish   */
+  UC_LP_FP32_REFINE = 3        /* FP32 until eps_rel, then rounds of iterative
+                                  refinement with FP32 inner solves until the
+                                  FP64-evaluated relative KKT error of the
+                                  refined point is <= eps_polish (see
+                                  eps_refine)                                      */
 };
 
 /* Solve status. */
@@ -153,6 +158,31 @@ typedef struct {
                             2e-5); UC_LP_FP32_MIXED_POLISH with a smaller
                             eps_polish does.  Default 0 = off.  Ignored by
                             UC_LP_FP32_MIXED_POLISH.                          */
+  /* UC_LP_FP32_REFINE: iterative refinement for LP (Gleixner, Steffy & Wolter,
+     INFORMS J. Computing 28(3), 2016) with this library's FP32 PDHG as the
+     inner solver.  After the FP32 solve reaches eps_rel, its point (x*, y*)
+     is kept in FP64; each round forms, on the device, the correction
+     problem of the same matrix whose data are the FP64 residuals of
+     (x*, y*) scaled up by D_P = 1/||primal violation||, D_D = 1/||dual
+     residual|| (each at most refine_growth times the previous round's):
+       c~ = D_D (c - A'y*), b~ = D_P (b - A x*), l~ = D_P (l - x*),
+       u~ = D_P (u - x*), inequality duals y~ >= -D_D y*,
+     solves it in FP32 from (0, 0), and adds the correction
+     (x~/D_P, y~/D_D) to (x*, y*), projected onto the bounds and y_G >= 0.
+     A correction solve measures its KKT error on the scale of the point it
+     corrects (residuals divided by D_P, D_D, duality gap by D_P D_D, each
+     relative as in the main solve) and stops once that estimate of the
+     refined point's error has fallen to eps_refine times its value at the
+     round start, or to eps_polish, or when it stalls (fp32_stall_checks).
+     The solve is OPTIMAL once the relative KKT error of (x*, y*) on the
+     original problem, evaluated in FP64, is <= eps_polish; ITER_LIMIT at
+     iter_limit iterations over all rounds or after refine_max_rounds
+     rounds.  Refinement runs in the scaled space of the solve, and the
+     primal weight carries over, times the change of D_D / D_P.           */
+  double eps_refine;     /* error reduction asked of each round, 1e-2         */
+  double refine_growth;  /* bound on the growth of D_P and D_D per round, 1e4 */
+  int32_t refine_max_rounds; /* default 20                                    */
+  int32_t reserved2;     /* must be 0                                         */
 } uc_lp_opts;
 
 typedef struct {
@@ -200,6 +230,13 @@ typedef struct {
                               = 1) guarantees; norm_a_est shows its tightness */
   double eta;              /* step: tau = eta / omega, sigma = eta * omega,
                               eta = step_scale / norm_a_bound                 */
+  int32_t refine_rounds;   /* UC_LP_FP32_REFINE: correction problems solved
+                              (or being solved); the KKT fields above then
+                              describe the refined point (x*, y*) at the last
+                              round boundary                                   */
+  int32_t reserved_i;
+  double rel_kkt_inner;    /* UC_LP_FP32_REFINE: relative KKT error of the
+                              running correction problem at the last check    */
 } uc_lp_info;
 
 /* Fill *opts with the defaults listed in uc_lp_opts. */
@@ -358,6 +395,37 @@ int uc_lp_debug_iterate(uc_lp* lp, int32_t precision, int32_t iters, int32_t blo
  * solver's own FP64 check kernels.  Fills pobj, dobj, rel_* and
  * abs_primal_inf of *out (other fields zero). */
 int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp_info* out);
+
+/* One round boundary of iterative refinement (UC_LP_FP32_REFINE), by the
+ * kernels the solve runs, on the scaled internal problem (A_hat, c_hat =
+ * D_c c, b_hat = D_r b, l_hat = l / D_c, u_hat = u / D_c):
+ *   x* <- proj_[l_hat,u_hat](x* + x~ inv_dp),  y* <- y* + y~ inv_dd with
+ *   inequality rows projected to >= 0 (first != 0: x* = y* = 0 before);
+ *   r = b_hat - A_hat x*, d = c_hat - A_hat' y*, violation v (E rows r, G rows
+ *   max(r, 0)), dual residual e = d - lambda(d) (lambda by the finiteness
+ *   of the bounds);
+ *   D_P = min(1/||v||_2, growth dp_prev) (growth dp_prev if ||v|| = 0), D_D
+ *   likewise from ||e||_2 and dd_prev; omega = omega_prev (D_D/D_P) /
+ *   (dd_prev/dp_prev);
+ *   c~ = D_D d, b~ = D_P r, l~ = D_P (l_hat - x*), u~ = D_P (u_hat - x*),
+ *   ylo = -D_D y* on inequality rows (-inf on equality rows).
+ * Inputs (host): x_star[n_int], y_star[m_int] (FP64, ignored if first),
+ * x_corr[n_int], y_corr[m_int] (FP32, the correction solve's output),
+ * par[6] = {inv_dp, inv_dd, dp_prev, dd_prev, growth, omega_prev}.
+ * Outputs (host, any may be NULL): x_new[n_int], y_new[m_int] (FP64);
+ * data64[3 n_int + m_int] = c~, l~, u~, b~ (FP64); data32[3 n_int + 2 m_int]
+ * = c~, l~, u~, b~, ylo as the FP32 inner solve receives them (c~, b~ to
+ * nearest; l~ and ylo rounded up, u~ rounded down, so every FP32-feasible
+ * correction maps back into the FP64 box and onto y >= 0);
+ * scal[14] = {D_P, D_D, omega, ||v||^2, ||e||^2 (scaled space),
+ *   unscaled sum of squared violations, b_hat'y*, inf-norm of unscaled
+ *   violations, unscaled sum of squared dual residuals, sum of l lambda+ +
+ *   u lambda-, c_hat'x*, ||b~||_2 and ||c~||_2 unscaled, relative KKT error
+ *   of (x*, y*) on the original problem}.
+ * Same handle requirements as the other step-level entry points. */
+int uc_lp_debug_refine(uc_lp* lp, const double* x_star, const double* y_star, const float* x_corr,
+                       const float* y_corr, int32_t first, const double* par, double* x_new,
+                       double* y_new, double* data64, float* data32, double* scal);
 
 /* Standalone SpMV y = A x on host arrays, through the same SpMV kernels:
  * precision UC_LP_FP64 (FP64 values, FP64 accumulation) or UC_LP_FP32_MIXED

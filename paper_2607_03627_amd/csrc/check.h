@@ -24,9 +24,13 @@ struct ChkParams {
   int32_t fp32_stall_checks;
   int64_t iter_limit;
   double eps_rel, eps_polish, eps_gap_rel, eps_abs_feas;
+  double eps_refine;  // UC_LP_FP32_REFINE: target of each correction problem
   double restart_sufficient, restart_necessary, restart_artificial;
   double pw_smoothing, pw_max_change, pw_integral, pw_balance;
   double norm_b, norm_c, obj_offset;
+  // > 0: denominator of the relative gap in place of 1 + |pobj| + |dobj|
+  // (a correction problem measures its gap on the scale of the refined point)
+  double gap_den;
 };
 
 // State of one run between checks, and what the last check found.
@@ -36,6 +40,8 @@ struct ChkState {
   int32_t promote;    // the last check ended the FP32 phase
   int32_t restart;    // the last check's restart flag for the finish kernel (0, 1, 2)
   int32_t r_start_set, r_prev_set, gap_phase, eps_reached;
+  int32_t round;      // UC_LP_FP32_REFINE: 0 the base solve, k > 0 correction problem k
+  int32_t pad_;
   double eta, omega;
   int64_t k_inner;      // steps since the last restart
   int64_t phase_total;  // steps in the current precision phase
@@ -59,13 +65,15 @@ __host__ __device__ inline void check_step(ChkState& st, const ChkParams& p, con
   // KKT quantities (unscaled, original problem)
   const double rho_p = sqrt(fmax(q[RQ_RES2], 0.0));
   const double rho_d = sqrt(fmax(q[RQ_N + CQ_DRES2] + q[RQ_YNEG2], 0.0));
-  const double pobj = q[RQ_N + CQ_CX] + p.obj_offset;
+  // a lower bound ylo on the inequality duals adds -ylo'(A_G x - b_G) to
+  // the primal objective (RQ_YLOR; zero unless ylo is in use)
+  const double pobj = q[RQ_N + CQ_CX] - q[RQ_YLOR] + p.obj_offset;
   const double dobj = q[RQ_BY] + q[RQ_N + CQ_LBUB] + p.obj_offset;
   st.pobj = pobj;
   st.dobj = dobj;
   st.rel_primal = rho_p / (1.0 + p.norm_b);
   st.rel_dual = rho_d / (1.0 + p.norm_c);
-  st.rel_gap = fabs(pobj - dobj) / (1.0 + fabs(pobj) + fabs(dobj));
+  st.rel_gap = fabs(pobj - dobj) / (p.gap_den > 0 ? p.gap_den : 1.0 + fabs(pobj) + fabs(dobj));
   st.rel_kkt = fmax(st.rel_primal, fmax(st.rel_dual, st.rel_gap));
   st.abs_primal_inf = q[RQ_RESMAX];
   st.iters += K;
@@ -78,7 +86,11 @@ __host__ __device__ inline void check_step(ChkState& st, const ChkParams& p, con
   const double dx2 = q[RQ_N + CQ_DX2], dy2 = q[RQ_DY2], cross = q[RQ_DYADX];
   const double rfp = sqrt(fmax(st.omega / st.eta * dx2 + dy2 / (st.omega * st.eta) + 2.0 * cross, 0.0));
   st.fp_residual = rfp;
-  const bool feas_ok = p.eps_abs_feas <= 0 || st.abs_primal_inf <= p.eps_abs_feas;
+  // a correction problem of iterative refinement: its own target; the
+  // absolute feasibility test applies to the refined point (host side)
+  const bool refine_mode = p.mode == UC_LP_FP32_REFINE;
+  const bool inner = refine_mode && st.round > 0;
+  const bool feas_ok = inner || p.eps_abs_feas <= 0 || st.abs_primal_inf <= p.eps_abs_feas;
   const bool finite = isfinite(st.rel_kkt) && isfinite(rfp) && isfinite(pobj);
   bool terminate = false, promote = false;
   int32_t status = UC_LP_RUNNING;
@@ -86,7 +98,7 @@ __host__ __device__ inline void check_step(ChkState& st, const ChkParams& p, con
     terminate = true;
     status = UC_LP_NUMERICAL;
   } else {
-    if (!st.eps_reached && st.rel_kkt <= p.eps_rel && feas_ok) {
+    if (!st.eps_reached && !inner && st.rel_kkt <= p.eps_rel && feas_ok) {
       st.eps_reached = 1;
       st.pobj_at_eps = pobj;
       st.rel_kkt_at_eps = st.rel_kkt;
@@ -96,12 +108,15 @@ __host__ __device__ inline void check_step(ChkState& st, const ChkParams& p, con
     }
     const bool polish_mode = p.mode == UC_LP_FP32_MIXED_POLISH;
     const bool polish_phase = polish_mode && st.prec == 0;
-    const double target = polish_phase ? p.eps_polish : p.eps_rel;
-    // outside the polish mode a returned point may also have to close the gap
-    const bool gap_rule = !polish_mode && p.eps_gap_rel > 0;
+    const double target = polish_phase ? p.eps_polish : inner ? p.eps_refine : p.eps_rel;
+    // outside the polish and refinement modes a returned point may also have
+    // to close the gap
+    const bool gap_rule = !polish_mode && !refine_mode && p.eps_gap_rel > 0;
     const bool gap_ok = !gap_rule || st.rel_gap <= p.eps_gap_rel;
     if (st.rel_kkt <= target && feas_ok) {
-      if (polish_mode && st.prec == 1) {
+      // the FP32 phase ends: polish in FP64, or (refinement) the host folds
+      // the point into the refined one and forms the next correction problem
+      if ((polish_mode || refine_mode) && st.prec == 1) {
         promote = true;
       } else if (gap_ok) {
         terminate = true;
@@ -122,10 +137,14 @@ __host__ __device__ inline void check_step(ChkState& st, const ChkParams& p, con
       if (st.best_check == 0 || err < 0.9 * st.best_kkt) {
         st.best_kkt = err;
         st.best_check = st.checks;
-      } else if (p.fp32_stall_checks > 0 && st.checks - st.best_check >= p.fp32_stall_checks &&
-                 (continuing || st.best_kkt <= 10.0 * target)) {
+      } else if (p.fp32_stall_checks > 0 &&
+                 st.checks - st.best_check >= (inner ? 4 : 1) * (int64_t)p.fp32_stall_checks &&
+                 (continuing || inner || st.best_kkt <= 10.0 * target)) {
         // a stall within a decade of the target (or of the gap past the
-        // milestone) is taken for the FP32 floor
+        // milestone) is taken for the FP32 floor.  A correction problem,
+        // which is O(1)-scaled and far from that floor, gets four times the
+        // window (restarted PDHG can take that long for 10% near 1e-8); when
+        // it stalls, it ends its round wherever it stands
         promote = true;
       }
     }
@@ -173,7 +192,7 @@ __host__ __device__ inline void check_step(ChkState& st, const ChkParams& p, con
       st.k_inner = k_end;
     }
   }
-  if (promote) {
+  if (promote && !refine_mode) {
     // the FP64 phase starts at (x_hat, y_hat) as after a restart
     st.prec = 0;
     st.k_inner = 0;

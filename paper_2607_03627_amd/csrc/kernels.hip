@@ -399,6 +399,8 @@ __global__ __launch_bounds__(NT) void k_primal(const SlotDev* __restrict__ slots
 
 // Dual half-step over the rows of A:
 //   y_hat = y + sigma (b - A xbar), projected to y >= 0 on rows i >= m_eq
+//   (y >= ylo in tiles flagged kRowYlo: the correction problems of
+//   iterative refinement)
 //   non-check: y <- w ((1+gamma) y_hat - gamma y) + (1 - w) y0 ; check: y_hat stored
 template <typename T, bool CHECK, int NT>
 __global__ __launch_bounds__(NT) void k_dual(const SlotDev* __restrict__ slots,
@@ -419,7 +421,8 @@ __global__ __launch_bounds__(NT) void k_dual(const SlotDev* __restrict__ slots,
   const int nz = tl.k1 - k0;
   // straight-line epilogue loads, as in k_primal
   int a[kRpt], b[kRpt];
-  T bi[kRpt], y[kRpt], ya[kRpt];
+  T bi[kRpt], y[kRpt], ya[kRpt], lo[kRpt];
+  const bool ylo = tl.flags & kRowYlo;
 #pragma unroll
   for (int q = 0; q < kRpt; ++q) {
     const int i = min(r0 + (int)threadIdx.x + q * NT, r1 - 1);
@@ -429,6 +432,7 @@ __global__ __launch_bounds__(NT) void k_dual(const SlotDev* __restrict__ slots,
     bi[q] = (tl.flags & kRowB0) ? (T)0 : gld(V.b)[i];
     y[q] = gld(V.y)[i];
     ya[q] = CHECK ? (T)0 : gld(V.y0)[i];
+    lo[q] = ylo ? (T)gld(S.ylo)[i] : (T)0;
   }
   T s[kRpt];
   if (nz <= kNnzTile) {
@@ -457,7 +461,7 @@ __global__ __launch_bounds__(NT) void k_dual(const SlotDev* __restrict__ slots,
     const int i = r0 + threadIdx.x + q * NT;
     if (i >= r1) break;
     T yh = y[q] + sigma * (bi[q] - s[q]);
-    if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
+    if (i >= S.m_eq) yh = yh > lo[q] ? yh : lo[q];
     if (CHECK) gst(V.yhat)[i] = yh;
     else gst(V.y)[i] = w * (g1 * yh - g * y[q]) + wa * ya[q];
   }
@@ -487,24 +491,28 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows(const SlotDev* __restrict
   const int k0 = tl.k0;
   const int k1 = tl.k1;
   const int nz = k1 - k0;
-  double q[RQ_N] = {0, 0, 0, 0, 0, 0, 0};
-  const bool is_max[RQ_N] = {false, false, false, false, false, false, true};
+  double q[RQ_N] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const bool is_max[RQ_N] = {false, false, false, false, false, false, true, false};
+  const bool ylo = tl.flags & kRowYlo;
   auto row_terms = [&](int row, double s1, double s2) {
+    const bool ineq = row >= S.m_eq;
     double r = S.d.b[row] - s1;
-    if (row >= S.m_eq) r = r > 0.0 ? r : 0.0;
+    if (ineq) r = r > 0.0 ? r : 0.0;
     const double ru = r / S.dr[row];
     const double yh = (double)V.yhat[row];
     const double dy = yh - (double)V.y[row];
     const double d0 = yh - (double)V.y0[row];
+    const double lo = ineq && ylo ? (double)S.ylo[row] : 0.0;
     q[RQ_RES2] += ru * ru;
     q[RQ_BY] += S.d.b[row] * yh;
     q[RQ_DY2] += dy * dy;
     q[RQ_DYADX] += dy * s2;
     q[RQ_DY0] += d0 * d0;
     // dual sign violation of an inequality row, unscaled (zero for projected iterates)
-    const double yneg = row >= S.m_eq && yh < 0.0 ? yh * S.dr[row] : 0.0;
+    const double yneg = ineq && yh < lo ? (yh - lo) * S.dr[row] : 0.0;
     q[RQ_YNEG2] += yneg * yneg;
     q[RQ_RESMAX] = fmax(q[RQ_RESMAX], fabs(ru));
+    q[RQ_YLOR] += lo * (s1 - S.d.b[row]);
   };
   if (nz <= kNnzTile) {
     const UCLP_GLOBAL double* vs = gld(S.d.avs);
@@ -799,6 +807,153 @@ __global__ void k_stamp(unsigned long long* t) {
 }
 
 // ---------------------------------------------------------------------------
+// iterative refinement: the round boundary of one instance (FP64, scaled space)
+// ---------------------------------------------------------------------------
+
+// Smallest float >= v and largest float <= v (infinities pass through).
+__device__ inline float f32_up(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = nextafterf(f, INFINITY);
+  return f;
+}
+__device__ inline float f32_down(double v) {
+  float f = (float)v;
+  if ((double)f > v) f = nextafterf(f, -INFINITY);
+  return f;
+}
+
+// x* <- clamp(x* + x~ / D_P, l_hat, u_hat), y* <- y* + y~ / D_D (>= 0 on
+// inequality rows); `first`: x* = y* = 0 before.
+__global__ void k_refine_fold(RefineArgs R) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < R.n) {
+    const double d = R.dc[i];
+    const double l = R.l_in[i] / d, u = R.u_in[i] / d;
+    const double v = (R.first ? 0.0 : R.xs[i]) + (double)R.xc[i] * R.inv_dp;
+    R.xs[i] = fmin(fmax(v, l), u);
+  } else if (i < (int64_t)R.n + R.m) {
+    const int r = (int)(i - R.n);
+    double v = (R.first ? 0.0 : R.ys[r]) + (double)R.yc[r] * R.inv_dd;
+    if (r >= R.m_eq) v = fmax(v, 0.0);
+    R.ys[r] = v;
+  }
+}
+
+constexpr int kFq = 5;  // FQ partials per row block (rows: FQ_VIOL2.., cols: FQ_DRES2..)
+
+// r = b_hat - A_hat x* over one row block of A, with the row FQ partials.
+__global__ __launch_bounds__(kThreads) void k_refine_rows(RefineArgs R) {
+  __shared__ double lds[kNnzTile];
+  __shared__ double red[(kThreads / 64) * kFq];
+  const int bk = blockIdx.x;
+  double q[kFq] = {0, 0, 0, 0, 0};
+  const bool is_max[kFq] = {false, false, false, false, true};
+  block_rows<double>(
+      R.a_ptr, R.a_blk[bk], R.a_blk[bk + 1], lds, red, [&](int k) { return R.a_v[k] * R.xs[R.a_col[k]]; },
+      [&](int i, double s) {
+        const double dr = R.dr[i];
+        const double bh = R.b_in[i] * dr;
+        const double r = bh - s;
+        const double v = i >= R.m_eq ? fmax(r, 0.0) : r;
+        const double ru = r / dr, vu = v / dr;
+        R.r[i] = r;
+        q[0] += v * v;
+        q[1] += ru * ru;
+        q[2] += vu * vu;
+        q[3] += bh * R.ys[i];
+        q[4] = fmax(q[4], fabs(vu));
+      });
+  __syncthreads();
+  block_reduce<kFq>(q, is_max, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kFq; ++k) R.part_a[(size_t)bk * kFq + k] = q[k];
+}
+
+// d = c_hat - A_hat' y* over one row block of A^T, with the column FQ partials.
+__global__ __launch_bounds__(kThreads) void k_refine_cols(RefineArgs R) {
+  __shared__ double lds[kNnzTile];
+  __shared__ double red[(kThreads / 64) * kFq];
+  const int bk = blockIdx.x;
+  double q[kFq] = {0, 0, 0, 0, 0};
+  const bool is_max[kFq] = {false, false, false, false, false};
+  block_rows<double>(
+      R.t_ptr, R.t_blk[bk], R.t_blk[bk + 1], lds, red, [&](int k) { return R.t_v[k] * R.ys[R.t_col[k]]; },
+      [&](int j, double s) {
+        const double dc = R.dc[j];
+        const double c = R.c_in[j] * dc, l = R.l_in[j] / dc, u = R.u_in[j] / dc;
+        const double dh = c - s;
+        const bool fl = isfinite(l), fu = isfinite(u);
+        double lam = 0.0;
+        if (fl && fu) lam = dh;
+        else if (fl) lam = dh > 0.0 ? dh : 0.0;
+        else if (fu) lam = dh < 0.0 ? dh : 0.0;
+        const double e = dh - lam;
+        const double du = dh / dc, eu = e / dc;
+        R.d[j] = dh;
+        q[0] += e * e;
+        q[1] += du * du;
+        q[2] += eu * eu;
+        q[3] += (lam > 0.0 ? l * lam : 0.0) + (lam < 0.0 ? u * lam : 0.0);
+        q[4] += c * R.xs[j];
+      });
+  __syncthreads();
+  block_reduce<kFq>(q, is_max, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kFq; ++k) R.part_t[(size_t)bk * kFq + k] = q[k];
+}
+
+// One workgroup: the block partials in a fixed order -> R.out[FQ_N].
+__global__ __launch_bounds__(kThreads) void k_refine_reduce(RefineArgs R) {
+  __shared__ double red[(kThreads / 64) * FQ_N];
+  double q[FQ_N];
+  bool is_max[FQ_N];
+#pragma unroll
+  for (int k = 0; k < FQ_N; ++k) {
+    q[k] = 0.0;
+    is_max[k] = k == FQ_VMAXU;
+  }
+  for (int b = threadIdx.x; b < R.a_nblk; b += kThreads)
+#pragma unroll
+    for (int k = 0; k < kFq; ++k) {
+      const double v = R.part_a[(size_t)b * kFq + k];
+      q[k] = is_max[k] ? fmax(q[k], v) : q[k] + v;
+    }
+  for (int b = threadIdx.x; b < R.t_nblk; b += kThreads)
+#pragma unroll
+    for (int k = 0; k < kFq; ++k) q[kFq + k] += R.part_t[(size_t)b * kFq + k];
+  block_reduce<FQ_N>(q, is_max, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < FQ_N; ++k) R.out[k] = q[k];
+}
+
+// Correction data of the next round (FP64, and FP32 rounded so that every
+// FP32-feasible correction maps back into the FP64 box and onto y >= 0).
+__global__ void k_refine_form(RefineArgs R) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < R.n) {
+    const double dc = R.dc[i];
+    const double l = R.l_in[i] / dc, u = R.u_in[i] / dc;
+    const double x = R.xs[i];
+    const double ct = R.dd * R.d[i];
+    const double lt = R.dp * (l - x), ut = R.dp * (u - x);
+    R.c64[i] = ct;
+    R.l64[i] = lt;
+    R.u64[i] = ut;
+    float lo = f32_up(lt), hi = f32_down(ut);
+    if (lo > hi) lo = hi = (float)((lt + ut) / 2);
+    R.c32[i] = (float)ct;
+    R.l32[i] = lo;
+    R.u32[i] = hi;
+  } else if (i < (int64_t)R.n + R.m) {
+    const int r = (int)(i - R.n);
+    const double bt = R.dp * R.r[r];
+    R.b64[r] = bt;
+    R.b32[r] = (float)bt;
+    R.ylo32[r] = r >= R.m_eq ? f32_up(-R.dd * R.ys[r]) : -INFINITY;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // scenario batches: several right-hand sides / costs / bounds over one matrix
 // ---------------------------------------------------------------------------
 // Vectors are interleaved (element j of scenario s at j * nscen + s).  A
@@ -1024,8 +1179,8 @@ __global__ __launch_bounds__(kThreads) void k_kkt_rows_ms(const SlotDev* __restr
   __syncthreads();
   const int ns = S.nscen;
   const int sc = threadIdx.x % kLanes;
-  double q[RQ_N] = {0, 0, 0, 0, 0, 0, 0};
-  const bool is_max[RQ_N] = {false, false, false, false, false, false, true};
+  double q[RQ_N] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const bool is_max[RQ_N] = {false, false, false, false, false, false, true, false};
   if (sc < ns) {
     for (int i = r0 + threadIdx.x / kLanes; i < r1; i += kRowsPerPass) {
       double s1 = 0, s2 = 0;
@@ -1734,6 +1889,19 @@ void launch_engine_check(SlotDev* slots, ChkState* chk, const ChkParams* prm, in
 }
 
 void launch_stamp(unsigned long long* t, hipStream_t s) { k_stamp<<<1, 64, 0, s>>>(t); }
+
+void launch_refine_measure(const RefineArgs& R, hipStream_t s) {
+  const int64_t nm = (int64_t)R.n + R.m;
+  k_refine_fold<<<nb(nm), kThreads, 0, s>>>(R);
+  if (R.a_nblk > 0) k_refine_rows<<<R.a_nblk, kThreads, 0, s>>>(R);
+  if (R.t_nblk > 0) k_refine_cols<<<R.t_nblk, kThreads, 0, s>>>(R);
+  k_refine_reduce<<<1, kThreads, 0, s>>>(R);
+}
+
+void launch_refine_form(const RefineArgs& R, hipStream_t s) {
+  const int64_t nm = (int64_t)R.n + R.m;
+  k_refine_form<<<nb(nm), kThreads, 0, s>>>(R);
+}
 
 void launch_promote(const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
                     int natiles, int nscen, hipStream_t s) {

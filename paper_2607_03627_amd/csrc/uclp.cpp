@@ -105,10 +105,17 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->fp32_stall_checks = 24;
   o->reserved = 0;
   o->eps_gap_rel = 0.0;
+  o->eps_refine = 1e-2;
+  o->refine_growth = 1e4;
+  o->refine_max_rounds = 20;
+  o->reserved2 = 0;
 }
 
 static int check_opts(const uc_lp_opts& o) {
-  if (o.precision < 0 || o.precision > 2) return fail(UC_LP_ENOTSUP, "precision %d", o.precision);
+  if (o.precision < 0 || o.precision > 3) return fail(UC_LP_ENOTSUP, "precision %d", o.precision);
+  if (!(o.eps_refine > 0 && o.eps_refine < 1) || !(o.refine_growth > 1) || o.refine_max_rounds < 0 ||
+      o.refine_max_rounds > 1000 || o.reserved2 != 0)
+    return fail(UC_LP_EINVAL, "refinement parameters out of range");
   if (o.kkt_every < 1 || o.kkt_every > 1 << 20) return fail(UC_LP_EINVAL, "kkt_every %d", o.kkt_every);
   if (o.ruiz_iters < 0 || o.ruiz_iters > 1000) return fail(UC_LP_EINVAL, "ruiz_iters");
   if (o.power_iters < 1 || o.power_iters > 100000) return fail(UC_LP_EINVAL, "power_iters");
@@ -486,6 +493,7 @@ struct DevMem {
   double *part_a, *part_t, *scal;
   double *x_out, *y_out, *x_warm, *y_warm;
   double *pv, *pw, *pu, *red_part, *red_out;  // power iteration / norms
+  float* ylo32;  // lower bound of the inequality duals (refinement rounds)
   int *row_of, *keys_in, *keys_out, *perm_in, *perm_out;
   void* sort_temp;
   size_t sort_bytes;
@@ -548,6 +556,7 @@ static void carve(DevMem& D, const HostProblem& P, int ns) {
   D.pu = A.take<double>(m);
   D.red_part = A.take<double>(1024);
   D.red_out = A.take<double>(8);
+  D.ylo32 = A.take<float>(m);
   D.row_of = A.take<int>(z);
   D.keys_in = D.a_col;  // the sort reads the column indices in place
   D.keys_out = A.take<int>(z);
@@ -611,6 +620,20 @@ struct uc_engine {
   std::string err;
 };
 
+// Iterative refinement state of one solve (UC_LP_FP32_REFINE).  The refined
+// point (x*, y*) lives in the instance's FP64 x_hat, y_hat; while a
+// correction problem runs, the scaled data arrays (FP64 and FP32) hold its
+// data and the FP32 iterates its solution.
+struct RefineRun {
+  int round = 0;          // correction problems started so far
+  double dp = 1, dd = 1;  // D_P, D_D of the running correction problem
+  bool have_outer = false;
+  // the refined point at the last round boundary (original problem)
+  double pobj = 0, dobj = 0, rel_primal = 0, rel_dual = 0, rel_gap = 0, rel_kkt = 0, abs_inf = 0;
+  double rel_kkt_inner = 0;
+  std::vector<int> t_flag, a_flag;  // tile flags while correction data are loaded
+};
+
 struct uc_lp {
   uc_engine* eng = nullptr;
   bool owns_engine = false;
@@ -641,6 +664,7 @@ struct uc_lp {
   double timed_primal_ms[2] = {0, 0}, timed_dual_ms[2] = {0, 0};
   long long timed_n[2] = {0, 0};
   int data_gen = 0;  // bumped by uc_lp_update_data (tile flags depend on the data)
+  RefineRun ref;
 };
 
 static void set_info(uc_lp* lp, const uc_lp_info& in) {
@@ -754,6 +778,7 @@ static SlotDev make_slot(const HostProblem& P, const DevMem& D, double gamma) {
   S.t_pk = D.t_pk;
   S.a_end = D.a_end;
   S.t_end = D.t_end;
+  S.ylo = D.ylo32;
   S.part_a = D.part_a;
   S.part_t = D.part_t;
   S.scal = D.scal;
@@ -915,7 +940,7 @@ static int fetch_solution(uc_lp* lp, int prec) {
 static void kkt_scalars(const double* q, double offset, double norm_b, double norm_c, uc_lp_info& in) {
   const double rho_p = std::sqrt(std::max(q[RQ_RES2], 0.0));
   const double rho_d = std::sqrt(std::max(q[RQ_N + CQ_DRES2] + q[RQ_YNEG2], 0.0));
-  const double pobj = q[RQ_N + CQ_CX] + offset;
+  const double pobj = q[RQ_N + CQ_CX] - q[RQ_YLOR] + offset;
   const double dobj = q[RQ_BY] + q[RQ_N + CQ_LBUB] + offset;
   in.pobj = pobj;
   in.dobj = dobj;
@@ -943,6 +968,7 @@ static ChkParams make_params(const uc_lp_opts& o, const HostProblem& P) {
   p.eps_polish = o.eps_polish;
   p.eps_gap_rel = o.eps_gap_rel;
   p.eps_abs_feas = o.eps_abs_feas;
+  p.eps_refine = o.eps_refine;
   p.restart_sufficient = o.restart_sufficient;
   p.restart_necessary = o.restart_necessary;
   p.restart_artificial = o.restart_artificial;
@@ -1022,6 +1048,20 @@ static void publish_state(uc_engine* E, uc_lp* lp, const ChkState& c, double tno
   std::lock_guard<std::mutex> g(lp->mu);
   uc_lp_info& in = lp->info;
   info_from_state(c, in);
+  const RefineRun& F = lp->ref;
+  if (F.have_outer) {
+    // refinement: the KKT fields describe the refined point, the running
+    // correction problem reports its own error separately
+    in.rel_kkt_inner = c.round > 0 && c.status == UC_LP_RUNNING ? c.rel_kkt : F.rel_kkt_inner;
+    in.pobj = F.pobj;
+    in.dobj = F.dobj;
+    in.rel_primal = F.rel_primal;
+    in.rel_dual = F.rel_dual;
+    in.rel_gap = F.rel_gap;
+    in.rel_kkt = F.rel_kkt;
+    in.abs_primal_inf = F.abs_inf;
+  }
+  in.refine_rounds = F.round;
   in.t_total_s = tnow - lp->t_start;
   if (c.eps_reached && in.t_to_eps_s < 0 && E->tick_rate > 0)
     in.t_to_eps_s = (lp->t_stamp - lp->t_start) + (double)(int64_t)(c.tick_at_eps - lp->tick_start) / E->tick_rate;
@@ -1037,6 +1077,212 @@ static void publish_state(uc_engine* E, uc_lp* lp, const ChkState& c, double tno
   const int bp = lp->timed_n[0] + lp->timed_n[1] > 0 ? tp : c.prec;
   in.primal_bytes = lp->hs_bytes[bp][0];
   in.dual_bytes = lp->hs_bytes[bp][1];
+}
+
+// ---- iterative refinement (UC_LP_FP32_REFINE) ---------------------------------
+//
+// At a round boundary the correction solve's FP32 point (x_hat, y_hat) is
+// folded into the refined FP64 point (x*, y*) (held in the FP64 x_hat,
+// y_hat), the residuals of (x*, y*) are formed and reduced in FP64, and the
+// host decides: OPTIMAL when the original problem's relative KKT error at
+// (x*, y*) meets eps_polish, else the next correction problem is written
+// into the scaled data arrays and a fresh FP32 PDHG run starts on it from
+// (0, 0).
+
+static RefineArgs refine_args(const uc_lp* lp) {
+  const DevMem& D = lp->D;
+  const HostProblem& P = lp->P;
+  RefineArgs R;
+  std::memset((void*)&R, 0, sizeof R);
+  R.a_ptr = D.a_ptr;
+  R.a_col = D.a_col;
+  R.t_ptr = D.t_ptr;
+  R.t_col = D.t_col;
+  R.a_blk = D.a_blk;
+  R.t_blk = D.t_blk;
+  R.a_v = D.a_v64;
+  R.t_v = D.t_v64;
+  R.c_in = D.c_in;
+  R.b_in = D.b_in;
+  R.l_in = D.l_in;
+  R.u_in = D.u_in;
+  R.dr = D.dr;
+  R.dc = D.dc;
+  R.m = P.mi;
+  R.n = P.ni;
+  R.m_eq = P.m_eq;
+  R.a_nblk = (int)P.a_blk.size() - 1;
+  R.t_nblk = (int)P.t_blk.size() - 1;
+  R.inv_dp = R.inv_dd = R.dp = R.dd = 1.0;
+  R.xs = D.d.xhat;
+  R.ys = D.d.yhat;
+  R.xc = D.f.xhat;
+  R.yc = D.f.yhat;
+  R.r = D.pu;
+  R.d = D.pw;
+  R.part_a = D.part_a;
+  R.part_t = D.part_t;
+  R.out = D.scal;
+  R.c64 = const_cast<double*>(D.d.c);
+  R.l64 = const_cast<double*>(D.d.l);
+  R.u64 = const_cast<double*>(D.d.u);
+  R.b64 = const_cast<double*>(D.d.b);
+  R.c32 = const_cast<float*>(D.f.c);
+  R.l32 = const_cast<float*>(D.f.l);
+  R.u32 = const_cast<float*>(D.f.u);
+  R.b32 = const_cast<float*>(D.f.b);
+  R.ylo32 = D.ylo32;
+  return R;
+}
+
+struct RefineFactors {
+  double dp, dd, omega;
+};
+
+// D_P = min(1/||v||, growth D_P_prev) (growth D_P_prev when v = 0), D_D
+// likewise; the primal weight carries over times the change of D_D / D_P.
+static RefineFactors refine_factors(const double* q, double dp_prev, double dd_prev, double growth,
+                                    double omega_prev) {
+  const double ep = std::sqrt(std::max(q[FQ_VIOL2], 0.0));
+  const double ed = std::sqrt(std::max(q[FQ_DRES2], 0.0));
+  RefineFactors f;
+  f.dp = ep > 0 ? std::min(1.0 / ep, growth * dp_prev) : growth * dp_prev;
+  f.dd = ed > 0 ? std::min(1.0 / ed, growth * dd_prev) : growth * dd_prev;
+  f.omega = omega_prev * (f.dd / f.dp) / (dd_prev / dp_prev);
+  return f;
+}
+
+// Relative KKT error of the refined point on the original problem.
+static void refine_outer(const double* q, const HostProblem& P, RefineRun& F) {
+  const double rho_p = std::sqrt(std::max(q[FQ_VIOL2U], 0.0));
+  const double rho_d = std::sqrt(std::max(q[FQ_DRES2U], 0.0));
+  F.pobj = q[FQ_CX] + P.obj_offset;
+  F.dobj = q[FQ_BY] + q[FQ_LBUB] + P.obj_offset;
+  F.rel_primal = rho_p / (1.0 + P.norm_b);
+  F.rel_dual = rho_d / (1.0 + P.norm_c);
+  F.rel_gap = std::fabs(F.pobj - F.dobj) / (1.0 + std::fabs(F.pobj) + std::fabs(F.dobj));
+  F.rel_kkt = std::max(F.rel_primal, std::max(F.rel_dual, F.rel_gap));
+  F.abs_inf = q[FQ_VMAXU];
+  F.have_outer = true;
+}
+
+// The original scaled data back in the arrays a correction problem used.
+static int restore_scaled_data(uc_lp* lp, hipStream_t s) {
+  DevMem& D = lp->D;
+  launch_scale_vectors(D.c_in, D.l_in, D.u_in, D.b_in, D.dc, D.dr, lp->P.ni, lp->P.mi, 1, (double*)D.d.c,
+                       (double*)D.d.l, (double*)D.d.u, (double*)D.d.b, (float*)D.f.c, (float*)D.f.l,
+                       (float*)D.f.u, (float*)D.f.b, s);
+  HIPOK(hipGetLastError());
+  HIPOK(hipStreamSynchronize(s));
+  return UC_LP_OK;
+}
+
+// One round boundary of lp's run (stream idle).  `fold`: fold the FP32
+// point of the running correction problem (or of the base solve) into
+// (x*, y*) first.  `stop`: a terminal status the run ends with regardless
+// (0 = none).  On return lp->chk either describes the next correction
+// problem (status RUNNING) or carries the terminal status with prec = 0, so
+// that the solution is read from (x*, y*).
+static int refine_boundary(uc_lp* lp, hipStream_t s, bool fold, int stop) {
+  RefineRun& F = lp->ref;
+  ChkState& c = lp->chk;
+  const uc_lp_opts& o = lp->opts;
+  const HostProblem& P = lp->P;
+  RefineArgs R = refine_args(lp);
+  double q[FQ_N] = {};
+  if (fold) {
+    R.first = F.round == 0 ? 1 : 0;
+    R.inv_dp = 1.0 / F.dp;
+    R.inv_dd = 1.0 / F.dd;
+    if (F.round > 0) F.rel_kkt_inner = c.rel_kkt;
+    launch_refine_measure(R, s);
+    HIPOK(hipGetLastError());
+    HIPOK(hipMemcpyAsync(q, R.out, sizeof q, hipMemcpyDeviceToHost, s));
+    HIPOK(hipStreamSynchronize(s));
+    refine_outer(q, P, F);
+    if (!c.eps_reached && F.rel_kkt <= o.eps_rel && (o.eps_abs_feas <= 0 || F.abs_inf <= o.eps_abs_feas)) {
+      // the eps_rel milestone, reached by the refined point (host clock)
+      c.eps_reached = 1;
+      c.iters_at_eps = c.iters;
+      c.pobj_at_eps = F.pobj;
+      c.rel_kkt_at_eps = F.rel_kkt;
+      c.rel_gap_at_eps = F.rel_gap;
+      std::lock_guard<std::mutex> g(lp->mu);
+      lp->info.t_to_eps_s = now_s() - lp->t_start;
+    }
+    if (o.verbose)
+      fprintf(stderr, "[uclp] refine boundary %d at it %lld: kkt %.2e (p %.1e d %.1e g %.1e) pobj %.12g inner %.2e\n",
+              F.round, (long long)c.iters, F.rel_kkt, F.rel_primal, F.rel_dual, F.rel_gap, F.pobj,
+              F.round > 0 ? c.rel_kkt : 0.0);
+  }
+  int status = stop;
+  if (status == 0) {
+    const bool feas = o.eps_abs_feas <= 0 || F.abs_inf <= o.eps_abs_feas;
+    if (!std::isfinite(F.rel_kkt)) status = UC_LP_NUMERICAL;
+    else if (F.rel_kkt <= o.eps_polish && feas) status = UC_LP_OPTIMAL;
+    else if (c.iters >= o.iter_limit || F.round >= o.refine_max_rounds) status = UC_LP_ITER_LIMIT;
+  }
+  if (status != 0) {
+    c.status = status;
+    c.promote = 0;
+    if (F.have_outer) c.prec = 0;  // the answer is (x*, y*)
+    return restore_scaled_data(lp, s);
+  }
+  const RefineFactors f = refine_factors(q, F.dp, F.dd, o.refine_growth, c.omega);
+  R.dp = f.dp;
+  R.dd = f.dd;
+  launch_refine_form(R, s);
+  launch_init_iterates(lp->D.slot_dev, 1, nullptr, nullptr, P.ni, P.mi, P.m_eq, 1, s);
+  HIPOK(hipGetLastError());
+  HIPOK(hipStreamSynchronize(s));
+  if (F.round == 0) {
+    // tiles of the correction problems: infinite bounds stay infinite, no
+    // other column value is known per block, and inequality duals are
+    // bounded by ylo
+    F.t_flag = P.t_flag;
+    for (int& v : F.t_flag) v &= (kColLInf | kColUInf);
+    F.a_flag.assign(P.a_flag.size(), kRowYlo);
+  }
+  if (o.verbose)
+    fprintf(stderr, "[uclp] refine round %d: D_P %.3e D_D %.3e omega %.3e\n", F.round + 1, f.dp, f.dd, f.omega);
+  F.dp = f.dp;
+  F.dd = f.dd;
+  ++F.round;
+  // The correction problem's KKT error, measured on the scale of the refined
+  // point it corrects: its residuals are D_P, D_D times those of
+  // (x* + x~/D_P, y* + y~/D_D), and its duality gap D_P D_D times that
+  // point's gap up to terms that vanish with the residuals.  So the check
+  // normalises by D_P (1 + ||b||), D_D (1 + ||c||) and D_P D_D (1 + |pobj*|
+  // + |dobj*|), and a round ends once this estimate of the refined point's
+  // error has fallen to eps_refine times its value at the boundary (or to
+  // eps_polish).
+  lp->prm.norm_b = f.dp * (1.0 + P.norm_b) - 1.0;
+  lp->prm.norm_c = f.dd * (1.0 + P.norm_c) - 1.0;
+  lp->prm.gap_den = f.dp * f.dd * (1.0 + std::fabs(F.pobj) + std::fabs(F.dobj));
+  lp->prm.eps_refine = std::max(o.eps_polish, o.eps_refine * F.rel_kkt);
+  // before the refined point has met eps_rel, a round ends as soon as its
+  // estimate says so, and the boundary dates the milestone
+  if (!c.eps_reached) lp->prm.eps_refine = std::max(lp->prm.eps_refine, o.eps_rel);
+  lp->prm.obj_offset = 0.0;
+  // PDHG on the correction problem from (0, 0) takes the steps PDHG on the
+  // original problem would take from (x*, y*) (in exact arithmetic): the run
+  // continues as after a restart there.  The phase's step count carries on,
+  // so the artificial restart rule does not fire again at once, and so do
+  // the iteration counts and the eps_rel milestone.
+  c.round = F.round;
+  c.omega = f.omega;
+  c.prec = 1;
+  c.status = UC_LP_RUNNING;
+  c.promote = 0;
+  c.restart = 0;
+  c.k_inner = 0;
+  c.r_start_set = 0;
+  c.r_prev_set = 0;
+  c.gap_phase = 0;
+  c.best_check = 0;
+  c.best_kkt = 0;
+  c.pw_int = 0;
+  return UC_LP_OK;
 }
 
 // ---- engine worker -----------------------------------------------------------
@@ -1105,6 +1351,7 @@ static void start_instance(uc_engine* E, uc_lp* lp) {
   if (rc == UC_LP_OK) rc = setup_device(lp);
   const int prec = lp->opts.precision == UC_LP_FP64 ? 0 : 1;
   lp->chk = fresh_state(prec, lp->chk.eta, lp->chk.omega);
+  lp->ref = RefineRun();
   lp->prm = make_params(lp->opts, lp->P);
   for (int p = 0; p < 2; ++p)
     half_step_bytes(lp->P, p ? 4 : 8, lp->opts.halpern_gamma == 1.0, &lp->hs_bytes[p][0], &lp->hs_bytes[p][1]);
@@ -1177,8 +1424,9 @@ static hipError_t build_layout(uc_engine* E) {
     lp->slot = a;
     ids[a] = a;
     const int p = lp->chk.prec;
-    push_tiles(tt[p], a, lp->P.t_blk, lp->P.t_ptr, &lp->P.t_flag, &lp->P.t_base);
-    push_tiles(at[p], a, lp->P.a_blk, lp->P.a_ptr, &lp->P.a_flag, &lp->P.a_base);
+    const bool corr = lp->ref.round > 0;  // correction data loaded (refinement)
+    push_tiles(tt[p], a, lp->P.t_blk, lp->P.t_ptr, corr ? &lp->ref.t_flag : &lp->P.t_flag, &lp->P.t_base);
+    push_tiles(at[p], a, lp->P.a_blk, lp->P.a_ptr, corr ? &lp->ref.a_flag : &lp->P.a_flag, &lp->P.a_base);
     SlotDev S = make_slot(lp);
     S.scal = E->d_scal + (size_t)a * kScal;
     S.tau[0] = lp->chk.eta / lp->chk.omega;
@@ -1321,6 +1569,25 @@ static void run_epochs(uc_engine* E) {
     uc_lp* lp = E->active[a];
     lp->chk = chk[a];
     publish_state(E, lp, chk[a], tnow);
+    if (lp->opts.precision == UC_LP_FP32_REFINE) {
+      // a round boundary of iterative refinement, or the end of a run that
+      // is inside a correction problem (its point is folded in unless it
+      // went non-finite)
+      const int dev = lp->chk.status;
+      int rc = UC_LP_OK;
+      if (dev == UC_LP_RUNNING && lp->chk.promote && !lp->host_stop) {
+        rc = refine_boundary(lp, s, true, 0);
+      } else if (lp->ref.round > 0 && (dev != UC_LP_RUNNING || lp->host_stop)) {
+        const int st = dev != UC_LP_RUNNING ? dev : lp->host_stop;
+        rc = refine_boundary(lp, s, st != UC_LP_NUMERICAL, st);
+      }
+      if (rc != UC_LP_OK) {
+        std::fprintf(stderr, "[uclp] refinement step failed: %s\n", g_err.c_str());
+        lp->chk.status = UC_LP_FAILED;
+      }
+      publish_state(E, lp, lp->chk, now_s());
+      continue;
+    }
     if (lp->chk.status == UC_LP_RUNNING && lp->chk.promote && !lp->host_stop) {
       // FP32 x_hat, y_hat -> FP64 iterates of the same slot
       push_tiles(pt, a, lp->P.t_blk, lp->P.t_ptr);
@@ -1888,6 +2155,71 @@ extern "C" int uc_lp_eval_kkt(uc_lp* lp, const double* x, const double* y, uc_lp
   return UC_LP_OK;
 }
 
+extern "C" int uc_lp_debug_refine(uc_lp* lp, const double* x_star, const double* y_star, const float* x_corr,
+                                  const float* y_corr, int32_t first, const double* par, double* x_new,
+                                  double* y_new, double* data64, float* data32, double* scal) {
+  g_err.clear();
+  int rc = debug_ready(lp);
+  if (rc) return rc;
+  if (!x_corr || !y_corr || !par || (!first && (!x_star || !y_star))) return fail(UC_LP_EINVAL, "NULL argument");
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(par[k])) return fail(UC_LP_EINVAL, "par[%d] is not finite", k);
+  if (!(par[0] > 0 && par[1] > 0 && par[2] > 0 && par[3] > 0 && par[4] > 1 && par[5] > 0))
+    return fail(UC_LP_EINVAL, "refinement factors must be positive (growth > 1)");
+  const HostProblem& P = lp->P;
+  DevMem& D = lp->D;
+  hipStream_t s = lp->eng->stream;
+  const size_t n = P.ni, m = P.mi;
+  if (!first) {
+    HIPOK(hipMemcpyAsync(D.d.xhat, x_star, 8 * n, hipMemcpyHostToDevice, s));
+    if (m) HIPOK(hipMemcpyAsync(D.d.yhat, y_star, 8 * m, hipMemcpyHostToDevice, s));
+  }
+  HIPOK(hipMemcpyAsync(D.f.xhat, x_corr, 4 * n, hipMemcpyHostToDevice, s));
+  if (m) HIPOK(hipMemcpyAsync(D.f.yhat, y_corr, 4 * m, hipMemcpyHostToDevice, s));
+  RefineArgs R = refine_args(lp);
+  R.first = first ? 1 : 0;
+  R.inv_dp = par[0];
+  R.inv_dd = par[1];
+  launch_refine_measure(R, s);
+  HIPOK(hipGetLastError());
+  double q[FQ_N];
+  HIPOK(hipMemcpyAsync(q, R.out, sizeof q, hipMemcpyDeviceToHost, s));
+  HIPOK(hipStreamSynchronize(s));
+  const RefineFactors f = refine_factors(q, par[2], par[3], par[4], par[5]);
+  R.dp = f.dp;
+  R.dd = f.dd;
+  launch_refine_form(R, s);
+  HIPOK(hipGetLastError());
+  if (x_new) HIPOK(hipMemcpyAsync(x_new, D.d.xhat, 8 * n, hipMemcpyDeviceToHost, s));
+  if (y_new && m) HIPOK(hipMemcpyAsync(y_new, D.d.yhat, 8 * m, hipMemcpyDeviceToHost, s));
+  if (data64) {
+    HIPOK(hipMemcpyAsync(data64, D.d.c, 8 * n, hipMemcpyDeviceToHost, s));
+    HIPOK(hipMemcpyAsync(data64 + n, D.d.l, 8 * n, hipMemcpyDeviceToHost, s));
+    HIPOK(hipMemcpyAsync(data64 + 2 * n, D.d.u, 8 * n, hipMemcpyDeviceToHost, s));
+    if (m) HIPOK(hipMemcpyAsync(data64 + 3 * n, D.d.b, 8 * m, hipMemcpyDeviceToHost, s));
+  }
+  if (data32) {
+    HIPOK(hipMemcpyAsync(data32, D.f.c, 4 * n, hipMemcpyDeviceToHost, s));
+    HIPOK(hipMemcpyAsync(data32 + n, D.f.l, 4 * n, hipMemcpyDeviceToHost, s));
+    HIPOK(hipMemcpyAsync(data32 + 2 * n, D.f.u, 4 * n, hipMemcpyDeviceToHost, s));
+    if (m) {
+      HIPOK(hipMemcpyAsync(data32 + 3 * n, D.f.b, 4 * m, hipMemcpyDeviceToHost, s));
+      HIPOK(hipMemcpyAsync(data32 + 3 * n + m, D.ylo32, 4 * m, hipMemcpyDeviceToHost, s));
+    }
+  }
+  HIPOK(hipStreamSynchronize(s));
+  RefineRun F;
+  refine_outer(q, P, F);
+  if (scal) {
+    const double v[14] = {f.dp, f.dd, f.omega, q[FQ_VIOL2], q[FQ_DRES2], q[FQ_VIOL2U], q[FQ_BY], q[FQ_VMAXU],
+                          q[FQ_DRES2U], q[FQ_LBUB], q[FQ_CX], f.dp * std::sqrt(std::max(q[FQ_R2U], 0.0)),
+                          f.dd * std::sqrt(std::max(q[FQ_D2U], 0.0)), F.rel_kkt};
+    std::memcpy(scal, v, sizeof v);
+  }
+  // the scaled data arrays held the correction problem
+  return restore_scaled_data(lp, s);
+}
+
 // ---------------------------------------------------------------------------
 // standalone SpMV and bandwidth probes
 // ---------------------------------------------------------------------------
@@ -2342,6 +2674,8 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
   if (!base) return fail(UC_LP_EINVAL, "NULL handle");
   if (n_scen < 1 || n_scen > kMaxScen) return fail(UC_LP_ENOTSUP, "n_scen %d not in 1..%d", n_scen, kMaxScen);
   if (!c || !b || !lb || !ub || !info) return fail(UC_LP_EINVAL, "NULL scenario array");
+  if (base->opts.precision == UC_LP_FP32_REFINE)
+    return fail(UC_LP_ENOTSUP, "scenario batches do not run UC_LP_FP32_REFINE");
   const HostProblem& P = base->P;
   const int S = n_scen, n = P.n, m = P.m, ni = P.ni, mi = P.mi;
   // per-scenario validation and minimal presolve (same fixed-column structure as the base)

@@ -19,7 +19,10 @@ constexpr int kNnzTile = 2048;
 constexpr int kMaxScen = 16;
 
 // Per-block partial sums written by the KKT check kernels.
-enum RowQ { RQ_RES2 = 0, RQ_BY, RQ_DY2, RQ_DYADX, RQ_DY0, RQ_YNEG2, RQ_RESMAX, RQ_N };
+// RQ_YLOR: sum over inequality rows of ylo_i ((A x)_i - b_i), the term that
+// a lower bound ylo != 0 on the inequality duals adds to the primal objective
+// (zero outside the correction problems of iterative refinement).
+enum RowQ { RQ_RES2 = 0, RQ_BY, RQ_DY2, RQ_DYADX, RQ_DY0, RQ_YNEG2, RQ_RESMAX, RQ_YLOR, RQ_N };
 enum ColQ { CQ_DRES2 = 0, CQ_LBUB, CQ_CX, CQ_DX2, CQ_DX0, CQ_N };
 // Per-slot scalars after the final reduction: row quantities then column ones.
 constexpr int kScal = 16;
@@ -73,6 +76,10 @@ struct SlotDev {
   const double* dc;  // D_c (n)
   Vecs<float> f;
   Vecs<double> d;
+  // lower bound of the inequality duals (m, FP32), read by the dual
+  // half-step and the KKT kernels only in tiles flagged kRowYlo (the
+  // correction problems of iterative refinement); elsewhere the bound is 0
+  const float* ylo;
   double* part_a;    // [a_nblk * RQ_N] (scenario batches: [a_nblk * RQ_N * kMaxScen])
   double* part_t;    // [t_nblk * CQ_N] (scenario batches: [t_nblk * CQ_N * kMaxScen])
   double* scal;      // [kScal] (scenario batches: [nscen * kScal])
@@ -117,7 +124,8 @@ enum TileFlag {
   kColLInf = 4,   // l_j == -inf
   kColLNegU = 8,  // l_j == -u_j
   kColUInf = 16,  // u_j == +inf
-  kRowB0 = 1      // b_i == +0
+  kRowB0 = 1,     // b_i == +0
+  kRowYlo = 2     // inequality duals bounded below by SlotDev::ylo instead of 0
 };
 
 // ---- launchers (kernels.hip) --------------------------------------------
@@ -163,6 +171,47 @@ void launch_kkt_ms(int prec, const SlotDev* slots, const Tile* ttiles, int nttil
 size_t red2_ms_doubles();
 void launch_finish_ms(int prec, const SlotDev* slots, int64_t nx, int64_t ny, int kk, hipStream_t s);
 void launch_promote_ms(const SlotDev* slots, int64_t nx, int64_t ny, hipStream_t s);
+
+// iterative refinement: one round boundary of one instance (scaled space).
+// Original scaled data are formed on the fly from the unscaled internal data
+// and D_r, D_c, with the operations of the setup.
+enum RefQ {
+  FQ_VIOL2 = 0,  // ||v||^2, v = (b_hat - A_hat x*) with G rows max(., 0)
+  FQ_R2U,        // sum ((b_hat - A_hat x*)_i / D_r,i)^2  (||b~|| / D_P, unscaled)
+  FQ_VIOL2U,     // sum (v_i / D_r,i)^2
+  FQ_BY,         // b_hat' y*
+  FQ_VMAXU,      // max |v_i / D_r,i|
+  FQ_DRES2,      // ||e||^2, e = d - lambda(d), d = c_hat - A_hat' y*
+  FQ_D2U,        // sum (d_j / D_c,j)^2  (||c~|| / D_D, unscaled)
+  FQ_DRES2U,     // sum (e_j / D_c,j)^2
+  FQ_LBUB,       // sum l_hat lambda+ + u_hat lambda-
+  FQ_CX,         // c_hat' x*
+  FQ_N
+};
+struct RefineArgs {
+  const int *a_ptr, *a_col, *t_ptr, *t_col, *a_blk, *t_blk;
+  const double *a_v, *t_v;                     // scaled FP64 values, CSR order
+  const double *c_in, *b_in, *l_in, *u_in;     // unscaled internal data
+  const double *dr, *dc;
+  int m, n, m_eq, a_nblk, t_nblk, first;
+  double inv_dp, inv_dd;                       // 1/D_P, 1/D_D of the correction folded in
+  double dp, dd;                               // D_P, D_D of the next correction problem
+  double* xs;  // refined point x* (n), y* (m), FP64
+  double* ys;
+  const float* xc;  // correction solve output (n), (m)
+  const float* yc;
+  double* r;       // b_hat - A_hat x* (m)
+  double* d;       // c_hat - A_hat' y* (n)
+  double* part_a;  // FQ partials per row block of A  (a_nblk * 5)
+  double* part_t;  // FQ partials per row block of A^T (t_nblk * 5)
+  double* out;     // FQ_N reduced scalars
+  double *c64, *l64, *u64, *b64;              // correction data, FP64
+  float *c32, *l32, *u32, *b32, *ylo32;       // and as the FP32 solve reads them
+};
+// fold the correction into (x*, y*), then residuals and their FQ scalars
+void launch_refine_measure(const RefineArgs& R, hipStream_t s);
+// correction data of the next round from r, d, x*, y* and R.dp, R.dd
+void launch_refine_form(const RefineArgs& R, hipStream_t s);
 
 // setup
 void launch_expand_rows(const int* ptr, int m, int* row_of, hipStream_t s);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libuclp.so")
 # enums of include/uc_lp.h
 UC_LP_OK, UC_LP_EINVAL, UC_LP_ENOMEM, UC_LP_EBUDGET, UC_LP_EHIP, UC_LP_ESTATE, UC_LP_ENOTSUP, UC_LP_ETIMEOUT = \
     0, -1, -2, -3, -4, -5, -6, -7
-UC_LP_FP64, UC_LP_FP32_MIXED, UC_LP_FP32_MIXED_POLISH = 0, 1, 2
+UC_LP_FP64, UC_LP_FP32_MIXED, UC_LP_FP32_MIXED_POLISH, UC_LP_FP32_REFINE = 0, 1, 2, 3
 (UC_LP_IDLE, UC_LP_QUEUED, UC_LP_RUNNING, UC_LP_OPTIMAL, UC_LP_ITER_LIMIT, UC_LP_TIME_LIMIT,
  UC_LP_CANCELLED, UC_LP_NUMERICAL, UC_LP_INFEASIBLE, UC_LP_FAILED) = range(10)
 UC_LP_SPMV_ROWSPLIT, UC_LP_SPMV_MERGEPATH = 0, 1
@@ -40,7 +40,9 @@ class uc_lp_opts(C.Structure):
                 ("restart_artificial", C.c_double), ("pw_smoothing", C.c_double),
                 ("halpern_gamma", C.c_double), ("pw_max_change", C.c_double),
                 ("fp32_stall_checks", C.c_int32), ("reserved", C.c_int32), ("pw_integral", C.c_double),
-                ("pw_balance", C.c_double), ("pw_balance_polish", C.c_double), ("eps_gap_rel", C.c_double)]
+                ("pw_balance", C.c_double), ("pw_balance_polish", C.c_double), ("eps_gap_rel", C.c_double),
+                ("eps_refine", C.c_double), ("refine_growth", C.c_double), ("refine_max_rounds", C.c_int32),
+                ("reserved2", C.c_int32)]
 
 
 class uc_lp_info(C.Structure):
@@ -56,7 +58,8 @@ class uc_lp_info(C.Structure):
                 ("timed_launches", C.c_int64), ("m_presolved", C.c_int32), ("n_presolved", C.c_int32),
                 ("nnz_presolved", C.c_int64), ("device_bytes", C.c_int64),
                 ("primal_bytes", C.c_double), ("dual_bytes", C.c_double), ("rel_gap_at_eps", C.c_double),
-                ("fp_residual", C.c_double), ("norm_a_bound", C.c_double), ("eta", C.c_double)]
+                ("fp_residual", C.c_double), ("norm_a_bound", C.c_double), ("eta", C.c_double),
+                ("refine_rounds", C.c_int32), ("reserved_i", C.c_int32), ("rel_kkt_inner", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -68,7 +71,7 @@ EXPORTS = ["uc_lp_opts_default", "uc_engine_create", "uc_engine_destroy", "uc_lp
            "uc_lp_update_data", "uc_lp_solve", "uc_lp_status", "uc_lp_wait", "uc_lp_cancel",
            "uc_lp_get_solution", "uc_lp_destroy", "uc_lp_last_error", "uc_lp_solve_scenarios",
            "uc_lp_internal_dims", "uc_lp_get_transpose", "uc_lp_get_scaling", "uc_lp_debug_step",
-           "uc_lp_debug_iterate", "uc_lp_eval_kkt", "uc_spmv", "uc_spmv_bench", "uc_copy_bench", "uc_lp_bench_half_steps",
+           "uc_lp_debug_iterate", "uc_lp_eval_kkt", "uc_lp_debug_refine", "uc_spmv", "uc_spmv_bench", "uc_copy_bench", "uc_lp_bench_half_steps",
            "uc_spmv_merge_noalloc"]
 
 _lib: Optional[C.CDLL] = None
@@ -76,6 +79,7 @@ _lib: Optional[C.CDLL] = None
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int32)
+_F = C.POINTER(C.c_float)
 
 
 def _sig(lib):
@@ -106,6 +110,7 @@ def _sig(lib):
     lib.uc_lp_debug_iterate.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _D, _D, _D, _D, C.c_int64,
                                         C.c_double, C.c_double, _D, _D, _D, _D, _D]
     lib.uc_lp_eval_kkt.argtypes = [_P, _D, _D, C.POINTER(uc_lp_info)]
+    lib.uc_lp_debug_refine.argtypes = [_P, _D, _D, _F, _F, C.c_int32, _D, _D, _D, _D, _F, _D]
     lib.uc_spmv.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int64, _I, _I, _D, _D, _D, C.c_int32,
                             C.c_int32]
     lib.uc_spmv_bench.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int64, _I, _I, _D, C.c_int32,
@@ -117,7 +122,7 @@ def _sig(lib):
     for name in ("uc_engine_create", "uc_lp_create", "uc_lp_update_data", "uc_lp_solve", "uc_lp_status",
                  "uc_lp_wait", "uc_lp_cancel", "uc_lp_get_solution", "uc_lp_solve_scenarios",
                  "uc_lp_internal_dims", "uc_lp_get_transpose", "uc_lp_get_scaling", "uc_lp_debug_step",
-                 "uc_lp_debug_iterate", "uc_lp_eval_kkt", "uc_spmv", "uc_spmv_bench", "uc_copy_bench",
+                 "uc_lp_debug_iterate", "uc_lp_eval_kkt", "uc_lp_debug_refine", "uc_spmv", "uc_spmv_bench", "uc_copy_bench",
                  "uc_lp_bench_half_steps", "uc_spmv_merge_noalloc"):
         getattr(lib, name).restype = C.c_int
 
@@ -319,6 +324,31 @@ def uc_lp_eval_kkt(h, x, y) -> uc_lp_info:
     info = uc_lp_info()
     _check(load().uc_lp_eval_kkt(h, _d(_f64(x)), _d(_f64(y)), C.byref(info)))
     return info
+
+
+def uc_lp_debug_refine(h, x_corr, y_corr, par, x_star=None, y_star=None, first=False):
+    """One refinement round boundary (see include/uc_lp.h).  x_corr, y_corr
+    are rounded to FP32; par = (inv_dp, inv_dd, dp_prev, dd_prev, growth,
+    omega_prev).  Returns dict(x, y, c, l, u, b (FP64), c32, l32, u32, b32,
+    ylo32, scal)."""
+    xc = np.ascontiguousarray(x_corr, dtype=np.float32)
+    yc = np.ascontiguousarray(y_corr, dtype=np.float32)
+    n, m = xc.size, yc.size
+    xs = _f64(x_star) if not first else None
+    ys = _f64(y_star) if not first else None
+    p = _f64(par, 6)
+    xn, yn = np.empty(n), np.empty(max(m, 1))
+    d64 = np.empty(3 * n + m)
+    d32 = np.empty(3 * n + 2 * m, np.float32)
+    sc = np.empty(14)
+    _check(load().uc_lp_debug_refine(h, _d(xs), _d(ys), xc.ctypes.data_as(_F), yc.ctypes.data_as(_F),
+                                      int(bool(first)), _d(p), _d(xn), _d(yn), _d(d64),
+                                      d32.ctypes.data_as(_F), _d(sc)))
+    names = ["dp", "dd", "omega", "viol2", "dres2", "viol2u", "by", "vmaxu", "dres2u", "lbub", "cx",
+             "norm_b_t", "norm_c_t", "rel_kkt"]
+    return dict(x=xn, y=yn[:m], c=d64[:n], l=d64[n:2 * n], u=d64[2 * n:3 * n], b=d64[3 * n:],
+                c32=d32[:n], l32=d32[n:2 * n], u32=d32[2 * n:3 * n], b32=d32[3 * n:3 * n + m],
+                ylo32=d32[3 * n + m:], scal=dict(zip(names, sc)))
 
 
 def uc_spmv(m, n, row_ptr, col_idx, val, x, precision=UC_LP_FP64, algo=UC_LP_SPMV_ROWSPLIT, device=0):

@@ -1,0 +1,220 @@
+"""GPU parity of iterative refinement (precision mode UC_LP_FP32_REFINE).
+
+The round boundary (fold of the correction into the refined point,
+residuals, scale factors, correction data and their FP32 rounding) is
+compared element by element with oracle/refine.py on the scaled internal
+problem, using the device's own D_r, D_c.  Whole solves are compared with
+the oracle's optima (simplex, or the stored HiGHS values), and their KKT
+error is recomputed by the oracle's evaluator."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import pdhg_steps as ps
+from oracle import refine as rf
+from oracle.kkt import kkt
+from oracle.simplex import simplex_solve
+from paper_2607_03627_amd import serving, uclp
+from paper_2607_03627_amd.instances import make_instance
+from test_gpu_parity import GOLDEN, U64, Handle, full_size_case, one_sided_instance, ragged_instance, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    uclp.load()
+
+
+def make_case(shape, seed):
+    if shape == "large":
+        return full_size_case()[0]
+    if shape == "one_sided":
+        return one_sided_instance(seed)
+    if shape == "ragged":
+        return ragged_instance(seed)
+    return make_instance(shape, seed)
+
+
+def scaled_problem(lp, h):
+    """The scaled internal problem with the device's own D_r, D_c (the data
+    formed with the operations the device uses, so they are the same bits)."""
+    ip = ps.internal_problem(lp)
+    d = uclp.uc_lp_internal_dims(h)
+    assert (d["m"], d["n"], d["m_eq"]) == (ip.m, ip.n, ip.m_eq)
+    dr, dc, _ = uclp.uc_lp_get_scaling(h, ip.m, ip.n)
+    Ah = (sp.diags(dr) @ ip.matrix() @ sp.diags(dc)).tocsr()
+    return ip, Ah, ip.c * dc, ip.b * dr, ip.l / dc, ip.u / dc, dr, dc
+
+
+def boundary_inputs(l, u, m, m_eq, seed):
+    rng = np.random.default_rng(seed)
+    n = len(l)
+    xs = np.clip(rng.normal(0.0, 1.0, n), l, u)
+    ys = rng.normal(0.0, 1.0, m)
+    ys[m_eq:] = np.abs(ys[m_eq:])
+    ys[m_eq::3] = 0.0  # inactive inequality rows
+    xc = rng.normal(0.0, 1.0, n).astype(np.float32)
+    yc = rng.normal(0.0, 1.0, m).astype(np.float32)
+    return xs, ys, xc, yc
+
+
+@pytest.mark.parametrize("shape,seed,first", [("tiny", 0, True), ("tiny", 1, False), ("one_sided", 2, False),
+                                              ("ragged", 0, False), ("medium", 1, False), ("medium", 2, True),
+                                              ("large", 0, False)])
+def test_refine_boundary_elementwise(shape, seed, first):
+    say("case refine boundary", shape, seed, first)
+    lp = make_case(shape, seed)
+    with Handle(lp, precision=uclp.UC_LP_FP32_REFINE) as H:
+        ip, Ah, c, b, l, u, dr, dc = scaled_problem(lp, H.h)
+        m, n, m_eq = ip.m, ip.n, ip.m_eq
+        xs, ys, xc, yc = boundary_inputs(l, u, m, m_eq, seed)
+        inv_dp, inv_dd = (1.0, 1.0) if first else (2.5e-3, 4e-2)
+        par = (inv_dp, inv_dd, 1.0 / inv_dp, 1.0 / inv_dd, 1e4, 1.7)
+        g = uclp.uc_lp_debug_refine(H.h, xc, yc, par, x_star=xs, y_star=ys, first=first)
+        # the handle's own data are restored afterwards: the check kernels
+        # evaluate the original problem again
+        z0, y0 = np.clip(np.zeros(lp.n), lp.lb, lp.ub), np.zeros(lp.m)
+        info = uclp.uc_lp_eval_kkt(H.h, z0, y0)
+    sc = g["scal"]
+    r = rf.refine_round(Ah, c, b, l, u, m_eq, None if first else xs, None if first else ys,
+                        xc.astype(np.float64), yc.astype(np.float64), inv_dp, inv_dd, first,
+                        par[2], par[3], par[4], par[5])
+    # fold: one rounding more or less than the oracle (a fused multiply-add)
+    bx = (0.0 if first else np.abs(xs)) + np.abs(xc.astype(np.float64) * inv_dp)
+    by = (0.0 if first else np.abs(ys)) + np.abs(yc.astype(np.float64) * inv_dd)
+    ex = 2 * U64 * bx
+    assert np.all(np.abs(g["x"] - r.x) <= ex)
+    assert np.all(np.abs(g["y"] - r.y) <= 2 * U64 * by)
+    assert np.all(g["x"] >= l) and np.all(g["x"] <= u) and np.all(g["y"][m_eq:] >= 0)
+    # residuals: forward error of a k-term FP64 sum, plus the fold's error
+    absA = abs(Ah)
+    k = max(np.diff(Ah.indptr).max(), np.diff(Ah.tocsc().indptr).max()) + 2
+    er = k * U64 * (np.abs(b) + absA @ np.abs(r.x)) + absA @ ex
+    ed = k * U64 * (np.abs(c) + absA.T @ np.abs(r.y)) + absA.T @ (2 * U64 * by)
+    isG = np.arange(m) >= m_eq
+    nv, ne = np.linalg.norm(r.viol), np.linalg.norm(r.dres)
+    en, ee = np.linalg.norm(er), np.linalg.norm(ed)
+    assert abs(np.sqrt(sc["viol2"]) - nv) <= en + 1e-14 * nv
+    assert abs(np.sqrt(sc["dres2"]) - ne) <= ee + 1e-14 * ne
+    # scale factors: the oracle's rule on the oracle's norms
+    rdp, rdd = (en + 1e-14 * nv) / nv, (ee + 1e-14 * ne) / ne
+    assert abs(sc["dp"] - r.delta_p) <= 1.01 * rdp * r.delta_p
+    assert abs(sc["dd"] - r.delta_d) <= 1.01 * rdd * r.delta_d
+    assert abs(sc["omega"] - r.omega) <= 1.01 * (rdp + rdd) * r.omega + 1e-15 * r.omega
+    # correction data
+    assert np.all(np.abs(g["b"] - r.b_t) <= r.delta_p * 1.01 * er + rdp * 1.01 * np.abs(r.b_t) + 4 * U64 * np.abs(r.b_t))
+    assert np.all(np.abs(g["c"] - r.c_t) <= r.delta_d * 1.01 * ed + rdd * 1.01 * np.abs(r.c_t) + 4 * U64 * np.abs(r.c_t))
+    for gv, rv, bnd in ((g["l"], r.l_t, l), (g["u"], r.u_t, u)):
+        fin = np.isfinite(rv)
+        assert np.array_equal(np.isfinite(gv), fin) and np.array_equal(gv[~fin], rv[~fin])
+        tol = r.delta_p * 1.01 * (ex + 2 * U64 * (np.abs(bnd) + np.abs(r.x))) + (rdp * 1.01 + 4 * U64) * np.abs(rv)
+        assert np.all(np.abs(gv[fin] - rv[fin]) <= tol[fin])
+    # the FP32 data are the device's FP64 data rounded as the oracle rounds
+    assert np.array_equal(g["c32"], g["c"].astype(np.float32))
+    assert np.array_equal(g["b32"], g["b"].astype(np.float32))
+    assert np.array_equal(g["l32"], rf.round_up32(g["l"]))
+    assert np.array_equal(g["u32"], rf.round_down32(g["u"]))
+    ylo = np.where(isG, -sc["dd"] * g["y"], -np.inf)
+    assert np.array_equal(g["ylo32"], rf.round_up32(ylo))
+    assert np.all(g["l32"] <= 0) and np.all(g["u32"] >= 0) and np.all(g["ylo32"][m_eq:] <= 0)
+    # unscaled KKT quantities of the refined point on the original problem
+    vu, eu = r.viol / dr, r.dres / dc
+    evu, edu = er / dr, ed / dc
+    assert abs(np.sqrt(sc["viol2u"]) - np.linalg.norm(vu)) <= 1.01 * np.linalg.norm(evu) + 1e-14 * np.linalg.norm(vu)
+    assert abs(np.sqrt(sc["dres2u"]) - np.linalg.norm(eu)) <= 1.01 * np.linalg.norm(edu) + 1e-14 * np.linalg.norm(eu)
+    assert abs(sc["vmaxu"] - np.abs(vu).max()) <= 1.01 * evu.max() + 1e-14 * np.abs(vu).max()
+    assert abs(sc["cx"] - c @ r.x) <= 1e-12 * (np.abs(c) @ np.abs(r.x)) + np.abs(c) @ ex
+    assert abs(sc["by"] - b @ r.y) <= 1e-12 * (np.abs(b) @ np.abs(r.y)) + np.abs(b) @ (2 * U64 * by)
+    # norms of the correction problem's data, unscaled
+    assert abs(sc["norm_b_t"] - np.linalg.norm(r.b_t / dr)) <= 1e-6 * np.linalg.norm(r.b_t / dr)
+    assert abs(sc["norm_c_t"] - np.linalg.norm(r.c_t / dc)) <= 1e-6 * np.linalg.norm(r.c_t / dc)
+    k0 = kkt(lp, z0, y0)
+    assert abs(info.rel_kkt - k0.rel_kkt) <= 1e-9 * k0.rel_kkt
+
+
+def refine_solve(lp, **opts):
+    o = dict(precision=uclp.UC_LP_FP32_REFINE)
+    o.update(opts)
+    return uclp.solve(lp, uclp.uc_lp_opts_default(**o), timeout_s=300)
+
+
+def oracle_objective(shape, seed, lp):
+    key = f"{shape}/{seed}"
+    if key in GOLDEN:
+        return GOLDEN[key]["obj"]
+    res = simplex_solve(lp)
+    assert res.status == "optimal"
+    return res.obj
+
+
+@pytest.mark.parametrize("shape,seed", [("tiny", 0), ("tiny", 3), ("one_sided", 2), ("ragged", 1),
+                                        ("medium", 0), ("medium", 2)])
+def test_refined_solve_matches_oracle(shape, seed):
+    lp = make_case(shape, seed)
+    z = oracle_objective(shape, seed, lp)
+    say("case refine solve", shape, seed)
+    x, y, info = refine_solve(lp)
+    say("  ", info["status_name"], "iters", info["iters"], "rounds", info["refine_rounds"], "kkt", info["rel_kkt"])
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    assert info["refine_rounds"] >= 1 and info["iters_fp64"] == 0
+    assert info["t_to_eps_s"] > 0 and info["rel_kkt_at_eps"] <= 1e-4
+    k = kkt(lp, x, y)
+    assert k.rel_kkt <= 1e-8 * 1.001
+    assert abs(k.rel_kkt - info["rel_kkt"]) <= 1e-10
+    assert abs(k.pobj - z) <= 1e-6 * abs(z)
+    assert np.all(x >= lp.lb) and np.all(x <= lp.ub)
+
+
+def test_refinement_round_limit_and_cancel():
+    lp = make_instance("medium", 1)
+    # no round allowed: the first boundary ends the solve with the refined
+    # point of the base FP32 solve (ITER_LIMIT), which the oracle evaluates
+    x, y, info = refine_solve(lp, refine_max_rounds=0)
+    assert info["status"] == uclp.UC_LP_ITER_LIMIT and info["refine_rounds"] == 0
+    k = kkt(lp, x, y)
+    assert abs(k.rel_kkt - info["rel_kkt"]) <= 1e-10 and k.rel_kkt <= 1e-4
+    # a cancel inside a correction problem: the point is folded in first
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_REFINE, eps_polish=1e-13,
+                                                      iter_limit=10**7))
+    try:
+        uclp.uc_lp_solve(h)
+        while uclp.uc_lp_status(h).refine_rounds < 2:
+            assert uclp.uc_lp_status(h).status in (uclp.UC_LP_QUEUED, uclp.UC_LP_RUNNING)
+            uclp.uc_lp_wait(h, 0.01)
+        uclp.uc_lp_cancel(h)
+        uclp.uc_lp_wait(h, 60)
+        info = uclp.uc_lp_status(h).as_dict()
+        assert info["status"] == uclp.UC_LP_CANCELLED, info
+        x, y = uclp.uc_lp_get_solution(h, lp.n, lp.m)
+    finally:
+        uclp.uc_lp_destroy(h)
+    k = kkt(lp, x, y)
+    assert abs(k.rel_kkt - info["rel_kkt"]) <= 1e-10
+    assert k.rel_kkt <= 1e-4 and info["refine_rounds"] >= 2
+
+
+def test_refined_alone_and_in_mix_are_bitwise_identical():
+    # round boundaries of one instance happen while others iterate; each
+    # result is the same bits as its solve alone
+    lps = [make_instance("tiny", s) for s in (5, 6, 7)]
+    opts = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_REFINE)
+    alone = [serving.run_stream([lp], [0.0], opts, max_slots=4, keep_solutions=True).served[0] for lp in lps]
+    mix = serving.run_stream(lps, [0.0, 0.001, 0.02], opts, max_slots=4, keep_solutions=True)
+    for a, b, lp in zip(alone, mix.served, lps):
+        assert a.info["status"] == uclp.UC_LP_OPTIMAL and b.info["status"] == uclp.UC_LP_OPTIMAL
+        assert a.info["iters"] == b.info["iters"] and a.info["refine_rounds"] == b.info["refine_rounds"]
+        assert np.array_equal(a.x, b.x) and np.array_equal(a.y, b.y)
+        assert kkt(lp, b.x, b.y).rel_kkt <= 1e-8 * 1.001
+
+
+def test_scenario_batches_refuse_refinement():
+    lp = make_instance("tiny", 0, n_periods=4)
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_REFINE))
+    try:
+        with pytest.raises(uclp.UcLpError) as e:
+            uclp.uc_lp_solve_scenarios(h, lp.n, lp.m, lp.c[None], lp.b[None], lp.lb[None], lp.ub[None])
+        assert e.value.code == uclp.UC_LP_ENOTSUP
+    finally:
+        uclp.uc_lp_destroy(h)
