@@ -559,6 +559,18 @@ def main():
                                       "status": ip_[0]["status_name"], "pobj": ip_[0]["pobj"],
                                       "rel_kkt": ip_[0]["rel_kkt"],
                                       "obj_err_vs_oracle": abs(ip_[0]["pobj"] - zstar) / abs(zstar) if zstar else None}
+            # FP32 to 1e-4, then iterative refinement with FP32 inner solves to 1e-8
+            h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_REFINE,
+                                                               eps_rel=1e-4, eps_polish=1e-8))
+            try:
+                wr, ir = run(h, 1, "refine")
+            finally:
+                uclp.uc_lp_destroy(h)
+            ex["fp32_refine_1e-8"] = {"wall_s": wr[0], "solve_s": ir[0]["t_total_s"], "t_to_1e-4_s": ir[0]["t_to_eps_s"],
+                                      "iters": ir[0]["iters"], "rounds": ir[0]["refine_rounds"],
+                                      "status": ir[0]["status_name"], "pobj": ir[0]["pobj"],
+                                      "rel_kkt": ir[0]["rel_kkt"],
+                                      "obj_err_vs_oracle": abs(ir[0]["pobj"] - zstar) / abs(zstar) if zstar else None}
         except Exception as e:
             ex["extra_error_modes"] = repr(e)
         if args.workload == "large" and args.seed == 0:
