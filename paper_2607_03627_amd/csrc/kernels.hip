@@ -1564,33 +1564,60 @@ __global__ void k_merge_coords(const int* __restrict__ ptr, int m, int64_t nnz, 
   coord[g] = make_int2(row, k);
 }
 
+// One merge-path tile per workgroup: the row ends and entries between two
+// consecutive diagonals (at most kMergeTile items).  The products are staged
+// in LDS in entry order and reduced by a segmented scan whose segments are
+// the rows (a row starts where the previous row ends); the scan is balanced
+// over the threads whatever the row lengths.  Thread t scans entries
+// [kMergeItems t, kMergeItems (t + 1)) sequentially, the per-thread
+// aggregates are combined by a wave-level then a block-level segmented scan,
+// and each thread then finishes its own entries.  The rows that end in the
+// tile are written by consecutive threads (coalesced stores), each reading
+// the scan at its last entry.  A row still open at the end of the tile
+// leaves its partial sum as the tile's carry (k_merge_fixup adds it, in tile
+// order, to the row's value written by the tile where it ends).
+// One merge-path tile per workgroup: the row ends and entries between two
+// consecutive diagonals (at most kMergeTile items).  The products are staged
+// in LDS and reduced by a segmented scan whose segments are the rows (a row
+// starts where the previous row ends), balanced over the threads whatever
+// the row lengths: thread t scans entries [kMergeItems t, kMergeItems (t+1))
+// sequentially, the per-thread aggregates are combined by a wave-level then
+// a block-level segmented scan, and each thread then finishes its own
+// entries.  The rows that end in the tile are written by consecutive
+// threads (coalesced stores), each reading the scan at its last entry.  A
+// row still open at the end of the tile leaves its partial sum as the tile's
+// carry (k_merge_fixup adds the carries, in tile order, to the row's value
+// written by the tile where it ends).  LDS index e + e/8 keeps the
+// per-thread runs of eight on distinct banks.
+__device__ __forceinline__ int merge_lds(int e) { return e + (e >> 3); }
+
 template <typename V>
 __global__ __launch_bounds__(kThreads) void k_spmv_merge(const int* __restrict__ ptr, const int* __restrict__ col,
                                                          const V* __restrict__ val, const V* __restrict__ x,
                                                          V* __restrict__ y, const int2* __restrict__ coord,
                                                          int* __restrict__ carry_row, V* __restrict__ carry_val) {
-  __shared__ int s_end[kMergeTile];
-  __shared__ V s_prod[kMergeTile];
-  __shared__ int s_crow[kThreads];
-  __shared__ V s_cval[kThreads];
+  __shared__ V s_val[kMergeTile + kMergeTile / 8];  // products, then their segmented scan
+  __shared__ int s_end[kMergeTile];                 // ends of the tile's rows, relative to k0
+  __shared__ unsigned char s_head[kMergeTile];      // 1: a row starts at this entry
+  __shared__ V s_wv[kThreads / 64];
+  __shared__ int s_wf[kThreads / 64];
   const int g = blockIdx.x;
   const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
   const int2 c0 = coord[g], c1 = coord[g + 1];
   const int row0 = c0.x, k0 = c0.y;
   const int nrows = c1.x - c0.x;  // row ends this workgroup consumes
   const int nk = c1.y - c0.y;     // entries it consumes
-  // staging: straight-line loads (items past the end re-read the last one)
+  // coalesced straight-line loads (items past the end re-read the last one)
+  int e[kMergeItems];
+  V pv[kMergeItems];
   if (nrows > 0) {
-    int e[kMergeItems];
 #pragma unroll
-    for (int u = 0; u < kMergeItems; ++u) e[u] = ptr[row0 + 1 + min(t + u * kThreads, nrows - 1)];
-#pragma unroll
-    for (int u = 0; u < kMergeItems; ++u)
-      if (t + u * kThreads < nrows) s_end[t + u * kThreads] = e[u];
+    for (int u = 0; u < kMergeItems; ++u) e[u] = ptr[row0 + 1 + min(t + u * kThreads, nrows - 1)] - k0;
   }
   if (nk > 0) {
     int cc[kMergeItems];
-    V vv[kMergeItems], xx[kMergeItems];
+    V vv[kMergeItems];
 #pragma unroll
     for (int u = 0; u < kMergeItems; ++u) {
       const int kk = k0 + min(t + u * kThreads, nk - 1);
@@ -1598,61 +1625,88 @@ __global__ __launch_bounds__(kThreads) void k_spmv_merge(const int* __restrict__
       vv[u] = val[kk];
     }
 #pragma unroll
-    for (int u = 0; u < kMergeItems; ++u) xx[u] = x[cc[u]];
+    for (int u = 0; u < kMergeItems; ++u) pv[u] = vv[u] * x[cc[u]];
+  }
+  const int first = max(ptr[row0] - k0, 0);  // first in-tile entry of row0
 #pragma unroll
-    for (int u = 0; u < kMergeItems; ++u)
-      if (t + u * kThreads < nk) s_prod[t + u * kThreads] = vv[u] * xx[u];
+  for (int u = 0; u < kMergeItems; ++u) {
+    const int i = t + u * kThreads;
+    s_head[i] = 0;
+    if (i < nk) s_val[merge_lds(i)] = pv[u];
   }
   __syncthreads();
-  // this thread's items [d0, d1) of the workgroup's merge, located by a
-  // binary search in LDS
-  const int total = nrows + nk;
-  const int d0 = min(t * kMergeItems, total), d1 = min(d0 + kMergeItems, total);
-  int lo = max(d0 - nk, 0), hi = min(d0, nrows);
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (s_end[mid] - k0 <= d0 - mid - 1) lo = mid + 1;
-    else hi = mid;
-  }
-  int r = lo, k = d0 - lo;
-  V sum = 0, first_val = 0;
-  int first_row = -1;
-  for (int it = d0; it < d1; ++it) {
-    if (r < nrows && s_end[r] - k0 <= k) {
-      if (first_row < 0) {
-        first_row = row0 + r;  // completed after the scan (carry-in from earlier threads)
-        first_val = sum;
-      } else {
-        y[row0 + r] = sum;
+  if (nrows > 0) {
+#pragma unroll
+    for (int u = 0; u < kMergeItems; ++u) {
+      const int i = t + u * kThreads;
+      if (i < nrows) {
+        s_end[i] = e[u];
+        if (e[u] < nk) s_head[e[u]] = 1;  // the next row starts here
       }
-      sum = 0;
-      ++r;
-    } else {
-      sum += s_prod[k];
-      ++k;
     }
   }
-  // carry-out: the row open at the end of this thread's items
-  const int crow = row0 + r;
-  s_crow[t] = crow;
-  s_cval[t] = sum;
   __syncthreads();
-  // inclusive segmented scan of the carries over the threads; rows are
-  // non-decreasing across threads, so equal rows form contiguous runs
-  for (int o = 1; o < kThreads; o <<= 1) {
-    V add = 0;
-    if (t >= o && s_crow[t - o] == crow) add = s_cval[t - o];
-    __syncthreads();
-    s_cval[t] += add;
-    __syncthreads();
+  // this thread's entries: segmented prefix sums from its first entry
+  const int b0 = t * kMergeItems;
+  V acc = 0;
+  int flag = 0;
+#pragma unroll
+  for (int u = 0; u < kMergeItems; ++u) {
+    if (b0 + u < nk) {
+      if (s_head[b0 + u]) {
+        acc = 0;
+        flag = 1;
+      }
+      acc += s_val[merge_lds(b0 + u)];
+      pv[u] = acc;
+    }
   }
-  if (first_row >= 0) {
-    const V cin = (t > 0 && s_crow[t - 1] == first_row) ? s_cval[t - 1] : (V)0;
-    y[first_row] = cin + first_val;
+  // inclusive segmented scan of (flag, aggregate) over the threads:
+  // (f1, v1) then (f2, v2) gives (f1 | f2, f2 ? v2 : v1 + v2)
+  V sv = acc;
+  int sf = flag;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const V ov = __shfl_up(sv, off, 64);
+    const int of = __shfl_up(sf, off, 64);
+    if (lane >= off) {
+      if (!sf) sv += ov;
+      sf |= of;
+    }
   }
-  if (t == kThreads - 1) {
-    carry_row[g] = crow;
-    carry_val[g] = s_cval[t];
+  if (lane == 63) {
+    s_wv[wave] = sv;
+    s_wf[wave] = sf;
+  }
+  // the value of the lane before (inclusive), for this thread's carry-in
+  const V pvv = __shfl_up(sv, 1, 64);
+  const int pff = __shfl_up(sf, 1, 64);
+  __syncthreads();
+  // the segment arriving from earlier waves
+  V wv = 0;
+  for (int w = 0; w < wave; ++w) wv = s_wf[w] ? s_wv[w] : wv + s_wv[w];
+  const V cin = lane == 0 ? wv : (pff ? pvv : wv + pvv);
+  // finish this thread's entries: those before its first row start take the
+  // carry-in
+  int seen = 0;
+#pragma unroll
+  for (int u = 0; u < kMergeItems; ++u) {
+    if (b0 + u < nk) {
+      seen |= s_head[b0 + u];
+      s_val[merge_lds(b0 + u)] = seen ? pv[u] : cin + pv[u];
+    }
+  }
+  __syncthreads();
+  // rows ending in this tile: the scan at their last entry (0 if none here)
+  for (int i = t; i < nrows; i += kThreads) {
+    const int end = s_end[i];
+    const int beg = i == 0 ? first : s_end[i - 1];
+    y[row0 + i] = end > beg ? s_val[merge_lds(end - 1)] : (V)0;
+  }
+  if (t == 0) {
+    const int last = nrows > 0 ? s_end[nrows - 1] : first;
+    carry_row[g] = row0 + nrows;
+    carry_val[g] = nk > last ? s_val[merge_lds(nk - 1)] : (V)0;
   }
 }
 
@@ -2019,22 +2073,27 @@ int merge_workgroups(int m, int64_t nnz) {
 
 template <typename V>
 static void launch_spmv_merge_t(const int* ptr, const int* col, const V* val, const V* x, V* y, int m, int64_t nnz,
-                                int2* coord, int* carry_row, V* carry_val, hipStream_t s) {
+                                int2* coord, int* carry_row, V* carry_val, hipStream_t s, bool planned) {
   const int nwg = merge_workgroups(m, nnz);
   if (nwg <= 0) return;
-  k_merge_coords<<<nb(nwg + 1), kThreads, 0, s>>>(ptr, m, nnz, nwg, coord);
+  if (!planned) k_merge_coords<<<nb(nwg + 1), kThreads, 0, s>>>(ptr, m, nnz, nwg, coord);
   k_spmv_merge<V><<<nwg, kThreads, 0, s>>>(ptr, col, val, x, y, coord, carry_row, carry_val);
   k_merge_fixup<V><<<nb(nwg), kThreads, 0, s>>>(carry_row, carry_val, nwg, m, y);
 }
 
 void launch_spmv_merge64(const int* ptr, const int* col, const double* val, const double* x, double* y, int m,
-                         int64_t nnz, int2* coord, int* carry_row, double* carry_val, hipStream_t s) {
-  launch_spmv_merge_t<double>(ptr, col, val, x, y, m, nnz, coord, carry_row, carry_val, s);
+                         int64_t nnz, int2* coord, int* carry_row, double* carry_val, hipStream_t s, bool planned) {
+  launch_spmv_merge_t<double>(ptr, col, val, x, y, m, nnz, coord, carry_row, carry_val, s, planned);
 }
 
 void launch_spmv_merge32(const int* ptr, const int* col, const float* val, const float* x, float* y, int m,
-                         int64_t nnz, int2* coord, int* carry_row, float* carry_val, hipStream_t s) {
-  launch_spmv_merge_t<float>(ptr, col, val, x, y, m, nnz, coord, carry_row, carry_val, s);
+                         int64_t nnz, int2* coord, int* carry_row, float* carry_val, hipStream_t s, bool planned) {
+  launch_spmv_merge_t<float>(ptr, col, val, x, y, m, nnz, coord, carry_row, carry_val, s, planned);
+}
+
+void launch_merge_coords(const int* ptr, int m, int64_t nnz, int2* coord, hipStream_t s) {
+  const int nwg = merge_workgroups(m, nnz);
+  if (nwg > 0) k_merge_coords<<<nb(nwg + 1), kThreads, 0, s>>>(ptr, m, nnz, nwg, coord);
 }
 
 void launch_norm2(const double* v, int64_t n, double* part, double* out, hipStream_t s) {

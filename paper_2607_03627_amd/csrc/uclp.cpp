@@ -2274,6 +2274,11 @@ static int spmv_prepare(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, co
     std::vector<double> ones(n, 1.0);
     HIPOK(hipMemcpy(S.x, ones.data(), 8 * n, hipMemcpyHostToDevice));
   }
+  // the merge-path coordinates depend on the row pointers only: computed
+  // once here, as the row-split partition is
+  launch_merge_coords(S.ptr, m, nnz, S.coord, s);
+  HIPOK(hipGetLastError());
+  HIPOK(hipStreamSynchronize(s));
   return UC_LP_OK;
 }
 
@@ -2281,13 +2286,13 @@ static void spmv_launch(const SpmvDev& S, int32_t m, int64_t nnz, int prec, int 
   if (prec == UC_LP_FP64) {
     if (algo == UC_LP_SPMV_MERGEPATH)
       launch_spmv_merge64(S.ptr, S.col, (const double*)S.val, (const double*)S.x, (double*)S.y, m, nnz, S.coord,
-                          S.crow, (double*)S.cval, s);
+                          S.crow, (double*)S.cval, s, true);
     else
       launch_spmv64(S.ptr, S.col, (const double*)S.val, (const double*)S.x, (double*)S.y, S.blk, S.nblk, s);
   } else {
     if (algo == UC_LP_SPMV_MERGEPATH)
       launch_spmv_merge32(S.ptr, S.col, (const float*)S.val, (const float*)S.x, (float*)S.y, m, nnz, S.coord,
-                          S.crow, (float*)S.cval, s);
+                          S.crow, (float*)S.cval, s, true);
     else
       launch_spmv32(S.ptr, S.col, (const float*)S.val, (const float*)S.x, (float*)S.y, S.blk, S.nblk, s);
   }

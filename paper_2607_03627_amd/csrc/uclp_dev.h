@@ -254,11 +254,15 @@ void launch_spmv32(const int* ptr, const int* col, const float* val, const float
 constexpr int kMergeItems = 8;
 constexpr int kMergeTile = kThreads * kMergeItems;
 int merge_workgroups(int m, int64_t nnz);
+// planned: coord[] already holds the workgroups' merge coordinates (they
+// depend on the row pointers only; launch_merge_coords computes them)
 void launch_spmv_merge64(const int* ptr, const int* col, const double* val, const double* x,
                          double* y, int m, int64_t nnz, int2* coord, int* carry_row, double* carry_val,
-                         hipStream_t s);
+                         hipStream_t s, bool planned = false);
 void launch_spmv_merge32(const int* ptr, const int* col, const float* val, const float* x, float* y,
-                         int m, int64_t nnz, int2* coord, int* carry_row, float* carry_val, hipStream_t s);
+                         int m, int64_t nnz, int2* coord, int* carry_row, float* carry_val, hipStream_t s,
+                         bool planned = false);
+void launch_merge_coords(const int* ptr, int m, int64_t nnz, int2* coord, hipStream_t s);
 // sum of squares of v (n) into *out (deterministic two-pass); part sized >= 1024
 void launch_norm2(const double* v, int64_t n, double* part, double* out, hipStream_t s);
 // v = w / sqrt(*nrm2)
