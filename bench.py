@@ -168,8 +168,9 @@ def cpu_baseline(lp, workload, seed, time_limit_s=25.0, hard_limit_s=60.0):
 
 def serving_leg(seed=0, n_requests=64, eps=1e-8, iter_limit=400000, extra_streams=0):
     """Poisson stream of differently sized UC LPs (Exp(50 ms) gaps, 300-2000 buses,
-    24 or 48 periods): continuous-batching FP32 + FP64 polish on one engine
-    against plain FP64 PDHG one request at a time (FIFO), same tolerance.
+    24 or 48 periods): continuous batching on one engine, FP32 + FP64 polish
+    and FP32 + iterative refinement, against plain FP64 PDHG one request at
+    a time (FIFO), same tolerance.
     extra_streams > 0 serves that many more streams (seeds 1, 2, ...) in the
     batched mode and pools their latencies with the first for p50 / p99."""
     from paper_2607_03627_amd import serving, uclp
@@ -186,6 +187,13 @@ def serving_leg(seed=0, n_requests=64, eps=1e-8, iter_limit=400000, extra_stream
                             progress=lambda m: log(f"[bench] serving batched: {m}"))
     out["batched_fp32_polish"] = rb.stats
     log(f"[bench] serving batched: {rb.stats}")
+    # the same stream, batched, FP32 with iterative refinement to the same target
+    orf = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_REFINE, eps_rel=1e-4, eps_polish=eps,
+                                  iter_limit=iter_limit)
+    rr = serving.run_stream(lps, arr, orf, max_slots=64, hbm_budget_bytes=200 << 30,
+                            progress=lambda m: log(f"[bench] serving batched refine: {m}"))
+    out["batched_fp32_refine"] = rr.stats
+    log(f"[bench] serving batched refine: {rr.stats}")
     if extra_streams > 0:
         more = [rb]
         for sd in range(seed + 1, seed + 1 + extra_streams):
@@ -204,7 +212,9 @@ def serving_leg(seed=0, n_requests=64, eps=1e-8, iter_limit=400000, extra_stream
     out["fp64_one_at_a_time"] = rf.stats
     log(f"[bench] serving fp64 fifo: {rf.stats}")
     out["throughput_ratio"] = rb.stats["solves_per_s"] / rf.stats["solves_per_s"]
+    out["throughput_ratio_refine"] = rr.stats["solves_per_s"] / rf.stats["solves_per_s"]
     out["worst_rel_kkt"] = {"batched": max(s.info["rel_kkt"] for s in rb.served),
+                            "batched_refine": max(s.info["rel_kkt"] for s in rr.served),
                             "fp64": max(s.info["rel_kkt"] for s in rf.served)}
     return out
 

@@ -181,7 +181,8 @@ typedef struct {
      primal weight carries over, times the change of D_D / D_P.           */
   double eps_refine;     /* error reduction asked of each round, 1e-2         */
   double refine_growth;  /* bound on the growth of D_P and D_D per round, 1e4 */
-  int32_t refine_max_rounds; /* default 20                                    */
+  int32_t refine_max_rounds; /* default 200 (a round is a restart of the inner
+                            solve: the iteration limit is the real bound)    */
   int32_t reserved2;     /* must be 0                                         */
 } uc_lp_opts;
 

@@ -107,7 +107,7 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->eps_gap_rel = 0.0;
   o->eps_refine = 1e-2;
   o->refine_growth = 1e4;
-  o->refine_max_rounds = 20;
+  o->refine_max_rounds = 200;
   o->reserved2 = 0;
 }
 

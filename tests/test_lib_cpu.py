@@ -74,7 +74,7 @@ def test_binding_structs_match_header_layout():
     assert ctypes.sizeof(uclp.uc_lp_opts) == 4 * 4 + 8 + 5 * 8 + 4 * 4 + 6 * 8 + 2 * 4 + 4 * 8 + 2 * 8 + 2 * 4
     o = uclp.uc_lp_opts_default()
     assert o.eps_gap_rel == 0.0
-    assert o.eps_refine == 1e-2 and o.refine_growth == 1e4 and o.refine_max_rounds == 20 and o.reserved2 == 0
+    assert o.eps_refine == 1e-2 and o.refine_growth == 1e4 and o.refine_max_rounds == 200 and o.reserved2 == 0
     assert o.precision == uclp.UC_LP_FP32_MIXED_POLISH and o.kkt_every == 64
     assert o.iter_limit == 100000 and o.eps_rel == 1e-4 and o.eps_polish == 1e-8
     assert (o.restart_sufficient, o.restart_necessary, o.restart_artificial, o.pw_smoothing) == \
