@@ -1722,8 +1722,26 @@ __global__ void k_merge_fixup(const int* __restrict__ carry_row, const V* __rest
   const int r = carry_row[g];
   if (r >= m) return;
   if (g > 0 && carry_row[g - 1] == r) return;
+  // the run's carries in order, eight independent loads at a time (a long
+  // row spans many tiles)
   V s = 0;
-  for (int u = g; u < nwg && carry_row[u] == r; ++u) s += carry_val[u];
+  for (int u = g; u < nwg; u += 8) {
+    int rr[8];
+    V vv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = min(u + k, nwg - 1);
+      rr[k] = carry_row[i];
+      vv[k] = carry_val[i];
+    }
+    bool more = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      more = more && u + k < nwg && rr[k] == r;
+      if (more) s += vv[k];
+    }
+    if (!more) break;
+  }
   y[r] = s + y[r];
 }
 
