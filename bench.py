@@ -88,13 +88,13 @@ def measured_traffic(kernel="k_primal"):
     return rec.get(kernel, {}).get("traffic_bytes")
 
 
-def _cpu_baseline_child(workload, seed, time_limit_s, q):
+def _cpu_baseline_child(workload, seed, time_limit_s, q, kw=None):
     """Child process of cpu_baseline: builds the workload and runs the oracle
     on it, then reports status, wall and CPU seconds of the solve."""
     from oracle.reference import highs_solve
     from paper_2607_03627_amd.instances import make_instance
 
-    lp = make_instance(workload, seed)
+    lp = make_instance(workload, seed, **(kw or {}))
     q.put(("start", time.perf_counter()))
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
@@ -104,11 +104,12 @@ def _cpu_baseline_child(workload, seed, time_limit_s, q):
     q.put(("done", int(st), wall, (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)))
 
 
-def cpu_baseline(lp, workload, seed, time_limit_s=25.0, hard_limit_s=60.0):
+def cpu_baseline(lp, workload, seed, time_limit_s=25.0, hard_limit_s=60.0, kw=None):
     """The oracle (HiGHS interior point through oracle/reference.py) on the
     workload itself, in a child process: the measured time if it finishes,
     else a lower bound.  HiGHS checks its own time limit only between
-    iterations, so the child is also stopped at a hard wall-clock limit."""
+    iterations, so the child is also stopped at a hard wall-clock limit.
+    kw: extra arguments of make_instance for the workload."""
     import multiprocessing as mp
     import queue as _queue
 
@@ -117,7 +118,7 @@ def cpu_baseline(lp, workload, seed, time_limit_s=25.0, hard_limit_s=60.0):
     ctx = mp.get_context("spawn")
     q = ctx.Queue()
     ru0 = resource.getrusage(resource.RUSAGE_CHILDREN)
-    proc = ctx.Process(target=_cpu_baseline_child, args=(workload, seed, time_limit_s, q), daemon=True)
+    proc = ctx.Process(target=_cpu_baseline_child, args=(workload, seed, time_limit_s, q, kw), daemon=True)
     proc.start()
     t_start, res = None, None
     t_spawn = time.perf_counter()
@@ -171,8 +172,9 @@ def serving_leg(seed=0, n_requests=64, eps=1e-8, iter_limit=400000, extra_stream
     24 or 48 periods): continuous batching on one engine, FP32 + FP64 polish
     and FP32 + iterative refinement, against plain FP64 PDHG one request at
     a time (FIFO), same tolerance.
-    extra_streams > 0 serves that many more streams (seeds 1, 2, ...) in the
-    batched mode and pools their latencies with the first for p50 / p99."""
+    extra_streams > 0 serves that many more streams (seeds 1, 2, ...) batched
+    with refinement and pools their latencies with the first refinement
+    stream for p50 / p99."""
     from paper_2607_03627_amd import serving, uclp
     from paper_2607_03627_amd.instances import make_instance, serving_stream
 
@@ -195,17 +197,17 @@ def serving_leg(seed=0, n_requests=64, eps=1e-8, iter_limit=400000, extra_stream
     out["batched_fp32_refine"] = rr.stats
     log(f"[bench] serving batched refine: {rr.stats}")
     if extra_streams > 0:
-        more = [rb]
+        more = [rr]
         for sd in range(seed + 1, seed + 1 + extra_streams):
             rq = serving_stream(sd, n_requests)
-            r = serving.run_stream([make_instance(q.shape, q.seed) for q in rq], [q.arrival_s for q in rq], ob,
+            r = serving.run_stream([make_instance(q.shape, q.seed) for q in rq], [q.arrival_s for q in rq], orf,
                                    max_slots=64, hbm_budget_bytes=200 << 30,
                                    progress=lambda m: log(f"[bench] serving stream {sd}: {m}"))
-            log(f"[bench] serving batched stream {sd}: {r.stats}")
+            log(f"[bench] serving batched refine stream {sd}: {r.stats}")
             more.append(r)
-        out["batched_pooled"] = serving.pooled_latency(more)
-        out["batched_pooled"]["streams"] = len(more)
-        out["batched_pooled"]["solves_per_s_by_stream"] = [r.stats["solves_per_s"] for r in more]
+        out["batched_refine_pooled"] = serving.pooled_latency(more)
+        out["batched_refine_pooled"]["streams"] = len(more)
+        out["batched_refine_pooled"]["solves_per_s_by_stream"] = [r.stats["solves_per_s"] for r in more]
     of = uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP64, eps_rel=eps, iter_limit=iter_limit)
     rf = serving.run_stream(lps, arr, of, max_slots=1, hbm_budget_bytes=200 << 30,
                             progress=lambda m: log(f"[bench] serving fp64 fifo: {m}"))
@@ -316,12 +318,12 @@ def race_leg(large_lp):
     return {"poll_s": 0.5, "cases": rows, "wins": wins}
 
 
-def size_sweep_leg(time_limit_s=60.0):
+def size_sweep_leg(time_limit_s=45.0):
     """GPU PDHG against the CPU oracle leg across problem sizes: where does the
     GPU stop paying off?  Each LP is solved by the library (FP32 to 1e-4, and
     FP32 + FP64 polish to 1e-8) and by HiGHS interior point with crossover on
     the host cores (stopped at a time limit)."""
-    from oracle.reference import highs_solve, host_threads
+    from oracle.reference import host_threads
     from paper_2607_03627_amd import uclp
     from paper_2607_03627_amd.instances import make_instance
 
@@ -338,8 +340,8 @@ def size_sweep_leg(time_limit_s=60.0):
             _, _, info = uclp.solve(lp, uclp.uc_lp_opts_default(**o), timeout_s=600)
             r[label] = {"create_to_done_s": time.perf_counter() - t, "solve_s": info["t_total_s"],
                         "status": info["status_name"], "iters": info["iters"], "pobj": info["pobj"]}
-        st, obj, _, _, secs = highs_solve(lp, "highs-ipm", time_limit=time_limit_s)
-        r["cpu_highs_ipm"] = {"s": secs, "status": st, "obj": obj, "finished": st == 0,
+        cb = cpu_baseline(lp, shape, seed, time_limit_s=time_limit_s, hard_limit_s=time_limit_s + 30.0, kw=kw)
+        r["cpu_highs_ipm"] = {"s": cb["value"], "finished": cb["bound"] == "measured", "cores": cb["cores"],
                               "host_cores": host_threads()}
         log(f"[bench] size sweep {r}")
         rows.append(r)
@@ -397,7 +399,7 @@ def main():
     ap.add_argument("--no-scenarios", action="store_true", help="skip the 16-scenario batch leg")
     ap.add_argument("--scenarios-full", action="store_true",
                     help="scenario leg with the cold batch and sequential FP32 solves")
-    ap.add_argument("--race", action="store_true", help="also run the GPU-CPU race on five LPs")
+    ap.add_argument("--no-race", action="store_true", help="skip the GPU-CPU race on five LPs")
     ap.add_argument("--size-sweep", action="store_true", help="GPU vs CPU oracle across problem sizes")
     ap.add_argument("--dual-form", action="store_true", help="the LP and its dual on the same library")
     ap.add_argument("--serving-streams", type=int, default=1,
@@ -621,7 +623,7 @@ def main():
             out["dual_form"] = dual_form_leg()
         except Exception as e:
             out["dual_form"] = {"error": repr(e)}
-    if args.race:
+    if not args.no_race:
         try:
             out["race"] = race_leg(lp)
         except Exception as e:

@@ -474,8 +474,8 @@ int uc_lp_bench_half_steps(uc_lp* lp, int32_t precision, int32_t copies, int32_t
  * the stream reaches them.  Same results, bit for bit, as uc_spmv on the
  * same values.
  * Scratch: a static 4 MiB array on each device (workgroup coordinates and
- * carries, 20 bytes per 2,048 rows + entries), held until the process ends;
- * m + nnz up to about 4.2e8.  Larger inputs: ENOTSUP, before any launch.  The
+ * carries, 20 bytes per 1,792 rows + entries), held until the process ends;
+ * m + nnz up to about 3.7e8.  Larger inputs: ENOTSUP, before any launch.  The
  * kernels overwrite every scratch entry they read, so nothing needs clearing,
  * but calls that overlap in time on one device (other streams, other host
  * threads) share the scratch and race: serialize them.

@@ -1531,16 +1531,16 @@ __global__ __launch_bounds__(kThreads) void k_spmv(const int* __restrict__ ptr, 
 
 // ---- merge-path SpMV (Merrill & Garland, SC'16) -----------------------------
 // The merge of the row-end list (row_ptr[1..m]) with the entry indices
-// 0..nnz-1 has m + nnz items; workgroup g takes items [g T, (g + 1) T) with
-// T = kMergeTile.  A small kernel finds every workgroup's start coordinate
-// (rows consumed, entries consumed) by a binary search along its diagonal.
-// A workgroup then stages its rows' ends and its entries' products in LDS
-// with coalesced loads, and each thread walks kMergeItems items of the
-// staged merge: a row end emits the row's sum, an entry adds its product.
-// A row that spans threads is completed by a segmented scan over the
-// threads' carries (in a fixed order); a row that spans workgroups gets the
+// 0..nnz-1 has m + nnz items; workgroup g starts near item g S with
+// S = kMergeStep.  A small kernel finds every workgroup's start coordinate
+// (rows consumed, entries consumed) by a binary search along its diagonal,
+// then moves it back to the start of the row it falls in when that row
+// began at most kMergeSlack items earlier: a tile then ends at a row
+// boundary unless a long row crosses it, and holds at most
+// S + kMergeSlack = kMergeTile items.  A row that spans workgroups gets the
 // carries of the earlier workgroups added, in workgroup order, by a fix-up
-// kernel.  Every sum is formed in an order fixed by the matrix alone.
+// kernel (not launched when no tile ends inside a row).  Every sum is
+// formed in an order fixed by the matrix alone.
 __device__ inline void merge_search(int64_t diag, const int* __restrict__ row_end, int m, int64_t nnz,
                                     int& row, int& k) {
   int lo = (int)max(diag - nnz, (int64_t)0);
@@ -1558,24 +1558,16 @@ __device__ inline void merge_search(int64_t diag, const int* __restrict__ row_en
 __global__ void k_merge_coords(const int* __restrict__ ptr, int m, int64_t nnz, int nwg, int2* __restrict__ coord) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g > nwg) return;
-  const int64_t d = min((int64_t)g * kMergeTile, (int64_t)m + nnz);
+  const int64_t d = min((int64_t)g * kMergeStep, (int64_t)m + nnz);
   int row, k;
   merge_search(d, ptr + 1, m, nnz, row, k);
+  if (row < m) {
+    const int start = ptr[row];
+    if (k > start && k - start <= kMergeSlack) k = start;  // end the previous tile at a row boundary
+  }
   coord[g] = make_int2(row, k);
 }
 
-// One merge-path tile per workgroup: the row ends and entries between two
-// consecutive diagonals (at most kMergeTile items).  The products are staged
-// in LDS in entry order and reduced by a segmented scan whose segments are
-// the rows (a row starts where the previous row ends); the scan is balanced
-// over the threads whatever the row lengths.  Thread t scans entries
-// [kMergeItems t, kMergeItems (t + 1)) sequentially, the per-thread
-// aggregates are combined by a wave-level then a block-level segmented scan,
-// and each thread then finishes its own entries.  The rows that end in the
-// tile are written by consecutive threads (coalesced stores), each reading
-// the scan at its last entry.  A row still open at the end of the tile
-// leaves its partial sum as the tile's carry (k_merge_fixup adds it, in tile
-// order, to the row's value written by the tile where it ends).
 // One merge-path tile per workgroup: the row ends and entries between two
 // consecutive diagonals (at most kMergeTile items).  The products are staged
 // in LDS and reduced by a segmented scan whose segments are the rows (a row
@@ -2086,27 +2078,30 @@ void launch_spmv32(const int* ptr, const int* col, const float* val, const float
 }
 
 int merge_workgroups(int m, int64_t nnz) {
-  return (int)(((int64_t)m + nnz + kMergeTile - 1) / kMergeTile);
+  return (int)(((int64_t)m + nnz + kMergeStep - 1) / kMergeStep);
 }
 
 template <typename V>
 static void launch_spmv_merge_t(const int* ptr, const int* col, const V* val, const V* x, V* y, int m, int64_t nnz,
-                                int2* coord, int* carry_row, V* carry_val, hipStream_t s, bool planned) {
+                                int2* coord, int* carry_row, V* carry_val, hipStream_t s, bool planned,
+                                bool fixup) {
   const int nwg = merge_workgroups(m, nnz);
   if (nwg <= 0) return;
   if (!planned) k_merge_coords<<<nb(nwg + 1), kThreads, 0, s>>>(ptr, m, nnz, nwg, coord);
   k_spmv_merge<V><<<nwg, kThreads, 0, s>>>(ptr, col, val, x, y, coord, carry_row, carry_val);
-  k_merge_fixup<V><<<nb(nwg), kThreads, 0, s>>>(carry_row, carry_val, nwg, m, y);
+  if (fixup || !planned) k_merge_fixup<V><<<nb(nwg), kThreads, 0, s>>>(carry_row, carry_val, nwg, m, y);
 }
 
 void launch_spmv_merge64(const int* ptr, const int* col, const double* val, const double* x, double* y, int m,
-                         int64_t nnz, int2* coord, int* carry_row, double* carry_val, hipStream_t s, bool planned) {
-  launch_spmv_merge_t<double>(ptr, col, val, x, y, m, nnz, coord, carry_row, carry_val, s, planned);
+                         int64_t nnz, int2* coord, int* carry_row, double* carry_val, hipStream_t s, bool planned,
+                         bool fixup) {
+  launch_spmv_merge_t<double>(ptr, col, val, x, y, m, nnz, coord, carry_row, carry_val, s, planned, fixup);
 }
 
 void launch_spmv_merge32(const int* ptr, const int* col, const float* val, const float* x, float* y, int m,
-                         int64_t nnz, int2* coord, int* carry_row, float* carry_val, hipStream_t s, bool planned) {
-  launch_spmv_merge_t<float>(ptr, col, val, x, y, m, nnz, coord, carry_row, carry_val, s, planned);
+                         int64_t nnz, int2* coord, int* carry_row, float* carry_val, hipStream_t s, bool planned,
+                         bool fixup) {
+  launch_spmv_merge_t<float>(ptr, col, val, x, y, m, nnz, coord, carry_row, carry_val, s, planned, fixup);
 }
 
 void launch_merge_coords(const int* ptr, int m, int64_t nnz, int2* coord, hipStream_t s) {

@@ -2229,6 +2229,7 @@ struct SpmvDev {
   void *val = nullptr, *x = nullptr, *y = nullptr, *cval = nullptr;
   int2* coord = nullptr;
   int nblk = 0;
+  bool fixup = true;  // some merge tile ends inside a row
 };
 
 static void spmv_free(SpmvDev& S) {
@@ -2275,10 +2276,16 @@ static int spmv_prepare(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, co
     HIPOK(hipMemcpy(S.x, ones.data(), 8 * n, hipMemcpyHostToDevice));
   }
   // the merge-path coordinates depend on the row pointers only: computed
-  // once here, as the row-split partition is
+  // once here, as the row-split partition is; the fix-up is needed only if
+  // a tile ends inside a row
   launch_merge_coords(S.ptr, m, nnz, S.coord, s);
   HIPOK(hipGetLastError());
+  std::vector<int2> cd((size_t)nc + 1);
+  HIPOK(hipMemcpyAsync(cd.data(), S.coord, sizeof(int2) * (nc + 1), hipMemcpyDeviceToHost, s));
   HIPOK(hipStreamSynchronize(s));
+  S.fixup = false;
+  for (int g = 1; g < nc; ++g)
+    if (cd[g].x < m && cd[g].y > rp[cd[g].x]) S.fixup = true;
   return UC_LP_OK;
 }
 
@@ -2286,13 +2293,13 @@ static void spmv_launch(const SpmvDev& S, int32_t m, int64_t nnz, int prec, int 
   if (prec == UC_LP_FP64) {
     if (algo == UC_LP_SPMV_MERGEPATH)
       launch_spmv_merge64(S.ptr, S.col, (const double*)S.val, (const double*)S.x, (double*)S.y, m, nnz, S.coord,
-                          S.crow, (double*)S.cval, s, true);
+                          S.crow, (double*)S.cval, s, true, S.fixup);
     else
       launch_spmv64(S.ptr, S.col, (const double*)S.val, (const double*)S.x, (double*)S.y, S.blk, S.nblk, s);
   } else {
     if (algo == UC_LP_SPMV_MERGEPATH)
       launch_spmv_merge32(S.ptr, S.col, (const float*)S.val, (const float*)S.x, (float*)S.y, m, nnz, S.coord,
-                          S.crow, (float*)S.cval, s, true);
+                          S.crow, (float*)S.cval, s, true, S.fixup);
     else
       launch_spmv32(S.ptr, S.col, (const float*)S.val, (const float*)S.x, (float*)S.y, S.blk, S.nblk, s);
   }
@@ -2574,7 +2581,7 @@ extern "C" int uc_spmv_merge_noalloc(int device, int32_t m, int32_t n, int64_t n
   if (precision != UC_LP_FP64 && precision != UC_LP_FP32_MIXED) return fail(UC_LP_ENOTSUP, "precision %d", precision);
   const size_t vb = precision == UC_LP_FP64 ? 8 : 4;
   const int64_t items = (int64_t)m + nnz;
-  const int64_t nwg64 = (items + kMergeTile - 1) / kMergeTile;
+  const int64_t nwg64 = (items + kMergeStep - 1) / kMergeStep;  // merge_workgroups without its int range
   size_t off_row = 0, off_val = 0;
   const size_t need = nwg64 < INT32_MAX ? merge_scratch_layout((int)nwg64, vb, &off_row, &off_val) : SIZE_MAX;
   if (need > kNoAllocScratchBytes)

@@ -248,20 +248,26 @@ void launch_spmv64(const int* ptr, const int* col, const double* val, const doub
                    const int* blk, int nblk, hipStream_t s);
 void launch_spmv32(const int* ptr, const int* col, const float* val, const float* x, float* y,
                    const int* blk, int nblk, hipStream_t s);
-// merge-path SpMV: kMergeItems merge items (row ends + entries) per thread,
-// kMergeTile per workgroup; nwg = merge_workgroups(m, nnz) workgroups and
-// scratch of coord[nwg + 1], carry_row[nwg], carry_val[nwg]
+// merge-path SpMV: at most kMergeTile merge items (row ends + entries) per
+// workgroup, kMergeItems per thread; tiles start every kMergeStep items,
+// moved back by at most kMergeSlack to a row start.  nwg =
+// merge_workgroups(m, nnz) workgroups and scratch of coord[nwg + 1],
+// carry_row[nwg], carry_val[nwg]
 constexpr int kMergeItems = 8;
 constexpr int kMergeTile = kThreads * kMergeItems;
+constexpr int kMergeSlack = kThreads;
+constexpr int kMergeStep = kMergeTile - kMergeSlack;
 int merge_workgroups(int m, int64_t nnz);
 // planned: coord[] already holds the workgroups' merge coordinates (they
-// depend on the row pointers only; launch_merge_coords computes them)
+// depend on the row pointers only; launch_merge_coords computes them), and
+// fixup = false skips the carry fix-up (correct when no tile ends inside a
+// row); unplanned launches compute the coordinates and always fix up
 void launch_spmv_merge64(const int* ptr, const int* col, const double* val, const double* x,
                          double* y, int m, int64_t nnz, int2* coord, int* carry_row, double* carry_val,
-                         hipStream_t s, bool planned = false);
+                         hipStream_t s, bool planned = false, bool fixup = true);
 void launch_spmv_merge32(const int* ptr, const int* col, const float* val, const float* x, float* y,
                          int m, int64_t nnz, int2* coord, int* carry_row, float* carry_val, hipStream_t s,
-                         bool planned = false);
+                         bool planned = false, bool fixup = true);
 void launch_merge_coords(const int* ptr, int m, int64_t nnz, int2* coord, hipStream_t s);
 // sum of squares of v (n) into *out (deterministic two-pass); part sized >= 1024
 void launch_norm2(const double* v, int64_t n, double* part, double* out, hipStream_t s);

@@ -67,12 +67,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--large", action="store_true", help="also the 6,049-bus-shaped grids")
     ap.add_argument("--only", default=None)
+    ap.add_argument("--large-method", default="highs-ipm", choices=["highs-ipm", "highs-ds"],
+                    help="HiGHS method for the 6,049-bus-shaped grids")
     args = ap.parse_args()
     d = load()
     jobs = [(f"tiny/{s}", "tiny", s, "simplex") for s in range(10)]
     jobs += [(f"medium/{s}", "medium", s, "highs-ds") for s in range(3)]
     if args.large:
-        jobs += [("large_kc0/0", "large_kc0", 0, "highs-ipm"), ("large/0", "large", 0, "highs-ipm")]
+        jobs += [("large_kc0/0", "large_kc0", 0, args.large_method), ("large/0", "large", 0, args.large_method)]
     for key, shape, seed, method in jobs:
         if args.only and not key.startswith(args.only):
             continue
