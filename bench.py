@@ -402,8 +402,9 @@ def main():
     ap.add_argument("--no-race", action="store_true", help="skip the GPU-CPU race on five LPs")
     ap.add_argument("--size-sweep", action="store_true", help="GPU vs CPU oracle across problem sizes")
     ap.add_argument("--dual-form", action="store_true", help="the LP and its dual on the same library")
-    ap.add_argument("--serving-streams", type=int, default=1,
-                    help="batched serving over this many streams (latencies pooled for p50 / p99)")
+    ap.add_argument("--serving-streams", type=int, default=5,
+                    help="batched refinement serving over this many request streams (latencies pooled for "
+                         "p50 / p99; 5 streams = 320 requests)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
