@@ -277,6 +277,24 @@ int uc_lp_create(uc_engine* eng, int32_t m, int32_t n, int64_t nnz,
                  const double* lb, const double* ub, const uc_lp_opts* opts,
                  uc_lp** out);
 
+/* uc_lp_create with the problem in DEVICE memory of the engine's device
+ * (device 0 when eng == NULL), e.g. the storage of torch tensors: the same
+ * arrays, types and validation as uc_lp_create.  The arrays are read on
+ * hip_stream (NULL: the null stream), so after the work the caller enqueued
+ * there, and deep-copied (through the host: the minimal presolve and the
+ * row-block partition are host work) before the call returns; the caller
+ * keeps ownership and may reuse them at once.  EINVAL also when a pointer
+ * is not device memory of that device; EHIP when a copy fails.  The
+ * caller's current device is restored on return.  A process that also uses
+ * PyTorch must initialise torch's GPU before it loads this library: torch
+ * ships its own HIP runtime under the same soname, and the process can hold
+ * only one of the two. */
+int uc_lp_create_device(uc_engine* eng, int32_t m, int32_t n, int64_t nnz,
+                        const int32_t* row_ptr, const int32_t* col_idx, const double* val,
+                        const double* c, const double* b, const char* sense,
+                        const double* lb, const double* ub, const uc_lp_opts* opts,
+                        void* hip_stream, uc_lp** out);
+
 /* Replace c, b, lb, ub (any may be NULL = keep) of an instance that is not
  * running; the matrix is unchanged.  Same validation as uc_lp_create. */
 int uc_lp_update_data(uc_lp* lp, const double* c, const double* b,
@@ -305,6 +323,13 @@ int uc_lp_cancel(uc_lp* lp);
  * x[n], y[m] (either may be NULL).  ESTATE unless the status is terminal
  * (OPTIMAL, ITER_LIMIT, TIME_LIMIT, CANCELLED or NUMERICAL). */
 int uc_lp_get_solution(const uc_lp* lp, double* x, double* y);
+
+/* uc_lp_get_solution into DEVICE buffers x[n], y[m] (double; either may be
+ * NULL) of the instance's device, enqueued on hip_stream (NULL: the null
+ * stream): the values are there when the stream reaches the copies.  The
+ * caller owns the buffers.  ESTATE as uc_lp_get_solution; EINVAL for
+ * pointers that are not device memory of that device. */
+int uc_lp_get_solution_device(const uc_lp* lp, double* x, double* y, void* hip_stream);
 
 /* Cancel if running, wait, release device memory.  NULL is a no-op. */
 void uc_lp_destroy(uc_lp* lp);

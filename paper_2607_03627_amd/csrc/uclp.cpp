@@ -3146,3 +3146,86 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
     });
   return UC_LP_OK;
 }
+
+// ---------------------------------------------------------------------------
+// problem and solution in caller-owned device memory
+// ---------------------------------------------------------------------------
+
+// D2H copy of n elements on s (n = 0: nothing).
+template <typename T>
+static int read_device(std::vector<T>& dst, const T* src, size_t n, hipStream_t s) {
+  dst.resize(n);
+  if (n) HIPOK(hipMemcpyAsync(dst.data(), src, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+  return UC_LP_OK;
+}
+
+extern "C" int uc_lp_create_device(uc_engine* eng, int32_t m, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                                   const int32_t* col_idx, const double* val, const double* c, const double* b,
+                                   const char* sense, const double* lb, const double* ub, const uc_lp_opts* opts,
+                                   void* hip_stream, uc_lp** out) {
+  g_err.clear();
+  if (!out) return fail(UC_LP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (m < 1 || n < 1 || nnz < 0) return fail(UC_LP_EINVAL, "m=%d n=%d nnz=%lld", m, n, (long long)nnz);
+  if (!row_ptr || !c || !b || !sense || !lb || !ub || (nnz > 0 && (!col_idx || !val)))
+    return fail(UC_LP_EINVAL, "NULL array");
+  const int device = eng ? eng->device : 0;
+  int prev = 0;
+  HIPOK(hipGetDevice(&prev));
+  HIPOK(hipSetDevice(device));
+  int rc = UC_LP_OK;
+  const void* ptrs[9] = {row_ptr, col_idx, val, c, b, sense, lb, ub, nullptr};
+  const char* names[8] = {"row_ptr", "col_idx", "val", "c", "b", "sense", "lb", "ub"};
+  for (int i = 0; i < 8 && rc == UC_LP_OK; ++i)
+    if (ptrs[i]) rc = check_device_pointer(ptrs[i], device, names[i]);
+  // deep copies to the host (the presolve and the row-block partition are
+  // host work), read after what the caller enqueued on its stream
+  std::vector<int32_t> hp, hc;
+  std::vector<double> hv, hcst, hb, hl, hu;
+  std::vector<char> hs;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (rc == UC_LP_OK) rc = read_device(hp, row_ptr, (size_t)m + 1, s);
+  if (rc == UC_LP_OK && nnz) rc = read_device(hc, col_idx, (size_t)nnz, s);
+  if (rc == UC_LP_OK && nnz) rc = read_device(hv, val, (size_t)nnz, s);
+  if (rc == UC_LP_OK) rc = read_device(hcst, c, (size_t)n, s);
+  if (rc == UC_LP_OK) rc = read_device(hb, b, (size_t)m, s);
+  if (rc == UC_LP_OK) rc = read_device(hs, sense, (size_t)m, s);
+  if (rc == UC_LP_OK) rc = read_device(hl, lb, (size_t)n, s);
+  if (rc == UC_LP_OK) rc = read_device(hu, ub, (size_t)n, s);
+  if (rc == UC_LP_OK) {
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(UC_LP_EHIP, "reading the device arrays: %s", hipGetErrorString(e));
+  }
+  (void)hipSetDevice(prev);
+  if (rc) return rc;
+  return uc_lp_create(eng, m, n, nnz, hp.data(), nnz ? hc.data() : nullptr, nnz ? hv.data() : nullptr, hcst.data(),
+                      hb.data(), hs.data(), hl.data(), hu.data(), opts, out);
+}
+
+extern "C" int uc_lp_get_solution_device(const uc_lp* lp, double* x, double* y, void* hip_stream) {
+  g_err.clear();
+  if (!lp) return fail(UC_LP_EINVAL, "NULL handle");
+  const int s = lp->status.load();
+  if (!(s == UC_LP_OPTIMAL || s == UC_LP_ITER_LIMIT || s == UC_LP_TIME_LIMIT || s == UC_LP_CANCELLED ||
+        s == UC_LP_NUMERICAL))
+    return fail(UC_LP_ESTATE, "no solution in status %d", s);
+  if (lp->sol_x.size() != (size_t)lp->P.n) return fail(UC_LP_ESTATE, "solution not available");
+  const int device = lp->eng->device;
+  int prev = 0;
+  HIPOK(hipGetDevice(&prev));
+  HIPOK(hipSetDevice(device));
+  int rc = UC_LP_OK;
+  if (x) rc = check_device_pointer(x, device, "x");
+  if (rc == UC_LP_OK && y) rc = check_device_pointer(y, device, "y");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (rc == UC_LP_OK && x) {
+    const hipError_t e = hipMemcpyAsync(x, lp->sol_x.data(), sizeof(double) * lp->P.n, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) rc = fail(UC_LP_EHIP, "copy of x: %s", hipGetErrorString(e));
+  }
+  if (rc == UC_LP_OK && y) {
+    const hipError_t e = hipMemcpyAsync(y, lp->sol_y.data(), sizeof(double) * lp->P.m, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) rc = fail(UC_LP_EHIP, "copy of y: %s", hipGetErrorString(e));
+  }
+  (void)hipSetDevice(prev);
+  return rc;
+}

@@ -67,7 +67,8 @@ class uc_lp_info(C.Structure):
         return d
 
 
-EXPORTS = ["uc_lp_opts_default", "uc_engine_create", "uc_engine_destroy", "uc_lp_create",
+EXPORTS = ["uc_lp_opts_default", "uc_engine_create", "uc_engine_destroy", "uc_lp_create", "uc_lp_create_device",
+           "uc_lp_get_solution_device",
            "uc_lp_update_data", "uc_lp_solve", "uc_lp_status", "uc_lp_wait", "uc_lp_cancel",
            "uc_lp_get_solution", "uc_lp_destroy", "uc_lp_last_error", "uc_lp_solve_scenarios",
            "uc_lp_internal_dims", "uc_lp_get_transpose", "uc_lp_get_scaling", "uc_lp_debug_step",
@@ -90,6 +91,9 @@ def _sig(lib):
     lib.uc_engine_destroy.restype = None
     lib.uc_lp_create.argtypes = [_P, C.c_int32, C.c_int32, C.c_int64, _I, _I, _D, _D, _D, C.c_char_p,
                                  _D, _D, C.POINTER(uc_lp_opts), C.POINTER(_P)]
+    lib.uc_lp_create_device.argtypes = [_P, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P,
+                                        C.POINTER(uc_lp_opts), _P, C.POINTER(_P)]
+    lib.uc_lp_get_solution_device.argtypes = [_P, _P, _P, _P]
     lib.uc_lp_update_data.argtypes = [_P, _D, _D, _D, _D]
     lib.uc_lp_solve.argtypes = [_P, _D, _D]
     lib.uc_lp_status.argtypes = [_P, C.POINTER(uc_lp_info)]
@@ -119,7 +123,8 @@ def _sig(lib):
     lib.uc_lp_bench_half_steps.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, _D, _D, _D, _D]
     lib.uc_spmv_merge_noalloc.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32,
                                           _P]
-    for name in ("uc_engine_create", "uc_lp_create", "uc_lp_update_data", "uc_lp_solve", "uc_lp_status",
+    for name in ("uc_engine_create", "uc_lp_create", "uc_lp_create_device", "uc_lp_get_solution_device",
+                 "uc_lp_update_data", "uc_lp_solve", "uc_lp_status",
                  "uc_lp_wait", "uc_lp_cancel", "uc_lp_get_solution", "uc_lp_solve_scenarios",
                  "uc_lp_internal_dims", "uc_lp_get_transpose", "uc_lp_get_scaling", "uc_lp_debug_step",
                  "uc_lp_debug_iterate", "uc_lp_eval_kkt", "uc_lp_debug_refine", "uc_spmv", "uc_spmv_bench", "uc_copy_bench",
@@ -218,6 +223,29 @@ def uc_lp_create(lp, opts: Optional[uc_lp_opts] = None, engine=None, raw: bool =
         return rc, (h if rc == UC_LP_OK else None)
     _check(rc)
     return h
+
+
+def uc_lp_create_device(m, n, nnz, row_ptr, col_idx, val, c, b, sense, lb, ub, opts: Optional[uc_lp_opts] = None,
+                        engine=None, stream=None, raw: bool = False):
+    """Device addresses (ints, e.g. tensor.data_ptr()) of caller-owned arrays
+    (int32 row_ptr/col_idx, float64 val/c/b/lb/ub, uint8 sense); stream: a
+    hipStream_t address or None.  raw=True returns (rc, handle or None)."""
+    h = _P()
+    rc = load().uc_lp_create_device(engine, int(m), int(n), int(nnz), _P(row_ptr), _P(col_idx) if col_idx else None,
+                                    _P(val) if val else None, _P(c), _P(b), _P(sense), _P(lb), _P(ub),
+                                    C.byref(opts) if opts is not None else None, _P(stream) if stream else None,
+                                    C.byref(h))
+    if raw:
+        return rc, (h if rc == UC_LP_OK else None)
+    _check(rc)
+    return h
+
+
+def uc_lp_get_solution_device(h, x_ptr, y_ptr, stream=None, raw: bool = False):
+    """Copy the solution into caller-owned device arrays (addresses as ints, or None)."""
+    rc = load().uc_lp_get_solution_device(h, _P(x_ptr) if x_ptr else None, _P(y_ptr) if y_ptr else None,
+                                          _P(stream) if stream else None)
+    return rc if raw else _check(rc)
 
 
 def uc_lp_update_data(h, c=None, b=None, lb=None, ub=None) -> None:
