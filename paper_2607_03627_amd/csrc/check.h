@@ -138,13 +138,13 @@ __host__ __device__ inline void check_step(ChkState& st, const ChkParams& p, con
         st.best_kkt = err;
         st.best_check = st.checks;
       } else if (p.fp32_stall_checks > 0 &&
-                 st.checks - st.best_check >= (inner ? 4 : 1) * (int64_t)p.fp32_stall_checks &&
+                 st.checks - st.best_check >= (inner ? 12 : 1) * (int64_t)p.fp32_stall_checks &&
                  (continuing || inner || st.best_kkt <= 10.0 * target)) {
         // a stall within a decade of the target (or of the gap past the
         // milestone) is taken for the FP32 floor.  A correction problem,
-        // which is O(1)-scaled and far from that floor, gets four times the
-        // window (restarted PDHG can take that long for 10% near 1e-8); when
-        // it stalls, it ends its round wherever it stands
+        // which is O(1)-scaled and far from that floor, gets twelve times
+        // the window (restarted PDHG can take that long for 10% near 1e-8);
+        // when it stalls, it ends its round wherever it stands
         promote = true;
       }
     }
