@@ -7,6 +7,8 @@ problem, using the device's own D_r, D_c.  Whole solves are compared with
 the oracle's optima (simplex, or the stored HiGHS values), and their KKT
 error is recomputed by the oracle's evaluator."""
 
+import time
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -180,8 +182,10 @@ def test_refinement_round_limit_and_cancel():
                                                       iter_limit=10**7))
     try:
         uclp.uc_lp_solve(h)
+        t0 = time.time()
         while uclp.uc_lp_status(h).refine_rounds < 2:
             assert uclp.uc_lp_status(h).status in (uclp.UC_LP_QUEUED, uclp.UC_LP_RUNNING)
+            assert time.time() - t0 < 120, "no second refinement round within 120 s"
             uclp.uc_lp_wait(h, 0.01)
         uclp.uc_lp_cancel(h)
         uclp.uc_lp_wait(h, 60)
