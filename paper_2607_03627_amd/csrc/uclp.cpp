@@ -3174,7 +3174,7 @@ extern "C" int uc_lp_create_device(uc_engine* eng, int32_t m, int32_t n, int64_t
   HIPOK(hipGetDevice(&prev));
   HIPOK(hipSetDevice(device));
   int rc = UC_LP_OK;
-  const void* ptrs[9] = {row_ptr, col_idx, val, c, b, sense, lb, ub, nullptr};
+  const void* ptrs[8] = {row_ptr, col_idx, val, c, b, sense, lb, ub};
   const char* names[8] = {"row_ptr", "col_idx", "val", "c", "b", "sense", "lb", "ub"};
   for (int i = 0; i < 8 && rc == UC_LP_OK; ++i)
     if (ptrs[i]) rc = check_device_pointer(ptrs[i], device, names[i]);
