@@ -327,6 +327,8 @@ int uc_lp_get_solution(const uc_lp* lp, double* x, double* y);
 /* uc_lp_get_solution into DEVICE buffers x[n], y[m] (double; either may be
  * NULL) of the instance's device, enqueued on hip_stream (NULL: the null
  * stream): the values are there when the stream reaches the copies.  The
+ * copies read the handle's host copy of the solution, so the handle is
+ * neither destroyed nor solved again until the stream has passed them.  The
  * caller owns the buffers.  ESTATE as uc_lp_get_solution; EINVAL for
  * pointers that are not device memory of that device. */
 int uc_lp_get_solution_device(const uc_lp* lp, double* x, double* y, void* hip_stream);
