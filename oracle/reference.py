@@ -19,9 +19,10 @@ import scipy.sparse as sp
 from scipy.optimize import linprog
 
 
-def highs_solve(lp, method: str = "highs-ipm", time_limit: float = None):
+def highs_solve(lp, method: str = "highs-ipm", time_limit: float = None, disp: bool = False):
     """Return (status, obj, x, y, seconds).  y uses the Lagrangian sign
-    convention of kkt.py (y >= 0 on 'G' rows)."""
+    convention of kkt.py (y >= 0 on 'G' rows).  disp: HiGHS prints its
+    progress log."""
     A = sp.csr_matrix((np.asarray(lp.val, float), np.asarray(lp.col_idx, np.int64),
                        np.asarray(lp.row_ptr, np.int64)), shape=(lp.m, lp.n))
     sense = np.asarray(lp.sense)
@@ -31,7 +32,7 @@ def highs_solve(lp, method: str = "highs-ipm", time_limit: float = None):
     ub_rows = np.concatenate([G, L])
     A_ub = sp.vstack([-A[G], A[L]]).tocsr()
     b_ub = np.concatenate([-np.asarray(lp.b)[G], np.asarray(lp.b)[L]])
-    opts = {"presolve": True}
+    opts = {"presolve": True, "disp": bool(disp)}
     if time_limit is not None:
         opts["time_limit"] = float(time_limit)
     t0 = time.perf_counter()

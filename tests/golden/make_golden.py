@@ -47,14 +47,14 @@ def save(d):
     os.replace(tmp, OUT)
 
 
-def record(d, key, lp, method):
+def record(d, key, lp, method, disp=False):
     t0 = time.perf_counter()
     if method == "simplex":
         r = simplex_solve(lp)
         assert r.status == "optimal", (key, r.status)
         obj, x, y = r.obj, r.x, r.y
     else:
-        st, obj, x, y, _ = highs_solve(lp, method)
+        st, obj, x, y, _ = highs_solve(lp, method, disp=disp)
         assert st == 0, (key, st)
     k = kkt(lp, x, y)
     d[key] = dict(obj=obj, method=method, rel_kkt=k.rel_kkt, m=lp.m, n=lp.n, nnz=lp.nnz,
@@ -69,6 +69,7 @@ def main():
     ap.add_argument("--only", default=None)
     ap.add_argument("--large-method", default="highs-ipm", choices=["highs-ipm", "highs-ds"],
                     help="HiGHS method for the 6,049-bus-shaped grids")
+    ap.add_argument("--log", action="store_true", help="HiGHS progress log on stdout")
     args = ap.parse_args()
     d = load()
     jobs = [(f"tiny/{s}", "tiny", s, "simplex") for s in range(10)]
@@ -80,7 +81,7 @@ def main():
             continue
         if key in d:
             continue
-        record(d, key, make_instance(shape, seed), method)
+        record(d, key, make_instance(shape, seed), method, args.log)
     # scenario variants of the 500-bus grid (shared matrix, perturbed c, b, ub)
     base = make_instance("medium", 0)
     for s in range(1, 5):
