@@ -184,6 +184,13 @@ typedef struct {
   int32_t refine_max_rounds; /* default 200 (a round is a restart of the inner
                             solve: the iteration limit is the real bound)    */
   int32_t reserved2;     /* must be 0                                         */
+  double pw_balance_refine; /* the residual-balance gain (as pw_balance) used
+                            inside the correction problems, in [0, 1],
+                            default 0.5                                       */
+  double refine_diverge; /* a correction problem whose relative KKT error
+                            rises above this times the best of its round
+                            ends the round at once (0: never; else > 1),
+                            default 0                                         */
 } uc_lp_opts;
 
 typedef struct {

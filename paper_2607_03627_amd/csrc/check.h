@@ -31,6 +31,9 @@ struct ChkParams {
   // > 0: denominator of the relative gap in place of 1 + |pobj| + |dobj|
   // (a correction problem measures its gap on the scale of the refined point)
   double gap_den;
+  // UC_LP_FP32_REFINE, correction problems: the balance gain, and the factor
+  // over the round's best error at which a round ends (0: never)
+  double pw_balance_inner, inner_diverge;
 };
 
 // State of one run between checks, and what the last check found.
@@ -137,6 +140,10 @@ __host__ __device__ inline void check_step(ChkState& st, const ChkParams& p, con
       if (st.best_check == 0 || err < 0.9 * st.best_kkt) {
         st.best_kkt = err;
         st.best_check = st.checks;
+      } else if (inner && p.inner_diverge > 0 && err > p.inner_diverge * st.best_kkt) {
+        // a correction problem moving away from the point it corrects
+        // (a primal weight run away): the round ends before it undoes more
+        promote = true;
       } else if (p.fp32_stall_checks > 0 &&
                  st.checks - st.best_check >= (inner ? 12 : 1) * (int64_t)p.fp32_stall_checks &&
                  (continuing || inner || st.best_kkt <= 10.0 * target)) {
@@ -177,8 +184,8 @@ __host__ __device__ inline void check_step(ChkState& st, const ChkParams& p, con
         st.pw_int += e;
         double lw = log(st.omega) - p.pw_smoothing * e - p.pw_integral * st.pw_int;
         // residual balance: a primal residual above the dual one raises w
-        if (p.pw_balance > 0 && st.rel_primal > 0 && st.rel_dual > 0)
-          lw += p.pw_balance * log(st.rel_primal / st.rel_dual);
+        const double gain = inner ? p.pw_balance_inner : p.pw_balance;
+        if (gain > 0 && st.rel_primal > 0 && st.rel_dual > 0) lw += gain * log(st.rel_primal / st.rel_dual);
         double w = exp(lw);
         if (p.pw_max_change >= 1) w = fmin(fmax(w, st.omega / p.pw_max_change), st.omega * p.pw_max_change);
         st.omega = w;

@@ -109,12 +109,16 @@ extern "C" void uc_lp_opts_default(uc_lp_opts* o) {
   o->refine_growth = 1e4;
   o->refine_max_rounds = 200;
   o->reserved2 = 0;
+  o->pw_balance_refine = 0.5;
+  o->refine_diverge = 0.0;
 }
 
 static int check_opts(const uc_lp_opts& o) {
   if (o.precision < 0 || o.precision > 3) return fail(UC_LP_ENOTSUP, "precision %d", o.precision);
   if (!(o.eps_refine > 0 && o.eps_refine < 1) || !(o.refine_growth > 1) || o.refine_max_rounds < 0 ||
-      o.refine_max_rounds > 1000 || o.reserved2 != 0)
+      o.refine_max_rounds > 1000 || o.reserved2 != 0 ||
+      !(o.pw_balance_refine >= 0 && o.pw_balance_refine <= 1) ||
+      !(o.refine_diverge == 0 || (o.refine_diverge > 1 && std::isfinite(o.refine_diverge))))
     return fail(UC_LP_EINVAL, "refinement parameters out of range");
   if (o.kkt_every < 1 || o.kkt_every > 1 << 20) return fail(UC_LP_EINVAL, "kkt_every %d", o.kkt_every);
   if (o.ruiz_iters < 0 || o.ruiz_iters > 1000) return fail(UC_LP_EINVAL, "ruiz_iters");
@@ -976,6 +980,8 @@ static ChkParams make_params(const uc_lp_opts& o, const HostProblem& P) {
   p.pw_max_change = o.pw_max_change;
   p.pw_integral = o.pw_integral;
   p.pw_balance = o.precision == UC_LP_FP32_MIXED_POLISH ? o.pw_balance_polish : o.pw_balance;
+  p.pw_balance_inner = o.pw_balance_refine;
+  p.inner_diverge = o.refine_diverge;
   p.norm_b = P.norm_b;
   p.norm_c = P.norm_c;
   p.obj_offset = P.obj_offset;

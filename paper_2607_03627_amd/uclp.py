@@ -42,7 +42,7 @@ class uc_lp_opts(C.Structure):
                 ("fp32_stall_checks", C.c_int32), ("reserved", C.c_int32), ("pw_integral", C.c_double),
                 ("pw_balance", C.c_double), ("pw_balance_polish", C.c_double), ("eps_gap_rel", C.c_double),
                 ("eps_refine", C.c_double), ("refine_growth", C.c_double), ("refine_max_rounds", C.c_int32),
-                ("reserved2", C.c_int32)]
+                ("reserved2", C.c_int32), ("pw_balance_refine", C.c_double), ("refine_diverge", C.c_double)]
 
 
 class uc_lp_info(C.Structure):

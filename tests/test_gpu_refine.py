@@ -169,6 +169,23 @@ def test_refined_solve_matches_oracle(shape, seed):
     assert np.all(x >= lp.lb) and np.all(x <= lp.ub)
 
 
+@pytest.mark.parametrize("shape,seed,opts", [("tiny", 1, dict(pw_balance_refine=0.0, refine_diverge=2.0)),
+                                             ("medium", 1, dict(pw_balance_refine=0.25, refine_diverge=4.0,
+                                                                    iter_limit=400000))])
+def test_refined_solve_with_round_options(shape, seed, opts):
+    # the balance gain inside the correction problems and the end of a round
+    # on a rising error change the rounds, not the point they converge to
+    lp = make_case(shape, seed)
+    z = oracle_objective(shape, seed, lp)
+    say("case refine options", shape, seed, opts)
+    x, y, info = refine_solve(lp, **opts)
+    say("  ", info["status_name"], "iters", info["iters"], "rounds", info["refine_rounds"], "kkt", info["rel_kkt"])
+    assert info["status"] == uclp.UC_LP_OPTIMAL, info
+    k = kkt(lp, x, y)
+    assert k.rel_kkt <= 1e-8 * 1.001
+    assert abs(k.pobj - z) <= 1e-6 * abs(z)
+
+
 def test_refinement_round_limit_and_cancel():
     lp = make_instance("medium", 1)
     # no round allowed: the first boundary ends the solve with the refined

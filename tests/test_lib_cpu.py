@@ -71,10 +71,11 @@ def test_binding_struct_layout_equals_the_c_layout(name):
 
 def test_binding_structs_match_header_layout():
     # the two structs are passed by pointer; their sizes must agree with the C layout
-    assert ctypes.sizeof(uclp.uc_lp_opts) == 4 * 4 + 8 + 5 * 8 + 4 * 4 + 6 * 8 + 2 * 4 + 4 * 8 + 2 * 8 + 2 * 4
+    assert ctypes.sizeof(uclp.uc_lp_opts) == 4 * 4 + 8 + 5 * 8 + 4 * 4 + 6 * 8 + 2 * 4 + 4 * 8 + 2 * 8 + 2 * 4 + 2 * 8
     o = uclp.uc_lp_opts_default()
     assert o.eps_gap_rel == 0.0
     assert o.eps_refine == 1e-2 and o.refine_growth == 1e4 and o.refine_max_rounds == 200 and o.reserved2 == 0
+    assert o.pw_balance_refine == 0.5 and o.refine_diverge == 0.0
     assert o.precision == uclp.UC_LP_FP32_MIXED_POLISH and o.kkt_every == 64
     assert o.iter_limit == 100000 and o.eps_rel == 1e-4 and o.eps_polish == 1e-8
     assert (o.restart_sufficient, o.restart_necessary, o.restart_artificial, o.pw_smoothing) == \
@@ -149,7 +150,8 @@ def test_bad_options_are_rejected():
                      (dict(pw_integral=2.0), uclp.UC_LP_EINVAL), (dict(pw_balance=-0.5), uclp.UC_LP_EINVAL),
                      (dict(eps_refine=0.0), uclp.UC_LP_EINVAL), (dict(eps_refine=1.0), uclp.UC_LP_EINVAL),
                      (dict(refine_growth=1.0), uclp.UC_LP_EINVAL), (dict(refine_max_rounds=-1), uclp.UC_LP_EINVAL),
-                     (dict(reserved2=3), uclp.UC_LP_EINVAL)):
+                     (dict(reserved2=3), uclp.UC_LP_EINVAL), (dict(pw_balance_refine=1.5), uclp.UC_LP_EINVAL),
+                     (dict(refine_diverge=0.5), uclp.UC_LP_EINVAL), (dict(refine_diverge=float("inf")), uclp.UC_LP_EINVAL)):
         rc, h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(**kw), raw=True)
         assert rc == code and h is None
 
