@@ -177,7 +177,8 @@ typedef struct {
      The solve is OPTIMAL once the relative KKT error of (x*, y*) on the
      original problem, evaluated in FP64, is <= eps_polish; ITER_LIMIT at
      iter_limit iterations over all rounds or after refine_max_rounds
-     rounds.  Refinement runs in the scaled space of the solve, and the
+     rounds.  A run that ends short of eps_polish returns the best refined
+     point of its round boundaries (a round can end worse than it began).  Refinement runs in the scaled space of the solve, and the
      primal weight carries over, times the change of D_D / D_P.           */
   double eps_refine;     /* error reduction asked of each round, 1e-2         */
   double refine_growth;  /* bound on the growth of D_P and D_D per round, 1e4 */

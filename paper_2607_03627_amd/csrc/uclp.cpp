@@ -636,6 +636,11 @@ struct RefineRun {
   double pobj = 0, dobj = 0, rel_primal = 0, rel_dual = 0, rel_gap = 0, rel_kkt = 0, abs_inf = 0;
   double rel_kkt_inner = 0;
   std::vector<int> t_flag, a_flag;  // tile flags while correction data are loaded
+  // the best refined point so far (its copy is in x_warm, y_warm, which the
+  // rounds leave unused): a run that ends short of its target returns it
+  // (a round can end worse than it began)
+  bool have_best = false;
+  double best[7] = {0, 0, 0, 0, 0, 0, 0};  // pobj, dobj, rel_primal, rel_dual, rel_gap, rel_kkt, abs_inf
 };
 
 struct uc_lp {
@@ -1172,6 +1177,23 @@ static void refine_outer(const double* q, const HostProblem& P, RefineRun& F) {
   F.have_outer = true;
 }
 
+// The KKT fields of the refined point to or from RefineRun::best.
+static void save_best(RefineRun& F) {
+  const double v[7] = {F.pobj, F.dobj, F.rel_primal, F.rel_dual, F.rel_gap, F.rel_kkt, F.abs_inf};
+  std::memcpy(F.best, v, sizeof v);
+  F.have_best = true;
+}
+
+static void load_best(RefineRun& F) {
+  F.pobj = F.best[0];
+  F.dobj = F.best[1];
+  F.rel_primal = F.best[2];
+  F.rel_dual = F.best[3];
+  F.rel_gap = F.best[4];
+  F.rel_kkt = F.best[5];
+  F.abs_inf = F.best[6];
+}
+
 // The original scaled data back in the arrays a correction problem used.
 static int restore_scaled_data(uc_lp* lp, hipStream_t s) {
   DevMem& D = lp->D;
@@ -1206,6 +1228,12 @@ static int refine_boundary(uc_lp* lp, hipStream_t s, bool fold, int stop) {
     HIPOK(hipMemcpyAsync(q, R.out, sizeof q, hipMemcpyDeviceToHost, s));
     HIPOK(hipStreamSynchronize(s));
     refine_outer(q, P, F);
+    if (!F.have_best || F.rel_kkt < F.best[5]) {
+      HIPOK(hipMemcpyAsync(lp->D.x_warm, lp->D.d.xhat, sizeof(double) * P.ni, hipMemcpyDeviceToDevice, s));
+      if (P.mi)
+        HIPOK(hipMemcpyAsync(lp->D.y_warm, lp->D.d.yhat, sizeof(double) * P.mi, hipMemcpyDeviceToDevice, s));
+      save_best(F);
+    }
     if (!c.eps_reached && F.rel_kkt <= o.eps_rel && (o.eps_abs_feas <= 0 || F.abs_inf <= o.eps_abs_feas)) {
       // the eps_rel milestone, reached by the refined point (host clock)
       c.eps_reached = 1;
@@ -1231,6 +1259,14 @@ static int refine_boundary(uc_lp* lp, hipStream_t s, bool fold, int stop) {
   if (status != 0) {
     c.status = status;
     c.promote = 0;
+    if (status != UC_LP_OPTIMAL && F.have_best && !(F.rel_kkt <= F.best[5])) {
+      // the run ends short of its target on a point worse than an earlier one
+      HIPOK(hipMemcpyAsync(lp->D.d.xhat, lp->D.x_warm, sizeof(double) * P.ni, hipMemcpyDeviceToDevice, s));
+      if (P.mi)
+        HIPOK(hipMemcpyAsync(lp->D.d.yhat, lp->D.y_warm, sizeof(double) * P.mi, hipMemcpyDeviceToDevice, s));
+      load_best(F);
+      if (o.verbose) fprintf(stderr, "[uclp] refine: returning the best refined point, kkt %.2e\n", F.rel_kkt);
+    }
     if (F.have_outer) c.prec = 0;  // the answer is (x*, y*)
     return restore_scaled_data(lp, s);
   }

@@ -186,6 +186,37 @@ def test_refined_solve_with_round_options(shape, seed, opts):
     assert abs(k.pobj - z) <= 1e-6 * abs(z)
 
 
+def test_run_short_of_its_target_returns_its_best_refined_point():
+    # On 6,049-bus seed 1 a late round ends worse than it began (the primal
+    # weight runs away inside it), and 100,000 iterations do not reach 1e-8:
+    # the point returned is never worse than a refined point the run has
+    # published at a round boundary, and the oracle's KKT error agrees.
+    lp = make_instance("large", 1)
+    say("case refine best point large 1", lp.m, lp.n)
+    h = uclp.uc_lp_create(lp, uclp.uc_lp_opts_default(precision=uclp.UC_LP_FP32_REFINE, iter_limit=100000))
+    seen = []
+    try:
+        uclp.uc_lp_solve(h)
+        t0 = time.time()
+        while True:
+            st = uclp.uc_lp_status(h)
+            if st.status not in (uclp.UC_LP_QUEUED, uclp.UC_LP_RUNNING):
+                break
+            if st.refine_rounds >= 1:
+                seen.append(st.rel_kkt)
+            assert time.time() - t0 < 120, "no end within 120 s"
+            uclp.uc_lp_wait(h, 0.005)
+        info = uclp.uc_lp_status(h).as_dict()
+        x, y = uclp.uc_lp_get_solution(h, lp.n, lp.m)
+    finally:
+        uclp.uc_lp_destroy(h)
+    say("  ", info["status_name"], "rounds", info["refine_rounds"], "kkt", info["rel_kkt"], "best seen", min(seen))
+    assert info["status"] == uclp.UC_LP_ITER_LIMIT and info["refine_rounds"] >= 2
+    assert seen and info["rel_kkt"] <= min(seen) * (1 + 1e-12)
+    k = kkt(lp, x, y)
+    assert abs(k.rel_kkt - info["rel_kkt"]) <= 1e-10
+
+
 def test_refinement_round_limit_and_cancel():
     lp = make_instance("medium", 1)
     # no round allowed: the first boundary ends the solve with the refined
