@@ -1228,7 +1228,7 @@ static int refine_boundary(uc_lp* lp, hipStream_t s, bool fold, int stop) {
     HIPOK(hipMemcpyAsync(q, R.out, sizeof q, hipMemcpyDeviceToHost, s));
     HIPOK(hipStreamSynchronize(s));
     refine_outer(q, P, F);
-    if (!F.have_best || F.rel_kkt < F.best[5]) {
+    if (std::isfinite(F.rel_kkt) && (!F.have_best || F.rel_kkt < F.best[5])) {
       HIPOK(hipMemcpyAsync(lp->D.x_warm, lp->D.d.xhat, sizeof(double) * P.ni, hipMemcpyDeviceToDevice, s));
       if (P.mi)
         HIPOK(hipMemcpyAsync(lp->D.y_warm, lp->D.d.yhat, sizeof(double) * P.mi, hipMemcpyDeviceToDevice, s));
