@@ -1005,10 +1005,105 @@ __device__ inline void stage_entries(const int* __restrict__ col, const T* __res
   }
 }
 
-template <typename T, bool CHECK>
+// W consecutive scenarios of one element as one access: W = 1, or the
+// lanes of a 16-byte vector (4 FP32 / 2 FP64 values) when the batch width
+// is a multiple of W, so that a thread moves 16 bytes per load and store.
+template <typename T, int W>
+__device__ __forceinline__ void ld_lanes(const UCLP_GLOBAL T* p, T (&o)[W]) {
+  if constexpr (W == 1) {
+    o[0] = p[0];
+  } else {
+    typedef T vt __attribute__((ext_vector_type(W)));
+    const vt a = *reinterpret_cast<const UCLP_GLOBAL vt*>(p);
+#pragma unroll
+    for (int w = 0; w < W; ++w) o[w] = a[w];
+  }
+}
+
+// Stores the lanes that are active (all of them with one vector store).
+template <typename T, int W>
+__device__ __forceinline__ void st_lanes(UCLP_GLOBAL T* p, const T (&v)[W], const bool (&act)[W], bool all) {
+  if constexpr (W == 1) {
+    if (act[0]) p[0] = v[0];
+  } else if (all) {
+    typedef T vt __attribute__((ext_vector_type(W)));
+    vt a;
+#pragma unroll
+    for (int w = 0; w < W; ++w) a[w] = v[w];
+    *reinterpret_cast<UCLP_GLOBAL vt*>(p) = a;
+  } else {
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+      if (act[w]) p[w] = v[w];
+  }
+}
+
+// row_dot_ms for the W lanes sc .. sc + W - 1: each lane's sum in entry order.
+template <typename T, int W>
+__device__ inline void row_dot_lanes(int a, int b, const int* lc, const T* lv, const UCLP_GLOBAL T* g, int ns,
+                                     int sc, T (&s)[W]) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) s[w] = 0;
+  if (b <= a) return;
+  T v[kMsDot], p[kMsDot][W];
+#pragma unroll
+  for (int t = 0; t < kMsDot; ++t) {
+    const int k = min(a + t, b - 1);
+    v[t] = lv[k];
+    ld_lanes<T, W>(g + (size_t)lc[k] * ns + sc, p[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < kMsDot; ++t)
+    if (a + t < b) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) s[w] += v[t] * p[t][w];
+    }
+  for (int k = a + kMsDot; k < b; ++k) {
+    T q[W];
+    ld_lanes<T, W>(g + (size_t)lc[k] * ns + sc, q);
+#pragma unroll
+    for (int w = 0; w < W; ++w) s[w] += lv[k] * q[w];
+  }
+}
+
+template <typename T, int W>
+__device__ inline void row_dot_lanes_global(int a, int b, const int* __restrict__ col, const T* __restrict__ val,
+                                            const UCLP_GLOBAL T* g, int ns, int sc, T (&s)[W]) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) s[w] = 0;
+  for (int k = a; k < b; ++k) {
+    T q[W];
+    ld_lanes<T, W>(g + (size_t)col[k] * ns + sc, q);
+#pragma unroll
+    for (int w = 0; w < W; ++w) s[w] += val[k] * q[w];
+  }
+}
+
+// The lanes a thread serves (sc .. sc + W - 1) and which of them run;
+// false when none does.
+template <int W>
+__device__ __forceinline__ bool lanes_of(const SlotDev& S, int sc, bool (&act)[W], bool& all) {
+  bool any = false;
+  all = true;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    act[w] = S.active[sc + w] != 0;
+    any = any || act[w];
+    all = all && act[w];
+  }
+  return any;
+}
+
+// Batched primal half-step: the row block's entries are staged in LDS once;
+// kLanes / W threads serve one row, thread sc / W its lanes sc .. sc + W - 1,
+// each lane computing what k_primal computes for one instance.
+template <typename T, bool CHECK, int W>
 __global__ __launch_bounds__(kThreads) void k_primal_ms(const SlotDev* __restrict__ slots,
                                                         const Tile* __restrict__ tiles, int ntiles,
                                                         int jiter) {
+  constexpr int G = kLanes / W;                    // threads per row
+  constexpr int R = kThreads / G;                  // rows per pass
+  constexpr int U = kMsUnroll / W > 0 ? kMsUnroll / W : 1;  // rows per thread in flight
   __shared__ int lc[kNnzTile];
   __shared__ T lv[kNnzTile];
   const int t = xcd_tile(ntiles);
@@ -1024,70 +1119,95 @@ __global__ __launch_bounds__(kThreads) void k_primal_ms(const SlotDev* __restric
   if (staged) stage_entries<T>(S.t_col + k0, V.tv + k0, nz, lc, lv);
   __syncthreads();
   const int ns = S.nscen;
-  const int sc = threadIdx.x % kLanes;
-  if (sc >= ns || !S.active[sc]) return;
+  const int sc = (threadIdx.x % G) * W;
+  if (sc >= ns) return;
+  bool act[W], all;
+  if (!lanes_of<W>(S, sc, act, all)) return;
   const int fl = tl.flags;
-  const T tau = (T)S.tau[sc];
-  const double kk = (double)(S.k0[sc] + jiter);
-  const T w = (T)((kk + 1.0) / (kk + 2.0));
-  const T wa = (T)(1.0 / (kk + 2.0));
   // full reflection: x is rebuilt from xbar and x0 as in k_primal
   const bool full = S.gamma == 1.0;
   const bool rebuild = full && jiter > 0;
-  T wp = 0, wap = 0;
-  if (rebuild) {
-    const double kp = (double)(S.k0[sc] + jiter - 1);
-    wp = (T)((kp + 1.0) / (kp + 2.0));
-    wap = (T)(1.0 / (kp + 2.0));
+  T tau[W], w[W], wa[W], wp[W], wap[W];
+#pragma unroll
+  for (int v = 0; v < W; ++v) {
+    tau[v] = (T)S.tau[sc + v];
+    const double kk = (double)(S.k0[sc + v] + jiter);
+    w[v] = (T)((kk + 1.0) / (kk + 2.0));
+    wa[v] = (T)(1.0 / (kk + 2.0));
+    wp[v] = 0;
+    wap[v] = 0;
+    if (rebuild) {
+      const double kp = (double)(S.k0[sc + v] + jiter - 1);
+      wp[v] = (T)((kp + 1.0) / (kp + 2.0));
+      wap[v] = (T)(1.0 / (kp + 2.0));
+    }
   }
   const UCLP_GLOBAL T* y = gld(V.y);
-  // kMsUnroll rows per thread at a time: their vector loads and gathers are
-  // all issued before the first epilogue
-  for (int jb = r0 + threadIdx.x / kLanes; jb < r1; jb += kMsUnroll * kRowsPerPass) {
-    T acc[kMsUnroll], x[kMsUnroll], c[kMsUnroll], l[kMsUnroll], u[kMsUnroll], xa[kMsUnroll];
+  // U rows per thread at a time: their vector loads and gathers are all
+  // issued before the first epilogue
+  for (int jb = r0 + threadIdx.x / G; jb < r1; jb += U * R) {
+    T acc[U][W], x[U][W], c[U][W], l[U][W], u[U][W], xa[U][W];
 #pragma unroll
-    for (int q = 0; q < kMsUnroll; ++q) {
+    for (int q = 0; q < U; ++q) {
       // straight-line loads: rows past the block's end load its last row
-      const int j = min(jb + q * kRowsPerPass, r1 - 1);
+      const int j = min(jb + q * R, r1 - 1);
       const size_t e = (size_t)j * ns + sc;
-      c[q] = (fl & kColC0) ? (T)0 : gld(V.c)[e];
-      u[q] = (fl & kColUInf) ? (T)INFINITY : gld(V.u)[e];
-      l[q] = (fl & (kColL0 | kColLInf | kColLNegU)) ? (T)0 : gld(V.l)[e];
-      xa[q] = 0;
-      if (rebuild) {
-        xa[q] = gld(V.x0)[e];
-        x[q] = gld(V.xbar)[e];
-      } else {
-        x[q] = gld(V.x)[e];
-        if (!CHECK) xa[q] = gld(V.x0)[e];
+#pragma unroll
+      for (int v = 0; v < W; ++v) {
+        c[q][v] = 0;
+        u[q][v] = (T)INFINITY;
+        l[q][v] = 0;
+        xa[q][v] = 0;
       }
-      acc[q] = staged ? row_dot_ms<T>(ptr[j] - k0, ptr[j + 1] - k0, lc, lv, y, ns, sc)
-                      : row_dot_ms_global<T>(ptr[j], ptr[j + 1], S.t_col, V.tv, y, ns, sc);
+      if (!(fl & kColC0)) ld_lanes<T, W>(gld(V.c) + e, c[q]);
+      if (!(fl & kColUInf)) ld_lanes<T, W>(gld(V.u) + e, u[q]);
+      if (!(fl & (kColL0 | kColLInf | kColLNegU))) ld_lanes<T, W>(gld(V.l) + e, l[q]);
+      if (rebuild) {
+        ld_lanes<T, W>(gld(V.x0) + e, xa[q]);
+        ld_lanes<T, W>(gld(V.xbar) + e, x[q]);
+      } else {
+        ld_lanes<T, W>(gld(V.x) + e, x[q]);
+        if (!CHECK) ld_lanes<T, W>(gld(V.x0) + e, xa[q]);
+      }
+      if (staged) row_dot_lanes<T, W>(ptr[j] - k0, ptr[j + 1] - k0, lc, lv, y, ns, sc, acc[q]);
+      else row_dot_lanes_global<T, W>(ptr[j], ptr[j + 1], S.t_col, V.tv, y, ns, sc, acc[q]);
     }
 #pragma unroll
-    for (int q = 0; q < kMsUnroll; ++q) {
-      const int j = jb + q * kRowsPerPass;
+    for (int q = 0; q < U; ++q) {
+      const int j = jb + q * R;
       if (j >= r1) break;
       const size_t e = (size_t)j * ns + sc;
-      const T xq = rebuild ? wp * x[q] + wap * xa[q] : x[q];
-      const T lq = (fl & kColL0) ? (T)0 : (fl & kColLInf) ? -(T)INFINITY : (fl & kColLNegU) ? -u[q] : l[q];
-      const T xh = clampv<T>(xq - tau * (c[q] - acc[q]), lq, u[q]);
-      const T xb = (T)2 * xh - xq;
-      gst(V.xbar)[e] = xb;
+      T xq[W], xb[W], xh[W], xn[W];
+#pragma unroll
+      for (int v = 0; v < W; ++v) {
+        xq[v] = rebuild ? wp[v] * x[q][v] + wap[v] * xa[q][v] : x[q][v];
+        const T lq = (fl & kColL0)     ? (T)0
+                     : (fl & kColLInf)  ? -(T)INFINITY
+                     : (fl & kColLNegU) ? -u[q][v]
+                                        : l[q][v];
+        xh[v] = clampv<T>(xq[v] - tau[v] * (c[q][v] - acc[q][v]), lq, u[q][v]);
+        xb[v] = (T)2 * xh[v] - xq[v];
+        xn[v] = w[v] * ((T)(1.0 + S.gamma) * xh[v] - (T)S.gamma * xq[v]) + wa[v] * xa[q][v];
+      }
+      st_lanes<T, W>(gst(V.xbar) + e, xb, act, all);
       if (CHECK) {
-        gst(V.xhat)[e] = xh;
-        if (rebuild) gst(V.x)[e] = xq;
+        st_lanes<T, W>(gst(V.xhat) + e, xh, act, all);
+        if (rebuild) st_lanes<T, W>(gst(V.x) + e, xq, act, all);
       } else if (!full) {
-        gst(V.x)[e] = w * ((T)(1.0 + S.gamma) * xh - (T)S.gamma * xq) + wa * xa[q];
+        st_lanes<T, W>(gst(V.x) + e, xn, act, all);
       }
     }
   }
 }
 
-template <typename T, bool CHECK>
+// Batched dual half-step, lanes as in k_primal_ms.
+template <typename T, bool CHECK, int W>
 __global__ __launch_bounds__(kThreads) void k_dual_ms(const SlotDev* __restrict__ slots,
                                                       const Tile* __restrict__ tiles, int ntiles,
                                                       int jiter) {
+  constexpr int G = kLanes / W;
+  constexpr int R = kThreads / G;
+  constexpr int U = kMsUnroll / W > 0 ? kMsUnroll / W : 1;
   __shared__ int lc[kNnzTile];
   __shared__ T lv[kNnzTile];
   const int t = xcd_tile(ntiles);
@@ -1103,36 +1223,52 @@ __global__ __launch_bounds__(kThreads) void k_dual_ms(const SlotDev* __restrict_
   if (staged) stage_entries<T>(S.a_col + k0, V.av + k0, nz, lc, lv);
   __syncthreads();
   const int ns = S.nscen;
-  const int sc = threadIdx.x % kLanes;
-  if (sc >= ns || !S.active[sc]) return;
+  const int sc = (threadIdx.x % G) * W;
+  if (sc >= ns) return;
+  bool act[W], all;
+  if (!lanes_of<W>(S, sc, act, all)) return;
   const bool b0 = (tl.flags & kRowB0) != 0;
-  const T sigma = (T)S.sigma[sc];
-  const double kk = (double)(S.k0[sc] + jiter);
-  const T w = (T)((kk + 1.0) / (kk + 2.0));
-  const T wa = (T)(1.0 / (kk + 2.0));
+  T sigma[W], w[W], wa[W];
+#pragma unroll
+  for (int v = 0; v < W; ++v) {
+    sigma[v] = (T)S.sigma[sc + v];
+    const double kk = (double)(S.k0[sc + v] + jiter);
+    w[v] = (T)((kk + 1.0) / (kk + 2.0));
+    wa[v] = (T)(1.0 / (kk + 2.0));
+  }
   const T g1 = (T)(1.0 + S.gamma), g = (T)S.gamma;
   const UCLP_GLOBAL T* xbv = gld(V.xbar);
-  for (int ib = r0 + threadIdx.x / kLanes; ib < r1; ib += kMsUnroll * kRowsPerPass) {
-    T acc[kMsUnroll], y[kMsUnroll], bi[kMsUnroll], ya[kMsUnroll];
+  for (int ib = r0 + threadIdx.x / G; ib < r1; ib += U * R) {
+    T acc[U][W], y[U][W], bi[U][W], ya[U][W];
 #pragma unroll
-    for (int q = 0; q < kMsUnroll; ++q) {
-      const int i = min(ib + q * kRowsPerPass, r1 - 1);
+    for (int q = 0; q < U; ++q) {
+      const int i = min(ib + q * R, r1 - 1);
       const size_t e = (size_t)i * ns + sc;
-      bi[q] = b0 ? (T)0 : gld(V.b)[e];
-      y[q] = gld(V.y)[e];
-      ya[q] = CHECK ? (T)0 : gld(V.y0)[e];
-      acc[q] = staged ? row_dot_ms<T>(ptr[i] - k0, ptr[i + 1] - k0, lc, lv, xbv, ns, sc)
-                      : row_dot_ms_global<T>(ptr[i], ptr[i + 1], S.a_col, V.av, xbv, ns, sc);
+#pragma unroll
+      for (int v = 0; v < W; ++v) {
+        bi[q][v] = 0;
+        ya[q][v] = 0;
+      }
+      if (!b0) ld_lanes<T, W>(gld(V.b) + e, bi[q]);
+      ld_lanes<T, W>(gld(V.y) + e, y[q]);
+      if (!CHECK) ld_lanes<T, W>(gld(V.y0) + e, ya[q]);
+      if (staged) row_dot_lanes<T, W>(ptr[i] - k0, ptr[i + 1] - k0, lc, lv, xbv, ns, sc, acc[q]);
+      else row_dot_lanes_global<T, W>(ptr[i], ptr[i + 1], S.a_col, V.av, xbv, ns, sc, acc[q]);
     }
 #pragma unroll
-    for (int q = 0; q < kMsUnroll; ++q) {
-      const int i = ib + q * kRowsPerPass;
+    for (int q = 0; q < U; ++q) {
+      const int i = ib + q * R;
       if (i >= r1) break;
       const size_t e = (size_t)i * ns + sc;
-      T yh = y[q] + sigma * (bi[q] - acc[q]);
-      if (i >= S.m_eq) yh = yh > (T)0 ? yh : (T)0;
-      if (CHECK) gst(V.yhat)[e] = yh;
-      else gst(V.y)[e] = w * (g1 * yh - g * y[q]) + wa * ya[q];
+      T yh[W], yn[W];
+#pragma unroll
+      for (int v = 0; v < W; ++v) {
+        yh[v] = y[q][v] + sigma[v] * (bi[q][v] - acc[q][v]);
+        if (i >= S.m_eq) yh[v] = yh[v] > (T)0 ? yh[v] : (T)0;
+        yn[v] = w[v] * (g1 * yh[v] - g * y[q][v]) + wa[v] * ya[q][v];
+      }
+      if (CHECK) st_lanes<T, W>(gst(V.yhat) + e, yh, act, all);
+      else st_lanes<T, W>(gst(V.y) + e, yn, act, all);
     }
   }
 }
@@ -2153,29 +2289,49 @@ void launch_copy_kernel(const float4* a, float4* b, int64_t n4, hipStream_t s) {
 
 // ---- scenario-batch launchers -------------------------------------------------
 
-void launch_primal_ms(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles, int jiter,
-                      hipStream_t s) {
+void launch_primal_ms(int prec, bool check, bool vec, const SlotDev* slots, const Tile* tiles, int ntiles,
+                      int jiter, hipStream_t s) {
   if (ntiles <= 0) return;
   const dim3 g(xcd_grid(ntiles));
   if (prec == 1) {
-    if (check) k_primal_ms<float, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
-    else k_primal_ms<float, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    if (vec) {
+      if (check) k_primal_ms<float, true, 4><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+      else k_primal_ms<float, false, 4><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    } else {
+      if (check) k_primal_ms<float, true, 1><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+      else k_primal_ms<float, false, 1><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    }
   } else {
-    if (check) k_primal_ms<double, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
-    else k_primal_ms<double, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    if (vec) {
+      if (check) k_primal_ms<double, true, 2><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+      else k_primal_ms<double, false, 2><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    } else {
+      if (check) k_primal_ms<double, true, 1><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+      else k_primal_ms<double, false, 1><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    }
   }
 }
 
-void launch_dual_ms(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles, int jiter,
-                    hipStream_t s) {
+void launch_dual_ms(int prec, bool check, bool vec, const SlotDev* slots, const Tile* tiles, int ntiles,
+                    int jiter, hipStream_t s) {
   if (ntiles <= 0) return;
   const dim3 g(xcd_grid(ntiles));
   if (prec == 1) {
-    if (check) k_dual_ms<float, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
-    else k_dual_ms<float, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    if (vec) {
+      if (check) k_dual_ms<float, true, 4><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+      else k_dual_ms<float, false, 4><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    } else {
+      if (check) k_dual_ms<float, true, 1><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+      else k_dual_ms<float, false, 1><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    }
   } else {
-    if (check) k_dual_ms<double, true><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
-    else k_dual_ms<double, false><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    if (vec) {
+      if (check) k_dual_ms<double, true, 2><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+      else k_dual_ms<double, false, 2><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    } else {
+      if (check) k_dual_ms<double, true, 1><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+      else k_dual_ms<double, false, 1><<<g, kThreads, 0, s>>>(slots, tiles, ntiles, jiter);
+    }
   }
 }
 

@@ -2721,6 +2721,22 @@ static void carve_scen(ScenArena& A, const HostProblem& P, int S) {
   A.tiles = a.take<Tile>(P.a_blk.size() + P.t_blk.size());
 }
 
+// The batched half-steps can serve 16 bytes of consecutive scenarios per
+// access (4 FP32 or 2 FP64 lanes) when the batch width is a multiple of that
+// and every vector they touch starts on a 16-byte boundary.
+template <typename T>
+static bool vecs_aligned16(const Vecs<T>& V) {
+  const void* p[11] = {V.x, V.x0, V.xbar, V.xhat, V.y, V.y0, V.yhat, V.c, V.l, V.u, V.b};
+  for (const void* q : p)
+    if (((uintptr_t)q & 15) != 0) return false;
+  return true;
+}
+
+static bool ms_vector_lanes(const SlotDev& S, int prec, int lanes) {
+  if (prec == 1) return lanes % 4 == 0 && vecs_aligned16(S.f);
+  return lanes % 2 == 0 && vecs_aligned16(S.d);
+}
+
 extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* c, const double* b,
                                      const double* lb, const double* ub, const double* x0, const double* y0,
                                      double* x, double* y, uc_lp_info* info) {
@@ -3071,10 +3087,11 @@ extern "C" int uc_lp_solve_scenarios(uc_lp* base, int32_t n_scen, const double* 
       SD.active[L] = done[s] ? 0 : 1;
     }
     SCEN_HIP(hipMemcpyAsync(A.slot_dev, &SD, sizeof SD, hipMemcpyHostToDevice, st));
+    const bool vec = ms_vector_lanes(SD, phase, SL);
     for (int j = 0; j < K; ++j) {
       const bool check = j == K - 1;
-      launch_primal_ms(phase, check, A.slot_dev, TT, nt, j, st);
-      launch_dual_ms(phase, check, A.slot_dev, TA, na, j, st);
+      launch_primal_ms(phase, check, vec, A.slot_dev, TT, nt, j, st);
+      launch_dual_ms(phase, check, vec, A.slot_dev, TA, na, j, st);
     }
     launch_kkt_ms(phase, A.slot_dev, TT, nt, TA, na, A.red2, st);
     SCEN_HIP(hipMemcpyAsync(q.data(), A.scal, (size_t)kScal * SL * 8, hipMemcpyDeviceToHost, st));

@@ -160,10 +160,13 @@ void launch_engine_check(SlotDev* slots, ChkState* chk, const ChkParams* prm, in
 void launch_stamp(unsigned long long* t, hipStream_t s);
 
 // scenario batches (nscen <= kMaxScen interleaved scenarios in slot 0)
-void launch_primal_ms(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles, int jiter,
-                      hipStream_t s);
-void launch_dual_ms(int prec, bool check, const SlotDev* slots, const Tile* tiles, int ntiles, int jiter,
-                    hipStream_t s);
+// vec: the batch width is a multiple of the lanes of a 16-byte vector (4 FP32
+// or 2 FP64 values) and every vector is 16-byte aligned; a thread then serves
+// that many consecutive scenarios with one access per element
+void launch_primal_ms(int prec, bool check, bool vec, const SlotDev* slots, const Tile* tiles, int ntiles,
+                      int jiter, hipStream_t s);
+void launch_dual_ms(int prec, bool check, bool vec, const SlotDev* slots, const Tile* tiles, int ntiles,
+                    int jiter, hipStream_t s);
 // KKT partials and their reduction into slots[0].scal[s * kScal + q]
 void launch_kkt_ms(int prec, const SlotDev* slots, const Tile* ttiles, int nttiles, const Tile* atiles,
                    int natiles, double* red2, hipStream_t s);
