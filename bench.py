@@ -104,6 +104,14 @@ def _cpu_baseline_child(workload, seed, time_limit_s, q, kw=None):
     q.put(("done", int(st), wall, (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)))
 
 
+def host_threads() -> int:
+    """CPU threads this process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(lp, workload, seed, time_limit_s=25.0, hard_limit_s=60.0, kw=None):
     """The oracle (HiGHS interior point through oracle/reference.py) on the
     workload itself, in a child process: the measured time if it finishes,
@@ -112,8 +120,6 @@ def cpu_baseline(lp, workload, seed, time_limit_s=25.0, hard_limit_s=60.0, kw=No
     kw: extra arguments of make_instance for the workload."""
     import multiprocessing as mp
     import queue as _queue
-
-    from oracle.reference import host_threads
 
     ctx = mp.get_context("spawn")
     q = ctx.Queue()
@@ -332,7 +338,6 @@ def size_sweep_leg(time_limit_s=45.0):
     GPU stop paying off?  Each LP is solved by the library (FP32 to 1e-4, and
     FP32 + FP64 polish to 1e-8) and by HiGHS interior point with crossover on
     the host cores (stopped at a time limit)."""
-    from oracle.reference import host_threads
     from paper_2607_03627_amd import uclp
     from paper_2607_03627_amd.instances import make_instance
 
