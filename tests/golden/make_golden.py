@@ -1,7 +1,7 @@
 """Write tests/golden/objectives.json: optimal objectives of the seeded
 synthetic instances, computed by the CPU oracle only.
 
-    python tests/golden/make_golden.py [--large]
+    python tests/golden/make_golden.py [--large [--large-method highs-ds]] [--only KEY] [--log]
 
 Tiny grids (30 buses, 24 periods) use the oracle's bounded simplex; the
 500-bus grids and the 6,049-bus-shaped grids, beyond the simplex's reach, use
