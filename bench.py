@@ -489,8 +489,8 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "shape": args.workload, "seed": args.seed,
                    "rows": lp.m, "cols": lp.n, "nnz": lp.nnz, "precision": "FP32 iterates, FP64 KKT/restart/gap",
                    "eps_rel": 1e-4, "eps_gap_rel": opts.eps_gap_rel, "kkt_every": 64,
-                   "value_is": "solve start -> first check at rel. KKT <= 1e-4 (library clock); the solve "
-                               "continues to close the FP64 gap, see extra.wall_s_returned",
+                   "value_is": "solve start -> first check at rel. KKT <= 1e-4 (library clock), where the "
+                               "solve ends; extra.wall_s_returned is the host wall time to the returned point",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_primal<float> (A^T SpMV + projection + Halpern)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
